@@ -1,0 +1,9 @@
+"""FP64 CPU oracle of the dense pyramidal Lucas-Kanade flow (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import this
+package.  It shares no code with the HIP path.
+"""
+from .lk import (  # noqa: F401
+    TAU, bilinear, blur5, box_sum, flow, gradients, lk_iteration, pyr_reduce, pyramid,
+    solve, upsample_flow, warp,
+)
