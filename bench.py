@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Frame pairs/s of dense pyramidal Lucas-Kanade flow at 1024x1024 on one MI355X.
+
+Workload (one step = one frame pair through the whole method): synthetic 1024x1024 uint8
+particle images (0.03 particles/px, sigma 1.2 px, shear layer 4 + 4 tanh((y - 512)/40) px plus
+a reverse Lamb-Oseen vortex), 4 pyramid levels, window radius 8, 4 iterations per level,
+FP32 storage, one of_compute call per pair on one stream.  Inputs rotate over 16 distinct
+pairs already resident in HBM.  Also reported: the FP16-storage form of the same workload,
+per-pair latency percentiles, the live per-kernel event timing of the fused iteration kernel
+against MI355X HBM peak, and the FP64 CPU oracle timed on this host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "frame pairs/s at 1024² (FP32 vs FP16-stored, % HBM peak); p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "c2"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _gen(i):
+    import synth
+    I1, I2, _, _ = synth.make_pair(WORKLOAD, i)
+    return I1, I2
+
+
+def _oracle_pair(args):
+    os.environ["OMP_NUM_THREADS"] = "1"
+    import oracle
+    I1, I2, L, r, K = args
+    t = time.perf_counter()
+    oracle.flow(I1, I2, L, r, K)
+    return time.perf_counter() - t
+
+
+def cpu_baseline(pairs, L, r, K, n_pairs, workers):
+    """The FP64 oracle on `n_pairs` pairs over a pool of `workers` processes (no GPU touched)."""
+    jobs = [(pairs[i % len(pairs)][0], pairs[i % len(pairs)][1], L, r, K) for i in range(n_pairs)]
+    t = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        per = list(ex.map(_oracle_pair, jobs))
+    wall = time.perf_counter() - t
+    return {"value": n_pairs / wall, "unit": "frame pairs/s", "cores": workers, "kind": "oracle",
+            "sample": f"{n_pairs} distinct 1024x1024 pairs of the bench workload, FP64 numpy oracle, "
+                      f"one pair per worker process ({workers} processes, 1 thread each); "
+                      f"mean single-pair time {sum(per) / len(per):.2f} s",
+            "cpu_seconds": round(sum(per), 2)}
+
+
+def time_plan(torch, plan, d1, d2, us, vs, steps, warmup):
+    n = len(d1)
+    for i in range(warmup):
+        plan.compute(d1[i % n], d2[i % n], us[i % n], vs[i % n])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(steps):
+        plan.compute(d1[i % n], d2[i % n], us[i % n], vs[i % n])
+    torch.cuda.synchronize()
+    return time.perf_counter() - t
+
+
+def latency(torch, plan, d1, d2, us, vs, n_calls):
+    """Host-observed per-pair latency: enqueue one pair, wait for it, repeat."""
+    n = len(d1)
+    out = []
+    for i in range(n_calls):
+        t = time.perf_counter()
+        plan.compute(d1[i % n], d2[i % n], us[i % n], vs[i % n])
+        torch.cuda.current_stream().synchronize()
+        out.append((time.perf_counter() - t) * 1e3)
+    out.sort()
+    return {"p50_ms": round(out[len(out) // 2], 4), "p99_ms": round(out[min(len(out) - 1, int(0.99 * len(out)))], 4)}
+
+
+def kernel_timing(torch, ofmi, plan, d1, d2, us, vs, steps):
+    """Average duration of each kernel from hipEvents recorded around its launches."""
+    n = len(d1)
+    plan.set_timing(True)
+    for i in range(steps):
+        plan.compute(d1[i % n], d2[i % n], us[i % n], vs[i % n])
+    torch.cuda.synchronize()
+    it = plan.read_timing(ofmi.OF_KERNEL_ITERATE)
+    rd = plan.read_timing(ofmi.OF_KERNEL_REDUCE)
+    plan.set_timing(False)
+    return it, rd
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--pairs", type=int, default=16, help="distinct resident pairs rotated over")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--cpu-pairs", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); pairs are "
+              "independent, so a multi-GPU run would deal pairs to GPUs with no exchange", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import synth
+    wl = synth.workload(WORKLOAD)
+    L, r, K = wl.levels, wl.radius, wl.iters
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    t = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=min(workers, args.pairs)) as ex:
+        pairs = list(ex.map(_gen, range(args.pairs)))
+    log(f"generated {len(pairs)} pairs in {time.perf_counter() - t:.1f} s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        n_cpu = min(args.cpu_pairs, workers)
+        cpu = cpu_baseline(pairs, L, r, K, args.cpu_pairs, n_cpu)
+        log(f"cpu baseline: {cpu['value']:.3f} pairs/s on {cpu['cores']} processes")
+
+    import torch
+    import paper_1306_2461_amd as ofmi
+    ofmi.load()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    d1 = [torch.from_numpy(p[0]).to(dev) for p in pairs]
+    d2 = [torch.from_numpy(p[1]).to(dev) for p in pairs]
+    us = [torch.empty((wl.H, wl.W), dtype=torch.float32, device=dev) for _ in pairs]
+    vs = [torch.empty((wl.H, wl.W), dtype=torch.float32, device=dev) for _ in pairs]
+    torch.cuda.synchronize()
+
+    results = {}
+    for tag, fp16 in (("fp32", False), ("fp16", True)):
+        plan = ofmi.Plan(wl.H, wl.W, L, r, K, fp16=fp16, device=dev)
+        el = time_plan(torch, plan, d1, d2, us, vs, args.steps, args.warmup)
+        lat = latency(torch, plan, d1, d2, us, vs, min(200, args.steps))
+        it, rd = kernel_timing(torch, ofmi, plan, d1, d2, us, vs, min(100, args.steps))
+        err = None
+        if not args.no_parity:
+            import oracle
+            plan.compute(d1[0], d2[0], us[0], vs[0])
+            torch.cuda.synchronize()
+            ou, ov = oracle.flow(pairs[0][0], pairs[0][1], L, r, K)
+            err = float(max(np.abs(us[0].cpu().numpy() - ou).max(), np.abs(vs[0].cpu().numpy() - ov).max()))
+        results[tag] = {"el": el, "lat": lat, "it": it, "rd": rd, "err": err}
+        plan.close()
+        log(f"{tag}: {args.steps / el:.1f} pairs/s, {el / args.steps * 1e3:.4f} ms/pair, "
+            f"latency {lat}, iterate kernel avg {it[0] / max(it[1], 1) * 1e3:.2f} us over {it[1]} launches, "
+            f"max |err| {err}")
+
+    r32 = results["fp32"]
+    ms_it, n_it, units_it, bytes_it = r32["it"]
+    achieved = bytes_it / ms_it / 1e6 if ms_it > 0 else 0.0
+    line = {
+        "metric": METRIC,
+        "value": round(args.steps / r32["el"], 3),
+        "unit": "frame pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["el"] / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1024x1024 uint8 particle-image pair, 4 levels, radius 8, 4 iterations/level, "
+                               "FP32 plain per-pair path (one of_compute per pair, one stream)",
+                   "H": wl.H, "W": wl.W, "levels": L, "radius": r, "iters": K,
+                   "distinct_pairs": args.pairs},
+        "latency_ms": r32["lat"],
+        "max_abs_err_px": r32["err"],
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "lk_iter (fused iteration)", "launches": n_it,
+                     "avg_launch_us": round(ms_it / max(n_it, 1) * 1e3, 3),
+                     "bytes_per_launch": round(bytes_it / max(n_it, 1))},
+        "fp16": {"value": round(args.steps / results["fp16"]["el"], 3),
+                 "ms_per_step": round(results["fp16"]["el"] / args.steps * 1e3, 5),
+                 "latency_ms": results["fp16"]["lat"], "max_abs_err_px": results["fp16"]["err"],
+                 "iterate_avg_launch_us": round(results["fp16"]["it"][0] / max(results["fp16"]["it"][1], 1) * 1e3, 3)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

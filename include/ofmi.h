@@ -1,0 +1,140 @@
+/*
+ * ofmi.h -- C ABI of the MI355X dense pyramidal Lucas-Kanade velocimetry library.
+ *
+ * The library computes, for two frames of a particle-image sequence, a dense displacement
+ * field with one vector per pixel (Gautier & Aider, Sec. 2.4): an image pyramid built by
+ * reducing each frame by a factor of 4 in area per level, a zero initial displacement at the
+ * coarsest level, a fixed number of Gauss-Newton iterations per level minimising a sum of
+ * squared differences over an interrogation window of radius r, each level's result seeding
+ * the next finer level.  The level count n_lev counts full resolution (eq. 1); n_iter is the
+ * number of iterations per level (Sec. 2.4, Table 1).
+ *
+ * Operators fixed where the paper is silent (identical on every entry point):
+ *   pyramid  separable 5-tap binomial [1 4 6 4 1]/16 (rows first, then columns),
+ *            clamp-to-edge, keep even rows/columns, level sizes ceil(H/2) x ceil(W/2);
+ *   seed     u <- 2 * bilinear(u_coarse, x/2, y/2) on the finer grid (same for v);
+ *   warp     W2(x,y) = bilinear(I2, x+u, y+v), sample coordinates clamped into the image;
+ *   gradient central differences of W2 with clamped neighbours;
+ *   window   unweighted (2r+1)^2 box, truncated at the image border;
+ *   step     each window pixel m is linearised around its own estimate u(m); with
+ *            It = W2 - I1 - Ix u - Iy v and A,B,C,sx,sy the window sums of
+ *            Ix^2, IxIy, Iy^2, Ix It, Iy It, the new estimate is u(x) + e where
+ *            H e = -(sx + A u + B v, sy + B u + C v), H = [[A,B],[B,C]]: Cramer's rule when
+ *            AC - B^2 > 1e-5 (A+C)^2, rank-1 pseudo-inverse H/(A+C)^2 when A+C > 0, else e = 0.
+ *   iterations are Jacobi (each iteration reads the previous iteration's whole field).
+ *
+ * Conventions for every entry point:
+ *   - Planes are row-major and dense: element (x, y) of an H x W plane is at index y*W + x
+ *     (x = column, y = row).  u is the displacement along x, v along y, in level-0 pixels,
+ *     from frame 1 to frame 2: I2(x + u, y + v) ~ I1(x, y).
+ *   - Every plane pointer is a HIP device pointer on the device that was current when the
+ *     object was created.  Frames are uint8 (or float32 with OF_FLAG_INPUT_F32) and are only
+ *     read; u and v are float32 and are written.  The caller owns frames and outputs and keeps
+ *     them alive until the work enqueued on `stream` has completed.  The library never frees
+ *     caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Compute calls
+ *     only enqueue work on it and never synchronise the host.
+ *   - Objects (plan, batch, session) are not re-entrant: calls on one object must be ordered
+ *     on one stream.  Distinct objects are independent.  *_destroy synchronises the device
+ *     before freeing.
+ *   - Errors: create functions return NULL and compute functions return a non-zero of_status;
+ *     nothing is enqueued on an argument error.  of_last_error() gives the text of the last
+ *     failure on the calling thread.  Device faults surface at the caller's next
+ *     synchronisation.
+ */
+#ifndef OFMI_H
+#define OFMI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OF_API __attribute__((visibility("default")))
+
+typedef enum {
+  OF_OK = 0,
+  OF_EINVAL = 1,   /* invalid argument; nothing enqueued */
+  OF_ENOMEM = 2,   /* workspace too small or allocation failure */
+  OF_EHIP = 3,     /* a HIP runtime call or kernel launch failed */
+  OF_ESTATE = 4    /* object used in a state that does not allow the call */
+} of_status;
+
+/* Flags of the *_ex constructors. */
+#define OF_FLAG_FP16_STORAGE (1u << 0) /* pyramid levels >= 1 stored in FP16; all math FP32 */
+#define OF_FLAG_INPUT_F32    (1u << 1) /* frames are float32 instead of uint8 */
+
+#define OF_MAX_LEVELS 12
+#define OF_MAX_RADIUS 12
+#define OF_MAX_ITERS 1000
+
+typedef struct of_plan of_plan;
+
+/* Workspace bytes a plan needs (pyramids of both frames + flow ping-pong), 0 on invalid
+ * parameters.  Parameters as of_plan_create_ex. */
+OF_API size_t of_plan_workspace_bytes(int H, int W, int levels, int radius, int iters,
+                                      unsigned flags);
+
+/* Plan for one frame size: H x W frames, `levels` pyramid levels including full resolution
+ * (1 <= levels <= min(OF_MAX_LEVELS, 1 + floor(log2(min(H, W))))), window radius
+ * 0 <= radius <= OF_MAX_RADIUS, 0 <= iters <= OF_MAX_ITERS iterations per level (Sec. 2.4,
+ * eq. 1).  uint8 frames, FP32 storage.  The plan allocates its own workspace.
+ * Returns NULL on invalid parameters or allocation failure. */
+OF_API of_plan* of_plan_create(int H, int W, int levels, int radius, int iters);
+
+/* As of_plan_create with `flags` (OF_FLAG_*).  If `workspace` is non-NULL it must be a device
+ * buffer of at least of_plan_workspace_bytes(...) bytes, 256-byte aligned, owned by the caller
+ * and kept alive until of_plan_destroy; if NULL the plan allocates it. */
+OF_API of_plan* of_plan_create_ex(int H, int W, int levels, int radius, int iters,
+                                  unsigned flags, void* workspace, size_t workspace_bytes);
+
+/* Dense flow from frame I1 to frame I2 (both H x W, uint8 or float32 per the plan's flags)
+ * into u and v (H x W float32, 4-byte aligned, u != v).  Enqueues the pyramid build and the
+ * levels x iters iterations on `stream`.  iters = 0 writes zeros.
+ * Errors: OF_EINVAL on a NULL plan or pointer or u == v (nothing enqueued); OF_EHIP if a
+ * launch fails. */
+OF_API of_status of_compute(of_plan* plan, const void* I1, const void* I2, float* u, float* v,
+                            void* stream);
+
+/* Releases the plan and the workspace it allocated.  NULL-safe. */
+OF_API void of_plan_destroy(of_plan* plan);
+
+/* Text of the last failure on the calling thread ("" if none). */
+OF_API const char* of_last_error(void);
+
+/* --------------------------------------------------------------------- kernel timing
+ * Per-kernel timing for measurement: while enabled, every kernel launch of the plan is
+ * bracketed by a pair of hipEvents recorded on the launch stream.  of_plan_read_timing
+ * waits for the recorded events, returns the totals since the last read and resets them.
+ *   kernel: OF_KERNEL_ITERATE (the fused iteration) or OF_KERNEL_REDUCE (pyramid step).
+ *   total_ms: summed event-to-event time; launches: number of launches; units: pixel-
+ *   iterations (ITERATE) or output pixels (REDUCE); bytes: algorithmic HBM bytes of those
+ *   launches (ITERATE: per pixel-iteration 2 frame elements + 16 bytes of u,v read and
+ *   written; REDUCE: input plane + output plane per frame).  Any out pointer may be NULL.
+ * Errors: OF_EINVAL on a NULL plan or unknown kernel; OF_EHIP if event creation fails. */
+#define OF_KERNEL_ITERATE 0
+#define OF_KERNEL_REDUCE 1
+OF_API of_status of_plan_set_timing(of_plan* plan, int enable);
+OF_API of_status of_plan_read_timing(of_plan* plan, int kernel, double* total_ms,
+                                     long long* launches, double* units, double* bytes);
+
+/* --------------------------------------------------------------------- stage entry points
+ * One step of the method on caller buffers, for stage-by-stage checking.
+ *   OF_STAGE_REDUCE:  one pyramid reduction (Sec. 2.4, factor 4 in area): in[0] is a level-`level`
+ *     plane of the plan's frame 1 geometry (uint8 / float32 at level 0, per flags; float32 or
+ *     FP16 above), out[0] receives the level-(level+1) plane (float32, or FP16 with
+ *     OF_FLAG_FP16_STORAGE).
+ *   OF_STAGE_ITERATE: one Gauss-Newton iteration at level `level`: in = {I1_l, I2_l, u, v},
+ *     out = {u_new, v_new}; frames typed as for that level, fields float32 of the level size.
+ * Errors: OF_EINVAL on a bad stage, level or NULL pointer. */
+#define OF_STAGE_REDUCE 0
+#define OF_STAGE_ITERATE 1
+OF_API of_status of_debug_stage(of_plan* plan, int stage, int level, const void* const* in,
+                                void* const* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OFMI_H */

@@ -1,0 +1,61 @@
+// Pyramid reduction: separable binomial [1 4 6 4 1]/16 blur (rows first, then columns),
+// clamp-to-edge, keep even rows and columns (factor 4 in area per level, Sec. 2.4).
+#include "kernels.h"
+
+namespace ofmi {
+
+namespace {
+
+constexpr float kB0 = 1.f / 16.f, kB1 = 4.f / 16.f, kB2 = 6.f / 16.f;
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void reduce_kernel(const Tin* __restrict__ in1,
+                                                      const Tin* __restrict__ in2, int H, int W,
+                                                      Tout* __restrict__ out1,
+                                                      Tout* __restrict__ out2, int Ho, int Wo) {
+  const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= Ho || j >= Wo) return;
+  const Tin* in = blockIdx.z ? in2 : in1;
+  Tout* out = blockIdx.z ? out2 : out1;
+  const float k[5] = {kB0, kB1, kB2, kB1, kB0};
+  int rows[5];
+#pragma unroll
+  for (int a = 0; a < 5; ++a) rows[a] = min(max(2 * i + a - 2, 0), H - 1) * W;
+  float acc = 0.f;
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    const int xx = min(max(2 * j + b - 2, 0), W - 1);
+    float col = 0.f;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) col = fmaf(k[a], ld(in, rows[a] + xx), col);
+    acc = fmaf(k[b], col, acc);
+  }
+  st(out, i * Wo + j, acc);
+}
+
+template <typename Tin, typename Tout>
+hipError_t go(const void* in1, const void* in2, int H, int W, void* out1, void* out2, int Ho,
+              int Wo, hipStream_t s) {
+  dim3 grid((Wo + 63) / 64, (Ho + 3) / 4, in2 ? 2 : 1);
+  hipLaunchKernelGGL((reduce_kernel<Tin, Tout>), grid, dim3(256), 0, s, (const Tin*)in1,
+                     (const Tin*)in2, H, W, (Tout*)out1, (Tout*)out2, Ho, Wo);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_reduce(Elem tin, Elem tout, const void* in1, const void* in2, int H, int W,
+                         void* out1, void* out2, int Ho, int Wo, hipStream_t s) {
+  if (tout == Elem::F32) {
+    if (tin == Elem::U8) return go<uint8_t, float>(in1, in2, H, W, out1, out2, Ho, Wo, s);
+    if (tin == Elem::F32) return go<float, float>(in1, in2, H, W, out1, out2, Ho, Wo, s);
+  } else if (tout == Elem::F16) {
+    if (tin == Elem::U8) return go<uint8_t, __half>(in1, in2, H, W, out1, out2, Ho, Wo, s);
+    if (tin == Elem::F32) return go<float, __half>(in1, in2, H, W, out1, out2, Ho, Wo, s);
+    if (tin == Elem::F16) return go<__half, __half>(in1, in2, H, W, out1, out2, Ho, Wo, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ofmi

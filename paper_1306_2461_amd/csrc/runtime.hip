@@ -1,0 +1,347 @@
+// Host runtime behind the C ABI: plan validation, workspace layout and the level x iteration
+// schedule of the pyramidal method (Sec. 2.4: coarsest level first from a zero field, each
+// level seeding the next finer one).
+#include <stdint.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/ofmi.h"
+#include "kernels.h"
+#include "runtime.h"
+
+namespace ofmi {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string& s) { g_last_error = s; }
+
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool check_params(int H, int W, int levels, int radius, int iters, unsigned flags) {
+  if (H < 1 || W < 1) return set_error("H and W must be >= 1"), false;
+  if ((long long)H * W > (1ll << 31) - 1) return set_error("H * W must fit in int32"), false;
+  if (levels < 1 || levels > OF_MAX_LEVELS) return set_error("levels out of range"), false;
+  int m = H < W ? H : W, maxl = 1;
+  while (m >= 2) { m >>= 1; ++maxl; }
+  if (levels > maxl) return set_error("levels > 1 + floor(log2(min(H, W)))"), false;
+  if (radius < 0 || radius > OF_MAX_RADIUS) return set_error("radius out of range"), false;
+  if (iters < 0 || iters > OF_MAX_ITERS) return set_error("iters out of range"), false;
+  if (flags & ~(OF_FLAG_FP16_STORAGE | OF_FLAG_INPUT_F32)) return set_error("unknown flags"), false;
+  return true;
+}
+
+Geometry make_geometry(int H, int W, int levels, int radius, int iters, unsigned flags) {
+  Geometry g{};
+  g.L = levels;
+  g.R = radius;
+  g.K = iters;
+  g.flags = flags;
+  g.H[0] = H;
+  g.W[0] = W;
+  for (int l = 1; l < levels; ++l) {
+    g.H[l] = (g.H[l - 1] + 1) / 2;
+    g.W[l] = (g.W[l - 1] + 1) / 2;
+  }
+  g.e0 = (flags & OF_FLAG_INPUT_F32) ? Elem::F32 : Elem::U8;
+  g.ep = (flags & OF_FLAG_FP16_STORAGE) ? Elem::F16 : Elem::F32;
+  size_t off = 0;
+  for (int l = 1; l < levels; ++l) {
+    const size_t b = align256((size_t)g.H[l] * g.W[l] * elem_bytes(g.ep));
+    g.off_p1[l] = off;
+    off += b;
+    g.off_p2[l] = off;
+    off += b;
+  }
+  const size_t fb = align256((size_t)H * W * sizeof(float));
+  for (int i = 0; i < 4; ++i) {
+    g.off_flow[i] = off;
+    off += fb;
+  }
+  g.bytes = off;
+  return g;
+}
+
+Elem Geometry::elem(int l) const { return l == 0 ? e0 : ep; }
+
+hipError_t KernelTimer::begin(hipStream_t s, hipEvent_t* a) {
+  *a = nullptr;
+  if (!on) return hipSuccess;
+  if (pool.empty()) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    pool.push_back(e);
+  }
+  *a = pool.back();
+  pool.pop_back();
+  return hipEventRecord(*a, s);
+}
+
+hipError_t KernelTimer::end(hipStream_t s, hipEvent_t a, int kernel, double units, double bytes) {
+  if (!on || !a) return hipSuccess;
+  hipEvent_t b;
+  if (pool.empty()) {
+    hipError_t r = hipEventCreate(&b);
+    if (r != hipSuccess) return r;
+  } else {
+    b = pool.back();
+    pool.pop_back();
+  }
+  recs.push_back({kernel, a, b, units, bytes});
+  return hipEventRecord(b, s);
+}
+
+hipError_t KernelTimer::read(int kernel, double* ms, long long* n, double* units, double* bytes) {
+  double tms = 0, tu = 0, tb = 0;
+  long long cnt = 0;
+  std::vector<Rec> keep;
+  for (const Rec& r : recs) {
+    if (r.kernel != kernel) {
+      keep.push_back(r);
+      continue;
+    }
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e != hipSuccess) return e;
+    float f = 0.f;
+    e = hipEventElapsedTime(&f, r.a, r.b);
+    if (e != hipSuccess) return e;
+    tms += f;
+    tu += r.units;
+    tb += r.bytes;
+    ++cnt;
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  recs.swap(keep);
+  if (ms) *ms = tms;
+  if (n) *n = cnt;
+  if (units) *units = tu;
+  if (bytes) *bytes = tb;
+  return hipSuccess;
+}
+
+KernelTimer::~KernelTimer() {
+  for (const Rec& r : recs) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : pool) hipEventDestroy(e);
+}
+
+// Enqueue the whole method for one pair: pyramid then levels x iterations.
+hipError_t enqueue_pair(const Geometry& g, char* ws, const void* I1, const void* I2, float* u,
+                        float* v, hipStream_t s, KernelTimer* t) {
+  const size_t n0 = (size_t)g.H[0] * g.W[0];
+  if (g.K == 0) return launch_zero(u, v, n0, s);
+  const void* P1[OF_MAX_LEVELS];
+  const void* P2[OF_MAX_LEVELS];
+  P1[0] = I1;
+  P2[0] = I2;
+  for (int l = 1; l < g.L; ++l) {
+    P1[l] = ws + g.off_p1[l];
+    P2[l] = ws + g.off_p2[l];
+    hipEvent_t ev;
+    hipError_t e = t ? t->begin(s, &ev) : hipSuccess;
+    if (e == hipSuccess)
+      e = launch_reduce(g.elem(l - 1), g.ep, P1[l - 1], P2[l - 1], g.H[l - 1], g.W[l - 1],
+                        (void*)P1[l], (void*)P2[l], g.H[l], g.W[l], s);
+    if (e == hipSuccess && t) {
+      const double no = (double)g.H[l] * g.W[l];
+      const double ni = (double)g.H[l - 1] * g.W[l - 1];
+      e = t->end(s, ev, OF_KERNEL_REDUCE, 2 * no,
+                 2 * (ni * elem_bytes(g.elem(l - 1)) + no * elem_bytes(g.ep)));
+    }
+    if (e != hipSuccess) return e;
+  }
+  float* fu[2] = {(float*)(ws + g.off_flow[0]), (float*)(ws + g.off_flow[1])};
+  float* fv[2] = {(float*)(ws + g.off_flow[2]), (float*)(ws + g.off_flow[3])};
+  const float* cu = nullptr;
+  const float* cv = nullptr;
+  int cH = 0, cW = 0, buf = 0;
+  for (int l = g.L - 1; l >= 0; --l) {
+    for (int k = 0; k < g.K; ++k) {
+      IterArgs a{};
+      a.I1 = P1[l];
+      a.I2 = P2[l];
+      a.H = g.H[l];
+      a.W = g.W[l];
+      a.uin = cu;
+      a.vin = cv;
+      a.Hc = cH;
+      a.Wc = cW;
+      a.mode = k > 0 ? kFlowSame : (l == g.L - 1 ? kFlowZero : kFlowCoarse);
+      const bool last = (l == 0 && k == g.K - 1);
+      a.uout = last ? u : fu[buf];
+      a.vout = last ? v : fv[buf];
+      hipEvent_t ev;
+      hipError_t e = t ? t->begin(s, &ev) : hipSuccess;
+      if (e == hipSuccess) e = launch_iter(g.elem(l), a, g.R, s);
+      if (e == hipSuccess && t) {
+        const double n = (double)a.H * a.W;
+        e = t->end(s, ev, OF_KERNEL_ITERATE, n, n * (2.0 * elem_bytes(g.elem(l)) + 16.0));
+      }
+      if (e != hipSuccess) return e;
+      cu = a.uout;
+      cv = a.vout;
+      cH = a.H;
+      cW = a.W;
+      buf ^= 1;
+    }
+  }
+  return hipSuccess;
+}
+
+}  // namespace ofmi
+
+using namespace ofmi;
+
+struct of_plan {
+  Geometry g;
+  char* ws;
+  bool owns_ws;
+  int device;
+  KernelTimer timer;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) hipSetDevice(prev);
+  }
+};
+
+of_status hip_fail(const char* what, hipError_t e) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return OF_EHIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t of_plan_workspace_bytes(int H, int W, int levels, int radius, int iters, unsigned flags) {
+  if (!check_params(H, W, levels, radius, iters, flags)) return 0;
+  return make_geometry(H, W, levels, radius, iters, flags).bytes;
+}
+
+of_plan* of_plan_create_ex(int H, int W, int levels, int radius, int iters, unsigned flags,
+                           void* workspace, size_t workspace_bytes) {
+  if (!check_params(H, W, levels, radius, iters, flags)) return nullptr;
+  Geometry g = make_geometry(H, W, levels, radius, iters, flags);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    hip_fail("hipGetDevice", e);
+    return nullptr;
+  }
+  char* ws = (char*)workspace;
+  bool owns = false;
+  if (ws) {
+    if (workspace_bytes < g.bytes) {
+      set_error("workspace smaller than of_plan_workspace_bytes()");
+      return nullptr;
+    }
+    if ((uintptr_t)ws & 255) {
+      set_error("workspace must be 256-byte aligned");
+      return nullptr;
+    }
+  } else {
+    e = hipMalloc((void**)&ws, g.bytes);
+    if (e != hipSuccess) {
+      hip_fail("hipMalloc(workspace)", e);
+      return nullptr;
+    }
+    owns = true;
+  }
+  of_plan* p = new of_plan{g, ws, owns, dev, {}};
+  return p;
+}
+
+of_plan* of_plan_create(int H, int W, int levels, int radius, int iters) {
+  return of_plan_create_ex(H, W, levels, radius, iters, 0u, nullptr, 0);
+}
+
+of_status of_compute(of_plan* p, const void* I1, const void* I2, float* u, float* v,
+                     void* stream) {
+  if (!p) return set_error("NULL plan"), OF_EINVAL;
+  if (!I1 || !I2 || !u || !v) return set_error("NULL frame or output pointer"), OF_EINVAL;
+  if (u == v) return set_error("u and v must be distinct planes"), OF_EINVAL;
+  if (((uintptr_t)u | (uintptr_t)v) & 3) return set_error("u, v must be 4-byte aligned"), OF_EINVAL;
+  if ((p->g.flags & OF_FLAG_INPUT_F32) && (((uintptr_t)I1 | (uintptr_t)I2) & 3))
+    return set_error("float32 frames must be 4-byte aligned"), OF_EINVAL;
+  DeviceGuard guard(p->device);
+  hipError_t e = enqueue_pair(p->g, p->ws, I1, I2, u, v, (hipStream_t)stream, &p->timer);
+  if (e != hipSuccess) return hip_fail("kernel launch", e);
+  return OF_OK;
+}
+
+void of_plan_destroy(of_plan* p) {
+  if (!p) return;
+  DeviceGuard guard(p->device);
+  hipDeviceSynchronize();
+  if (p->owns_ws) hipFree(p->ws);
+  delete p;
+}
+
+const char* of_last_error(void) { return g_last_error.c_str(); }
+
+of_status of_plan_set_timing(of_plan* p, int enable) {
+  if (!p) return set_error("NULL plan"), OF_EINVAL;
+  p->timer.on = enable != 0;
+  return OF_OK;
+}
+
+of_status of_plan_read_timing(of_plan* p, int kernel, double* total_ms, long long* launches,
+                              double* units, double* bytes) {
+  if (!p) return set_error("NULL plan"), OF_EINVAL;
+  if (kernel != OF_KERNEL_ITERATE && kernel != OF_KERNEL_REDUCE)
+    return set_error("unknown kernel id"), OF_EINVAL;
+  DeviceGuard guard(p->device);
+  hipError_t e = p->timer.read(kernel, total_ms, launches, units, bytes);
+  if (e != hipSuccess) return hip_fail("timing events", e);
+  return OF_OK;
+}
+
+of_status of_debug_stage(of_plan* p, int stage, int level, const void* const* in,
+                         void* const* out, void* stream) {
+  if (!p || !in || !out) return set_error("NULL argument"), OF_EINVAL;
+  const Geometry& g = p->g;
+  DeviceGuard guard(p->device);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (stage == OF_STAGE_REDUCE) {
+    if (level < 0 || level >= g.L - 1) return set_error("reduce level out of range"), OF_EINVAL;
+    if (!in[0] || !out[0]) return set_error("NULL plane"), OF_EINVAL;
+    e = launch_reduce(g.elem(level), g.ep, in[0], nullptr, g.H[level], g.W[level], out[0],
+                      nullptr, g.H[level + 1], g.W[level + 1], s);
+  } else if (stage == OF_STAGE_ITERATE) {
+    if (level < 0 || level >= g.L) return set_error("level out of range"), OF_EINVAL;
+    for (int i = 0; i < 4; ++i)
+      if (!in[i]) return set_error("NULL input plane"), OF_EINVAL;
+    if (!out[0] || !out[1] || out[0] == out[1]) return set_error("bad output planes"), OF_EINVAL;
+    IterArgs a{};
+    a.I1 = in[0];
+    a.I2 = in[1];
+    a.uin = (const float*)in[2];
+    a.vin = (const float*)in[3];
+    a.uout = (float*)out[0];
+    a.vout = (float*)out[1];
+    a.H = g.H[level];
+    a.W = g.W[level];
+    a.mode = kFlowSame;
+    e = launch_iter(g.elem(level), a, g.R, s);
+  } else {
+    return set_error("unknown stage"), OF_EINVAL;
+  }
+  if (e != hipSuccess) return hip_fail("kernel launch", e);
+  return OF_OK;
+}
+
+}  // extern "C"
