@@ -14,7 +14,8 @@ OBJ = os.path.join(PKG, "_build")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libofmi.so")
 
-SOURCES = ["pyramid.hip", "lk_iter.hip", "runtime.hip"]
+SOURCES = ["pyramid.hip", "lk_iter.hip", "lk_iter_u8.hip", "lk_iter_f32.hip", "lk_iter_f16.hip",
+           "runtime.hip"]
 
 # Packed FP32 arithmetic is disabled for every HIP translation unit.
 HIPFLAGS = [

@@ -26,12 +26,24 @@ struct IterArgs {
   int mode;            // FlowMode
 };
 
-__device__ __forceinline__ float ld(const uint8_t* p, int i) { return (float)p[i]; }
-__device__ __forceinline__ float ld(const float* p, int i) { return p[i]; }
-__device__ __forceinline__ float ld(const __half* p, int i) { return __half2float(p[i]); }
+// Element access by an unsigned 32-bit element index whose byte offset is formed in 32 bits
+// (planes are below 4 GiB): with the base pointer in scalar registers this selects the
+// scalar-base + 32-bit vector-offset global addressing form.
+template <typename T>
+__device__ __forceinline__ const T& at(const T* p, unsigned i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + i * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ T& at(T* p, unsigned i) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + i * (unsigned)sizeof(T));
+}
 
-__device__ __forceinline__ void st(float* p, int i, float x) { p[i] = x; }
-__device__ __forceinline__ void st(__half* p, int i, float x) { p[i] = __float2half_rn(x); }
+__device__ __forceinline__ float ld(const uint8_t* p, unsigned i) { return (float)at(p, i); }
+__device__ __forceinline__ float ld(const float* p, unsigned i) { return at(p, i); }
+__device__ __forceinline__ float ld(const __half* p, unsigned i) { return __half2float(at(p, i)); }
+
+__device__ __forceinline__ void st(float* p, unsigned i, float x) { at(p, i) = x; }
+__device__ __forceinline__ void st(__half* p, unsigned i, float x) { at(p, i) = __float2half_rn(x); }
 
 // Integer base and fraction of the sample coordinate x + d along one axis of length n,
 // clamped into [0, n-1].  Splitting d = floor(d) + frac keeps the coordinate exact in FP32
@@ -53,37 +65,50 @@ __device__ __forceinline__ float warp_sample(const T* __restrict__ I, int H, int
   float a, b;
   const int xi = split_coord(x, u, W, a);
   const int yi = split_coord(y, v, H, b);
-  const int x1 = min(xi + 1, W - 1);
-  const int y1 = min(yi + 1, H - 1);
-  const float z00 = ld(I, yi * W + xi), z01 = ld(I, yi * W + x1);
-  const float z10 = ld(I, y1 * W + xi), z11 = ld(I, y1 * W + x1);
+  const unsigned dx = xi < W - 1 ? 1u : 0u;
+  const unsigned dy = yi < H - 1 ? (unsigned)W : 0u;
+  const unsigned o00 = (unsigned)yi * (unsigned)W + (unsigned)xi;
+  const float z00 = ld(I, o00), z01 = ld(I, o00 + dx);
+  const float z10 = ld(I, o00 + dy), z11 = ld(I, o00 + dy + dx);
   const float t = fmaf(a, z01 - z00, z00);
   const float s = fmaf(a, z11 - z10, z10);
   return fmaf(b, s - t, t);
 }
 
 // Field value at in-image pixel (x, y) of the current level for the iteration's source.
+// The source mode is a compile-time parameter so every kernel reads its field straight-line.
+template <int MODE>
 __device__ __forceinline__ void read_flow(const IterArgs& a, int x, int y, float& u, float& v) {
-  if (a.mode == kFlowSame) {
-    const int i = y * a.W + x;
-    u = a.uin[i];
-    v = a.vin[i];
-  } else if (a.mode == kFlowCoarse) {
+  if constexpr (MODE == kFlowSame) {
+    const unsigned i = (unsigned)y * (unsigned)a.W + (unsigned)x;
+    u = at(a.uin, i);
+    v = at(a.vin, i);
+  } else if constexpr (MODE == kFlowCoarse) {
     // 2 * bilinear(coarse, x/2, y/2): base floor(x/2), fraction 0 or 1/2.
     const int x0 = x >> 1, y0 = y >> 1;
-    const int x1 = min(x0 + 1, a.Wc - 1), y1 = min(y0 + 1, a.Hc - 1);
+    const unsigned dx = x0 < a.Wc - 1 ? 1u : 0u;
+    const unsigned dy = y0 < a.Hc - 1 ? (unsigned)a.Wc : 0u;
     const float fa = (x & 1) ? 0.5f : 0.f, fb = (y & 1) ? 0.5f : 0.f;
-    const int i00 = y0 * a.Wc + x0, i01 = y0 * a.Wc + x1, i10 = y1 * a.Wc + x0, i11 = y1 * a.Wc + x1;
-    float t = fmaf(fa, a.uin[i01] - a.uin[i00], a.uin[i00]);
-    float s = fmaf(fa, a.uin[i11] - a.uin[i10], a.uin[i10]);
+    const unsigned i00 = (unsigned)y0 * (unsigned)a.Wc + (unsigned)x0;
+    const unsigned i01 = i00 + dx, i10 = i00 + dy, i11 = i00 + dy + dx;
+    const float u00 = at(a.uin, i00), u01 = at(a.uin, i01), u10 = at(a.uin, i10), u11 = at(a.uin, i11);
+    const float v00 = at(a.vin, i00), v01 = at(a.vin, i01), v10 = at(a.vin, i10), v11 = at(a.vin, i11);
+    float t = fmaf(fa, u01 - u00, u00);
+    float s = fmaf(fa, u11 - u10, u10);
     u = 2.f * fmaf(fb, s - t, t);
-    t = fmaf(fa, a.vin[i01] - a.vin[i00], a.vin[i00]);
-    s = fmaf(fa, a.vin[i11] - a.vin[i10], a.vin[i10]);
+    t = fmaf(fa, v01 - v00, v00);
+    s = fmaf(fa, v11 - v10, v10);
     v = 2.f * fmaf(fb, s - t, t);
   } else {
     u = 0.f;
     v = 0.f;
   }
+}
+
+// 1/x from the hardware reciprocal (1 ulp) refined by one Newton-Raphson step.
+__device__ __forceinline__ float recip(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 
 // New estimate at a pixel from its window sums and its current estimate (u, v).
@@ -97,12 +122,13 @@ __device__ __forceinline__ void solve_update(float A, float B, float C, float sx
   const float e = fmaf(-B, B, w);
   const float D = fmaf(A, C, -w) + e;
   float du = 0.f, dv = 0.f;
+  // D > tau T^2 > 0 keeps the reciprocals finite.
   if (D > kTau * (T * T)) {
-    const float inv = 1.0f / D;
+    const float inv = recip(D);
     du = -(fmaf(C, bx, -B * by)) * inv;
     dv = -(fmaf(A, by, -B * bx)) * inv;
   } else if (T > 0.f) {
-    const float inv = 1.0f / (T * T);
+    const float inv = recip(T * T);
     du = -(fmaf(A, bx, B * by)) * inv;
     dv = -(fmaf(B, bx, C * by)) * inv;
   }

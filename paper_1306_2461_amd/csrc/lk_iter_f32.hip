@@ -1,0 +1,8 @@
+// Instantiations of the fused iteration kernel for float frames.
+#include "lk_iter_impl.h"
+
+namespace ofmi {
+
+hipError_t launch_iter_f32(const IterArgs& a, int R, hipStream_t s) { return launch_iter_t<float>(a, R, s); }
+
+}  // namespace ofmi

@@ -1,0 +1,282 @@
+// One fused Gauss-Newton iteration of the dense window-based Lucas-Kanade method at one
+// pyramid level (Sec. 2.4): warp of frame 2 by the current field, central-difference
+// gradients of the warped frame, the five window sums, the 2x2 solve and the update.
+//
+// Work decomposition (gfx950, wave64):
+//   * a workgroup of 5*TW threads owns a strip of TW output columns and TH output rows;
+//   * it walks down the strip in bands of N = 2r+1 product rows; per band:
+//       P1  warped frame for the band's new rows into an LDS ring; all global loads of the
+//           band (field, frame 1, centre field of the band's outputs) are issued here;
+//       P2  the five products Ix^2, IxIy, Iy^2, Ix It, Iy It of the band's rows into LDS;
+//       P3  horizontal window sums: one thread per (channel, row, 8-column segment), a
+//           direct (2r+1)-term sum re-seeded at every segment, then a running sum over the
+//           segment's 8 outputs (segments sit on multiples of 8 of the level's columns);
+//       P4  vertical window sums: one thread per (channel, column) holds the previous
+//           band's horizontal sums in registers; the window of the band's row i is the
+//           suffix sum of the previous band from row i+1 plus the prefix sum of the current
+//           band up to row i (fixed order; bands sit on a global grid of period N);
+//       P5  per-pixel 2x2 solve and update for the band's output rows.
+//   The window sums therefore do not depend on how the image is cut into tiles.
+#pragma once
+
+#include "kernels.h"
+
+namespace ofmi {
+
+namespace {
+
+template <int R, int TW_>
+struct Cfg {
+  static constexpr int N = 2 * R + 1;                 // band height = window height
+  static constexpr int TW = TW_;                      // output columns per strip
+  static constexpr int NT = 5 * TW;                   // threads per workgroup
+  static constexpr int PC = TW + 2 * R;               // product columns
+  static constexpr int WC = PC + 2;                   // warped-frame columns
+  static constexpr int HL = 8 + 2 * R;                // products read per horizontal segment
+  static constexpr int HL4 = (HL + 3) / 4;            // ... in float4 units
+  static constexpr int PP = ((TW + 4 * HL4 - 8) + 3) / 4 * 4 + 4;  // product row pitch
+  static constexpr int WP = WC + 1;                   // warped-frame row pitch
+  static constexpr int RING = N + 2 <= 16 ? 16 : 32;  // warped-frame ring rows (power of 2)
+  static constexpr int NSEG = TW / 8;
+  static constexpr int P1_ROWS_MAX = N + 2;
+  static constexpr int K1 = (P1_ROWS_MAX * WC + NT - 1) / NT;   // P1 items per thread
+  static constexpr int K2 = (N * PC + NT - 1) / NT;             // P2 items per thread
+  static constexpr int K3 = (5 * N * NSEG + NT - 1) / NT;       // P3 items per thread
+  static constexpr int K5 = (N * TW + NT - 1) / NT;             // P5 items per thread
+  static constexpr size_t LDS_FLOATS = 5 * (size_t)N * PP + 5 * (size_t)N * TW + (size_t)RING * WP;
+};
+
+template <typename T, int R, int TW, int MODE>
+__global__ __launch_bounds__(5 * TW) void lk_iter_strip(IterArgs a, int TH, int nbands) {
+  using C = Cfg<R, TW>;
+  constexpr int N = C::N, NT = C::NT, PC = C::PC, WC = C::WC, PP = C::PP, WP = C::WP;
+  constexpr int RMASK = C::RING - 1;
+  extern __shared__ float4 sm4[];
+  float* sm = reinterpret_cast<float*>(sm4);
+  float* pr = sm;                               // [5][N][PP] products (16-byte aligned rows)
+  float* hs = pr + 5 * N * PP;                  // [5][N][TW] horizontal, then window sums
+  float* w2 = hs + 5 * N * TW;                  // [RING][WP] warped frame ring
+
+  const int tid = threadIdx.x;
+  const int H = a.H, W = a.W;
+  const int x0 = blockIdx.x * TW;
+  const int y0 = blockIdx.y * TH;
+  const T* __restrict__ I1 = (const T*)a.I1;
+  const T* __restrict__ I2 = (const T*)a.I2;
+
+  // P4 ownership: channel and column of this thread.
+  const int vk = tid / TW, vc = tid - vk * TW;
+  float prev[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) prev[i] = 0.f;
+
+  for (int b = 0; b < nbands; ++b) {
+    const int tb = N * b;                        // first product row of the band
+    // ---------------------------------------------------------------- P1
+    // Every global load of the band is issued here, branch-free (clamped addresses; results
+    // for items outside the image or the band are discarded), in two rounds: the field at the
+    // warped-frame positions, frame 1 and the field at this thread's P2 items and the centre
+    // field of its P5 items; then the four frame-2 samples of every warped-frame position.
+    const int wfirst = b == 0 ? -1 : tb + 1;
+    const int nw = (b == 0 ? N + 2 : N) * WC;
+    int wofs[C::K1], wgx[C::K1], wgy[C::K1];
+    float wu[C::K1], wv[C::K1];
+#pragma unroll
+    for (int k = 0; k < C::K1; ++k) {
+      const int i = min(tid + k * NT, nw - 1);
+      const int w = wfirst + i / WC, lx = i % WC;
+      wgx[k] = min(max(x0 - R - 1 + lx, 0), W - 1);
+      wgy[k] = min(max(y0 - R + w, 0), H - 1);
+      wofs[k] = (w & RMASK) * WP + lx;
+      read_flow<MODE>(a, wgx[k], wgy[k], wu[k], wv[k]);
+    }
+    float i1v[C::K2], pu[C::K2], pv[C::K2];
+#pragma unroll
+    for (int k = 0; k < C::K2; ++k) {
+      const int i = min(tid + k * NT, N * PC - 1);
+      const int gx = min(max(x0 - R + i % PC, 0), W - 1);
+      const int gy = min(max(y0 - R + tb + i / PC, 0), H - 1);
+      i1v[k] = ld(I1, (unsigned)gy * (unsigned)W + (unsigned)gx);
+      read_flow<MODE>(a, gx, gy, pu[k], pv[k]);
+    }
+    float cu[C::K5], cv[C::K5];
+#pragma unroll
+    for (int k = 0; k < C::K5; ++k) {
+      const int i = min(tid + k * NT, N * TW - 1);
+      const int gx = min(x0 + i % TW, W - 1);
+      const int gy = min(max(y0 + tb + i / TW - 2 * R, 0), H - 1);
+      read_flow<MODE>(a, gx, gy, cu[k], cv[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < C::K1; ++k) {
+      const float z = warp_sample(I2, H, W, wgx[k], wgy[k], wu[k], wv[k]);
+      if (tid + k * NT < nw) w2[wofs[k]] = z;
+    }
+    __syncthreads();
+    // ---------------------------------------------------------------- P2
+#pragma unroll
+    for (int k = 0; k < C::K2; ++k) {
+      const int i = tid + k * NT;
+      if (i < N * PC) {
+        const int r = i / PC, c = i % PC;
+        const int t = tb + r;
+        const int gx = x0 - R + c, gy = y0 - R + t;
+        float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f, p4 = 0.f;
+        if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
+          const int s0 = t & RMASK, sm1 = (t - 1) & RMASK, sp1 = (t + 1) & RMASK;
+          const float* row = w2 + s0 * WP + c + 1;
+          const float ix = 0.5f * (row[1] - row[-1]);
+          const float iy = 0.5f * (w2[sp1 * WP + c + 1] - w2[sm1 * WP + c + 1]);
+          float it = row[0] - i1v[k];
+          it = fmaf(-ix, pu[k], it);
+          it = fmaf(-iy, pv[k], it);
+          p0 = ix * ix;
+          p1 = ix * iy;
+          p2 = iy * iy;
+          p3 = ix * it;
+          p4 = iy * it;
+        }
+        float* q = pr + r * PP + c;
+        q[0] = p0;
+        q[N * PP] = p1;
+        q[2 * N * PP] = p2;
+        q[3 * N * PP] = p3;
+        q[4 * N * PP] = p4;
+      }
+    }
+    __syncthreads();
+    // ---------------------------------------------------------------- P3
+#pragma unroll
+    for (int k = 0; k < C::K3; ++k) {
+      const int i = tid + k * NT;
+      if (i < 5 * N * C::NSEG) {
+        const int seg = i % C::NSEG, rr = i / C::NSEG;   // rr = ch * N + row
+        const float4* src = reinterpret_cast<const float4*>(pr + rr * PP + 8 * seg);
+        float vbuf[4 * C::HL4];
+#pragma unroll
+        for (int q = 0; q < C::HL4; ++q) {
+          const float4 f = src[q];
+          vbuf[4 * q] = f.x;
+          vbuf[4 * q + 1] = f.y;
+          vbuf[4 * q + 2] = f.z;
+          vbuf[4 * q + 3] = f.w;
+        }
+        float out[8];
+        float s = vbuf[0];
+#pragma unroll
+        for (int q = 1; q <= 2 * R; ++q) s += vbuf[q];
+        out[0] = s;
+#pragma unroll
+        for (int j = 1; j < 8; ++j) {
+          s = (s - vbuf[j - 1]) + vbuf[j + 2 * R];
+          out[j] = s;
+        }
+        float4* dst = reinterpret_cast<float4*>(hs + rr * C::TW + 8 * seg);
+        dst[0] = make_float4(out[0], out[1], out[2], out[3]);
+        dst[1] = make_float4(out[4], out[5], out[6], out[7]);
+      }
+    }
+    __syncthreads();
+    // ---------------------------------------------------------------- P4
+    {
+      float cur[N];
+      float* col = hs + vk * N * TW + vc;
+#pragma unroll
+      for (int r = 0; r < N; ++r) cur[r] = col[r * TW];
+      // suffix sums of the previous band: suf[r] = prev[r] + ... + prev[N-1]
+      float suf[N + 1];
+      suf[N] = 0.f;
+      suf[N - 1] = prev[N - 1];
+#pragma unroll
+      for (int r = N - 2; r >= 0; --r) suf[r] = suf[r + 1] + prev[r];
+      float pre = 0.f;
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        pre = r == 0 ? cur[0] : pre + cur[r];
+        col[r * TW] = r + 1 < N ? suf[r + 1] + pre : pre;
+        prev[r] = cur[r];
+      }
+    }
+    __syncthreads();
+    // ---------------------------------------------------------------- P5
+#pragma unroll
+    for (int k = 0; k < C::K5; ++k) {
+      const int i = tid + k * NT;
+      if (i < N * TW) {
+        const int r = i / TW, c = i % TW;
+        const int j = tb + r - 2 * R;
+        const int gx = x0 + c, gy = y0 + j;
+        if (j >= 0 && j < TH && gx < W && gy < H) {
+          const float* s = hs + r * TW + c;
+          float un, vn;
+          solve_update(s[0], s[N * TW], s[2 * N * TW], s[3 * N * TW], s[4 * N * TW], cu[k],
+                       cv[k], un, vn);
+          const unsigned o = (unsigned)gy * (unsigned)W + (unsigned)gx;
+          at(a.uout, o) = un;
+          at(a.vout, o) = vn;
+        }
+      }
+    }
+    // The next band's P1 writes ring rows and P2/P3 buffers that P2/P3 of this band have
+    // finished reading before the barriers above; P5 reads only hs, which the next band
+    // rewrites after two more barriers.
+  }
+}
+
+template <typename T, int R, int TW, int MODE>
+hipError_t go_strip(const IterArgs& a, int TH, hipStream_t s) {
+  using C = Cfg<R, TW>;
+  const int nbands = TH / C::N + 1;
+  dim3 grid((a.W + TW - 1) / TW, (a.H + TH - 1) / TH);
+  const size_t lds = C::LDS_FLOATS * sizeof(float);
+  hipLaunchKernelGGL((lk_iter_strip<T, R, TW, MODE>), grid, dim3(C::NT), lds, s, a, TH, nbands);
+  return hipGetLastError();
+}
+
+template <typename T, int R, int MODE>
+hipError_t go_rm(const IterArgs& a, hipStream_t s) {
+  constexpr int N = 2 * R + 1;
+  // Tile height: a multiple of the band height; short tiles on small levels for parallelism.
+  const long long px = (long long)a.H * a.W;
+  const int nb = px >= (1 << 22) ? 4 : (px >= (1 << 18) ? 2 : 1);
+  const int TH = N * nb;
+  // 64-column strips while the LDS footprint stays within 64 KB, else 32-column strips.
+  if constexpr (Cfg<R, 64>::LDS_FLOATS * sizeof(float) <= 65536)
+    return go_strip<T, R, 64, MODE>(a, TH, s);
+  else
+    return go_strip<T, R, 32, MODE>(a, TH, s);
+}
+
+template <typename T, int R>
+hipError_t go_r(const IterArgs& a, hipStream_t s) {
+  switch (a.mode) {
+    case kFlowSame: return go_rm<T, R, kFlowSame>(a, s);
+    case kFlowCoarse: return go_rm<T, R, kFlowCoarse>(a, s);
+    case kFlowZero: return go_rm<T, R, kFlowZero>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_iter_t(const IterArgs& a, int R, hipStream_t s) {
+  switch (R) {
+    case 0: return go_r<T, 0>(a, s);
+    case 1: return go_r<T, 1>(a, s);
+    case 2: return go_r<T, 2>(a, s);
+    case 3: return go_r<T, 3>(a, s);
+    case 4: return go_r<T, 4>(a, s);
+    case 5: return go_r<T, 5>(a, s);
+    case 6: return go_r<T, 6>(a, s);
+    case 7: return go_r<T, 7>(a, s);
+    case 8: return go_r<T, 8>(a, s);
+    case 9: return go_r<T, 9>(a, s);
+    case 10: return go_r<T, 10>(a, s);
+    case 11: return go_r<T, 11>(a, s);
+    case 12: return go_r<T, 12>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+}  // namespace ofmi

@@ -1,0 +1,8 @@
+// Instantiations of the fused iteration kernel for uint8_t frames.
+#include "lk_iter_impl.h"
+
+namespace ofmi {
+
+hipError_t launch_iter_u8(const IterArgs& a, int R, hipStream_t s) { return launch_iter_t<uint8_t>(a, R, s); }
+
+}  // namespace ofmi

@@ -19,19 +19,19 @@ __global__ __launch_bounds__(256) void reduce_kernel(const Tin* __restrict__ in1
   const Tin* in = blockIdx.z ? in2 : in1;
   Tout* out = blockIdx.z ? out2 : out1;
   const float k[5] = {kB0, kB1, kB2, kB1, kB0};
-  int rows[5];
+  unsigned rows[5];
 #pragma unroll
-  for (int a = 0; a < 5; ++a) rows[a] = min(max(2 * i + a - 2, 0), H - 1) * W;
+  for (int a = 0; a < 5; ++a) rows[a] = (unsigned)min(max(2 * i + a - 2, 0), H - 1) * (unsigned)W;
   float acc = 0.f;
 #pragma unroll
   for (int b = 0; b < 5; ++b) {
-    const int xx = min(max(2 * j + b - 2, 0), W - 1);
+    const unsigned xx = (unsigned)min(max(2 * j + b - 2, 0), W - 1);
     float col = 0.f;
 #pragma unroll
     for (int a = 0; a < 5; ++a) col = fmaf(k[a], ld(in, rows[a] + xx), col);
     acc = fmaf(k[b], col, acc);
   }
-  st(out, i * Wo + j, acc);
+  st(out, (unsigned)i * (unsigned)Wo + (unsigned)j, acc);
 }
 
 template <typename Tin, typename Tout>
