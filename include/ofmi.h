@@ -64,6 +64,8 @@ typedef enum {
 /* Flags of the *_ex constructors. */
 #define OF_FLAG_FP16_STORAGE (1u << 0) /* pyramid levels >= 1 stored in FP16; all math FP32 */
 #define OF_FLAG_INPUT_F32    (1u << 1) /* frames are float32 instead of uint8 */
+#define OF_FLAG_NO_GRAPH     (1u << 2) /* launch kernels one by one instead of replaying a
+                                          captured hipGraph of the schedule */
 
 #define OF_MAX_LEVELS 12
 #define OF_MAX_RADIUS 12
@@ -91,7 +93,10 @@ OF_API of_plan* of_plan_create_ex(int H, int W, int levels, int radius, int iter
 
 /* Dense flow from frame I1 to frame I2 (both H x W, uint8 or float32 per the plan's flags)
  * into u and v (H x W float32, 4-byte aligned, u != v).  Enqueues the pyramid build and the
- * levels x iters iterations on `stream`.  iters = 0 writes zeros.
+ * levels x iters iterations on `stream`.  iters = 0 writes zeros.  Unless OF_FLAG_NO_GRAPH is
+ * set (or kernel timing is on), the schedule is captured once per distinct (I1, I2, u, v)
+ * into a hipGraph held by the plan (at most 64, least recently used evicted) and replayed on
+ * `stream`; the first call for a pointer tuple pays the capture.
  * Errors: OF_EINVAL on a NULL plan or pointer or u == v (nothing enqueued); OF_EHIP if a
  * launch fails. */
 OF_API of_status of_compute(of_plan* plan, const void* I1, const void* I2, float* u, float* v,
@@ -118,6 +123,59 @@ OF_API const char* of_last_error(void);
 OF_API of_status of_plan_set_timing(of_plan* plan, int enable);
 OF_API of_status of_plan_read_timing(of_plan* plan, int kernel, double* total_ms,
                                      long long* launches, double* units, double* bytes);
+
+/* --------------------------------------------------------------------- batched form
+ * Many frame pairs of different sizes with common levels, radius and iterations, computed
+ * together: each pyramid step and each (level, iteration) phase of the method (Sec. 2.4) is
+ * one launch whose workgroups stride over a work list of tiles of all pairs.  The paper runs
+ * one field at a time and notes that fields are independent of one another (Sec. 3.3); the
+ * batch exploits that independence on one device. */
+typedef struct of_batch of_batch;
+
+/* Workspace bytes of a batch of n pairs of sizes H[i] x W[i] (host arrays), 0 on invalid
+ * parameters (each pair as of_plan_create_ex; 1 <= n <= 65536). */
+OF_API size_t of_batch_workspace_bytes(int n, const int* H, const int* W, int levels, int radius,
+                                       int iters, unsigned flags);
+
+/* Batch object.  H, W: host arrays of n sizes (copied).  workspace as in of_plan_create_ex.
+ * Returns NULL on invalid parameters or allocation failure. */
+OF_API of_batch* of_batch_create(int n, const int* H, const int* W, int levels, int radius,
+                                 int iters, unsigned flags, void* workspace,
+                                 size_t workspace_bytes);
+
+/* Flow of every pair i: frames I1[i] -> I2[i] into u[i], v[i].  I1, I2, u, v are HOST arrays
+ * of n DEVICE pointers, each plane laid out as for of_compute with pair i's size.  The whole
+ * schedule is one hipGraph replay per call, captured on the first call with a given set of
+ * pointers (at most 64 sets kept; each holds a small device argument block).  With
+ * OF_FLAG_NO_GRAPH or timing on, launches are eager and the arguments are uploaded through a
+ * pinned staging buffer.  Results are bitwise identical to of_compute on the same pair with
+ * the same tile configuration (the window sums do not depend on the tiling).
+ * Errors: OF_EINVAL for a NULL batch, array or buffer or u[i] == v[i]; OF_EHIP on launch
+ * failure. */
+OF_API of_status of_batch_compute(of_batch* b, const void* const* I1, const void* const* I2,
+                                  float* const* u, float* const* v, void* stream);
+
+/* Per-level launch configuration: bands[l] = tile height in bands of 2r+1 rows (1..64),
+ * grid[l] = workgroups of the iteration launches (0 = one per tile, else a persistent grid
+ * striding over the work list).  Arrays of `levels` entries.  set_config rebuilds the work
+ * lists and drops captured graphs. */
+OF_API of_status of_batch_get_config(const of_batch* b, int* bands, int* grid);
+OF_API of_status of_batch_set_config(of_batch* b, const int* bands, const int* grid);
+
+/* Autotuner: for each level in turn, times that level's iteration launches for every
+ * candidate (bands in {1,2,4,8}, grid in {one per tile, 256, 512, 1024, 2048}) on the given
+ * buffers (reps timed runs after one warm-up) and keeps the fastest.  Synchronises `stream`.
+ * The chosen configuration is read back with of_batch_get_config. */
+OF_API of_status of_batch_autotune(of_batch* b, const void* const* I1, const void* const* I2,
+                                   float* const* u, float* const* v, void* stream, int reps);
+
+/* Kernel timing of a batch, as of_plan_set_timing / of_plan_read_timing. */
+OF_API of_status of_batch_set_timing(of_batch* b, int enable);
+OF_API of_status of_batch_read_timing(of_batch* b, int kernel, double* total_ms,
+                                      long long* launches, double* units, double* bytes);
+
+/* Releases the batch (synchronises the device first).  NULL-safe. */
+OF_API void of_batch_destroy(of_batch* b);
 
 /* --------------------------------------------------------------------- stage entry points
  * One step of the method on caller buffers, for stage-by-stage checking.

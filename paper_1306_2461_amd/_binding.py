@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libofmi.so")
 OF_OK, OF_EINVAL, OF_ENOMEM, OF_EHIP, OF_ESTATE = range(5)
 OF_FLAG_FP16_STORAGE = 1 << 0
 OF_FLAG_INPUT_F32 = 1 << 1
+OF_FLAG_NO_GRAPH = 1 << 2
 OF_STAGE_REDUCE = 0
 OF_STAGE_ITERATE = 1
 OF_KERNEL_ITERATE = 0
@@ -32,6 +33,17 @@ SIGNATURES = {
     "of_plan_destroy": (None, [_vp]),
     "of_last_error": (ctypes.c_char_p, []),
     "of_debug_stage": (_c_int, [_vp, _c_int, _c_int, _VPP, _VPP, _vp]),
+    "of_batch_workspace_bytes": (_c_size, [_c_int, _INTP, _INTP, _c_int, _c_int, _c_int, _c_uint]),
+    "of_batch_create": (_vp, [_c_int, _INTP, _INTP, _c_int, _c_int, _c_int, _c_uint, _vp, _c_size]),
+    "of_batch_compute": (_c_int, [_vp, _VPP, _VPP, _VPP, _VPP, _vp]),
+    "of_batch_get_config": (_c_int, [_vp, _INTP, _INTP]),
+    "of_batch_set_config": (_c_int, [_vp, _INTP, _INTP]),
+    "of_batch_autotune": (_c_int, [_vp, _VPP, _VPP, _VPP, _VPP, _vp, _c_int]),
+    "of_batch_set_timing": (_c_int, [_vp, _c_int]),
+    "of_batch_read_timing": (_c_int, [_vp, _c_int, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_longlong),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "of_batch_destroy": (None, [_vp]),
     "of_plan_set_timing": (_c_int, [_vp, _c_int]),
     "of_plan_read_timing": (_c_int, [_vp, _c_int, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_longlong),

@@ -30,10 +30,12 @@ class Plan:
     The workspace is a torch allocation owned by the plan.
     """
 
-    def __init__(self, H, W, levels, radius, iters, fp16=False, input_f32=False, device=None):
+    def __init__(self, H, W, levels, radius, iters, fp16=False, input_f32=False, device=None,
+                 graph=True):
         lib = B.load()
         self.H, self.W, self.levels, self.radius, self.iters = H, W, levels, radius, iters
-        self.flags = (B.OF_FLAG_FP16_STORAGE if fp16 else 0) | (B.OF_FLAG_INPUT_F32 if input_f32 else 0)
+        self.flags = ((B.OF_FLAG_FP16_STORAGE if fp16 else 0) | (B.OF_FLAG_INPUT_F32 if input_f32 else 0)
+                      | (0 if graph else B.OF_FLAG_NO_GRAPH))
         self.frame_dtype = torch.float32 if input_f32 else torch.uint8
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         nbytes = lib.of_plan_workspace_bytes(H, W, levels, radius, iters, self.flags)
@@ -62,6 +64,10 @@ class Plan:
                                  v.data_ptr(), _stream_handle(self.device, stream))
         B.check(st, "of_compute")
         return u, v
+
+    def compute_raw(self, i1_ptr: int, i2_ptr: int, u_ptr: int, v_ptr: int, stream_handle: int):
+        """of_compute on raw device pointers (no Python-side checks; the C side validates)."""
+        B.check(B.load().of_compute(self._h, i1_ptr, i2_ptr, u_ptr, v_ptr, stream_handle), "of_compute")
 
     def set_timing(self, enable: bool):
         """Bracket every kernel launch with hipEvents on its stream (measurement only)."""
@@ -109,3 +115,104 @@ def debug_stage(plan: Plan, stage: int, level: int, inputs, outputs, stream=None
     st = B.load().of_debug_stage(plan._h, stage, level, pin, pout,
                                  _stream_handle(plan.device, stream))
     B.check(st, "of_debug_stage")
+
+
+class Batch:
+    """``of_batch``: many frame pairs of different sizes computed together.
+
+    ``sizes`` is a list of (H, W); all pairs share levels, radius, iterations and flags.
+    Each pyramid step and each (level, iteration) phase is one launch over a work list of
+    all pairs' tiles; the whole schedule is replayed as a hipGraph per set of buffers.
+    """
+
+    def __init__(self, sizes, levels, radius, iters, fp16=False, input_f32=False, device=None,
+                 graph=True):
+        import ctypes
+        lib = B.load()
+        self.sizes = [(int(h), int(w)) for h, w in sizes]
+        self.n = len(self.sizes)
+        self.levels, self.radius, self.iters = levels, radius, iters
+        self.flags = ((B.OF_FLAG_FP16_STORAGE if fp16 else 0) | (B.OF_FLAG_INPUT_F32 if input_f32 else 0)
+                      | (0 if graph else B.OF_FLAG_NO_GRAPH))
+        self.frame_dtype = torch.float32 if input_f32 else torch.uint8
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self._H = (ctypes.c_int * self.n)(*[h for h, _ in self.sizes])
+        self._W = (ctypes.c_int * self.n)(*[w for _, w in self.sizes])
+        nbytes = lib.of_batch_workspace_bytes(self.n, self._H, self._W, levels, radius, iters, self.flags)
+        if nbytes == 0:
+            raise B.OfError(f"invalid batch parameters: {B.last_error()}")
+        self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            h = lib.of_batch_create(self.n, self._H, self._W, levels, radius, iters, self.flags,
+                                    self._ws.data_ptr(), nbytes)
+        if not h:
+            raise B.OfError(f"of_batch_create failed: {B.last_error()}")
+        self._h = h
+        self.workspace_bytes = nbytes
+
+    def outputs(self):
+        """Fresh (us, vs) lists of float32 planes for every pair."""
+        us = [torch.empty(s, dtype=torch.float32, device=self.device) for s in self.sizes]
+        vs = [torch.empty(s, dtype=torch.float32, device=self.device) for s in self.sizes]
+        return us, vs
+
+    def pointer_arrays(self, I1s, I2s, us, vs):
+        """ctypes pointer arrays for compute_raw (checks every plane once)."""
+        for i, (h, w) in enumerate(self.sizes):
+            _check_frame(I1s[i], h, w, self.frame_dtype, self.device, f"I1[{i}]")
+            _check_frame(I2s[i], h, w, self.frame_dtype, self.device, f"I2[{i}]")
+            _check_frame(us[i], h, w, torch.float32, self.device, f"u[{i}]")
+            _check_frame(vs[i], h, w, torch.float32, self.device, f"v[{i}]")
+        return tuple(B.ptr_array([t.data_ptr() for t in ts]) for ts in (I1s, I2s, us, vs))
+
+    def compute(self, I1s, I2s, us=None, vs=None, stream=None):
+        if us is None or vs is None:
+            us, vs = self.outputs()
+        arrs = self.pointer_arrays(I1s, I2s, us, vs)
+        self.compute_raw(arrs, _stream_handle(self.device, stream))
+        return us, vs
+
+    def compute_raw(self, arrs, stream_handle: int):
+        """of_batch_compute on pointer arrays from pointer_arrays()."""
+        (p1, _a), (p2, _b), (pu, _c), (pv, _d) = arrs
+        B.check(B.load().of_batch_compute(self._h, p1, p2, pu, pv, stream_handle), "of_batch_compute")
+
+    def autotune(self, I1s, I2s, us, vs, reps=3, stream=None):
+        (p1, _a), (p2, _b), (pu, _c), (pv, _d) = self.pointer_arrays(I1s, I2s, us, vs)
+        B.check(B.load().of_batch_autotune(self._h, p1, p2, pu, pv, _stream_handle(self.device, stream), reps),
+                "of_batch_autotune")
+        return self.config()
+
+    def config(self):
+        import ctypes
+        bands = (ctypes.c_int * self.levels)()
+        grid = (ctypes.c_int * self.levels)()
+        B.check(B.load().of_batch_get_config(self._h, bands, grid), "of_batch_get_config")
+        return {"bands": list(bands), "grid": list(grid)}
+
+    def set_config(self, cfg):
+        import ctypes
+        bands = (ctypes.c_int * self.levels)(*cfg["bands"])
+        grid = (ctypes.c_int * self.levels)(*cfg["grid"])
+        B.check(B.load().of_batch_set_config(self._h, bands, grid), "of_batch_set_config")
+
+    def set_timing(self, enable: bool):
+        B.check(B.load().of_batch_set_timing(self._h, 1 if enable else 0), "of_batch_set_timing")
+
+    def read_timing(self, kernel: int):
+        import ctypes
+        ms, n, un, by = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
+        B.check(B.load().of_batch_read_timing(self._h, kernel, ctypes.byref(ms), ctypes.byref(n),
+                                              ctypes.byref(un), ctypes.byref(by)), "of_batch_read_timing")
+        return ms.value, n.value, un.value, by.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            B.load().of_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,532 @@
+// Batched form of the method: many frame pairs of different sizes with the same levels,
+// radius and iteration count.  Every (level, iteration) phase is one launch whose
+// workgroups stride over a work list of tiles of all pairs; the pyramid steps are batched
+// the same way.  The whole schedule of a batch is captured once per set of caller buffers
+// into a hipGraph and replayed.  Tile height and workgroup count per level come from a
+// configuration the autotuner can search.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/ofmi.h"
+#include "kernels.h"
+#include "runtime.h"
+
+using namespace ofmi;
+
+namespace {
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct LevelCfg {
+  int nb;     // tile height in bands of 2R+1 rows
+  int grid;   // iteration workgroups; 0 = one per tile
+};
+
+}  // namespace
+
+struct of_batch {
+  int n = 0, L = 0, R = 0, K = 0;
+  unsigned flags = 0;
+  int device = 0;
+  std::vector<Geometry> g;          // per pair
+  std::vector<size_t> pair_off;     // workspace offset of each pair's buffers
+  char* ws = nullptr;               // workspace (pair buffers, work lists, eager arguments)
+  bool owns_ws = false;
+  size_t off_tiles = 0, cap_tiles = 0;   // int4 tile lists of all levels (capacity per level)
+  size_t off_items = 0;                  // int2 pyramid items of all levels
+  size_t off_args = 0;                   // eager argument block
+  size_t arg_bytes = 0;
+  std::vector<int> ntiles, nitems;
+  std::vector<size_t> items_at;
+  LevelCfg cfg[OF_MAX_LEVELS];
+  std::vector<char> staging_host;   // argument block being built
+  char* pinned = nullptr;           // pinned staging for eager uploads
+  hipEvent_t staged = nullptr;      // last eager upload consumed the staging buffer
+  bool staged_pending = false;
+  KernelTimer timer;
+  GraphCache graphs;
+  std::vector<void*> graph_args;    // device argument blocks of cached graphs
+};
+
+namespace {
+
+of_status hip_fail(const char* what, hipError_t e) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return OF_EHIP;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) hipSetDevice(prev);
+  }
+};
+
+// Bytes of the argument block: pyramid jobs of all reduce steps, then the iteration
+// arguments of all phases.
+size_t args_bytes(int n, int L, int K) {
+  return align256(sizeof(ReduceJob) * 2 * (size_t)n * (L > 1 ? L - 1 : 0)) +
+         align256(sizeof(IterArgs) * (size_t)n * L * (K > 0 ? K : 1));
+}
+
+bool check_batch(int n, const int* H, const int* W, int levels, int radius, int iters,
+                 unsigned flags) {
+  if (n < 1 || n > 65536) return set_error("batch size out of range"), false;
+  if (!H || !W) return set_error("NULL size arrays"), false;
+  for (int i = 0; i < n; ++i)
+    if (!check_params(H[i], W[i], levels, radius, iters, flags)) {
+      set_error("pair " + std::to_string(i) + ": " + of_last_error());
+      return false;
+    }
+  return true;
+}
+
+int default_batch_bands(const of_batch* b, int l) {
+  long long px = 0;
+  for (int i = 0; i < b->n; ++i) px += (long long)b->g[i].H[l] * b->g[i].W[l];
+  // Many pairs fill the device even with tall tiles, which cut the vertical halo.
+  if (px >= (24ll << 20)) return 4;
+  if (px >= (4ll << 20)) return 2;
+  return 1;
+}
+
+// Tile work list of level l for the current configuration (host side).
+std::vector<int4> tile_list(const of_batch* b, int l) {
+  const int TW = strip_width_for(b->R);
+  const int TH = (2 * b->R + 1) * b->cfg[l].nb;
+  std::vector<int4> t;
+  for (int p = 0; p < b->n; ++p) {
+    const int tx = (b->g[p].W[l] + TW - 1) / TW, ty = (b->g[p].H[l] + TH - 1) / TH;
+    for (int y = 0; y < ty; ++y)
+      for (int x = 0; x < tx; ++x) t.push_back(make_int4(p, x, y, TH));
+  }
+  return t;
+}
+
+hipError_t upload_tiles(of_batch* b) {
+  for (int l = 0; l < b->L; ++l) {
+    std::vector<int4> t = tile_list(b, l);
+    if (t.size() > b->cap_tiles) return hipErrorInvalidValue;
+    b->ntiles[l] = (int)t.size();
+    hipError_t e = hipMemcpy(b->ws + b->off_tiles + l * b->cap_tiles * sizeof(int4), t.data(),
+                             t.size() * sizeof(int4), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Fill the argument block for the given caller buffers.
+void fill_args(const of_batch* b, char* blk, const void* const* I1, const void* const* I2,
+               float* const* u, float* const* v) {
+  const int n = b->n, L = b->L, K = b->K;
+  ReduceJob* jobs = (ReduceJob*)blk;
+  IterArgs* args =
+      (IterArgs*)(blk + align256(sizeof(ReduceJob) * 2 * (size_t)n * (L > 1 ? L - 1 : 0)));
+  for (int p = 0; p < n; ++p) {
+    const Geometry& g = b->g[p];
+    char* ws = b->ws + b->pair_off[p];
+    const void* P1[OF_MAX_LEVELS];
+    const void* P2[OF_MAX_LEVELS];
+    P1[0] = I1[p];
+    P2[0] = I2[p];
+    for (int l = 1; l < L; ++l) {
+      P1[l] = ws + g.off_p1[l];
+      P2[l] = ws + g.off_p2[l];
+      ReduceJob* j = jobs + (size_t)(l - 1) * 2 * n + 2 * p;
+      j[0] = {P1[l - 1], (void*)P1[l], g.H[l - 1], g.W[l - 1], g.H[l], g.W[l]};
+      j[1] = {P2[l - 1], (void*)P2[l], g.H[l - 1], g.W[l - 1], g.H[l], g.W[l]};
+    }
+    float* fu[2] = {(float*)(ws + g.off_flow[0]), (float*)(ws + g.off_flow[1])};
+    float* fv[2] = {(float*)(ws + g.off_flow[2]), (float*)(ws + g.off_flow[3])};
+    const float* cu = nullptr;
+    const float* cv = nullptr;
+    int cH = 0, cW = 0, buf = 0, phase = 0;
+    for (int l = L - 1; l >= 0; --l) {
+      for (int k = 0; k < K; ++k, ++phase) {
+        IterArgs& a = args[(size_t)phase * n + p];
+        a = IterArgs{};
+        a.I1 = P1[l];
+        a.I2 = P2[l];
+        a.H = g.H[l];
+        a.W = g.W[l];
+        a.uin = cu;
+        a.vin = cv;
+        a.Hc = cH;
+        a.Wc = cW;
+        a.mode = k > 0 ? kFlowSame : (l == L - 1 ? kFlowZero : kFlowCoarse);
+        const bool last = (l == 0 && k == K - 1);
+        a.uout = last ? u[p] : fu[buf];
+        a.vout = last ? v[p] : fv[buf];
+        cu = a.uout;
+        cv = a.vout;
+        cH = a.H;
+        cW = a.W;
+        buf ^= 1;
+      }
+    }
+  }
+}
+
+// Enqueue the whole schedule reading arguments from device block `blk`.
+hipError_t enqueue_batch(of_batch* b, char* blk, float* const* u, float* const* v,
+                         hipStream_t s, KernelTimer* t) {
+  const int n = b->n, L = b->L, K = b->K;
+  if (K == 0) {
+    for (int p = 0; p < n; ++p) {
+      hipError_t e = launch_zero(u[p], v[p], (size_t)b->g[p].H[0] * b->g[p].W[0], s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  const Geometry& g0 = b->g[0];
+  const ReduceJob* jobs = (const ReduceJob*)blk;
+  const IterArgs* args =
+      (const IterArgs*)(blk + align256(sizeof(ReduceJob) * 2 * (size_t)n * (L > 1 ? L - 1 : 0)));
+  for (int l = 1; l < L; ++l) {
+    hipEvent_t ev = nullptr;
+    hipError_t e = t ? t->begin(s, &ev) : hipSuccess;
+    const int ni = b->nitems[l];
+    if (e == hipSuccess)
+      e = launch_reduce_batch(g0.elem(l - 1), g0.ep, jobs + (size_t)(l - 1) * 2 * n,
+                              (const int2*)(b->ws + b->items_at[l]), ni, std::min(ni, 8192), s);
+    if (e == hipSuccess && t) {
+      double no = 0, bytes = 0;
+      for (int p = 0; p < n; ++p) {
+        const double o = (double)b->g[p].H[l] * b->g[p].W[l];
+        const double i = (double)b->g[p].H[l - 1] * b->g[p].W[l - 1];
+        no += 2 * o;
+        bytes += 2 * (i * elem_bytes(g0.elem(l - 1)) + o * elem_bytes(g0.ep));
+      }
+      e = t->end(s, ev, OF_KERNEL_REDUCE, no, bytes);
+    }
+    if (e != hipSuccess) return e;
+  }
+  int phase = 0;
+  for (int l = L - 1; l >= 0; --l) {
+    double px = 0;
+    for (int p = 0; p < n; ++p) px += (double)b->g[p].H[l] * b->g[p].W[l];
+    for (int k = 0; k < K; ++k, ++phase) {
+      BatchLaunch bl;
+      bl.args = args + (size_t)phase * n;
+      bl.tiles = (const int4*)(b->ws + b->off_tiles + l * b->cap_tiles * sizeof(int4));
+      bl.ntiles = b->ntiles[l];
+      bl.grid = b->cfg[l].grid > 0 ? std::min(b->cfg[l].grid, bl.ntiles) : bl.ntiles;
+      bl.grid = (bl.grid + 7) / 8 * 8;
+      const int mode = k > 0 ? kFlowSame : (l == L - 1 ? kFlowZero : kFlowCoarse);
+      hipEvent_t ev = nullptr;
+      hipError_t e = t ? t->begin(s, &ev) : hipSuccess;
+      if (e == hipSuccess) e = launch_iter_batch(g0.elem(l), bl, b->R, mode, s);
+      if (e == hipSuccess && t)
+        e = t->end(s, ev, OF_KERNEL_ITERATE, px, px * (2.0 * elem_bytes(g0.elem(l)) + 16.0));
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+// Eager path: stage the argument block through pinned memory into the workspace copy.
+hipError_t run_eager(of_batch* b, const void* const* I1, const void* const* I2, float* const* u,
+                     float* const* v, hipStream_t s, KernelTimer* t) {
+  hipError_t e;
+  if (b->staged_pending) {
+    e = hipEventSynchronize(b->staged);
+    if (e != hipSuccess) return e;
+  }
+  fill_args(b, b->pinned, I1, I2, u, v);
+  char* blk = b->ws + b->off_args;
+  e = hipMemcpyAsync(blk, b->pinned, b->arg_bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b->staged, s);
+  if (e != hipSuccess) return e;
+  b->staged_pending = true;
+  return enqueue_batch(b, blk, u, v, s, t);
+}
+
+void drop_graphs(of_batch* b) {
+  hipDeviceSynchronize();
+  b->graphs.clear();
+  for (void* p : b->graph_args) hipFree(p);
+  b->graph_args.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t of_batch_workspace_bytes(int n, const int* H, const int* W, int levels, int radius,
+                                int iters, unsigned flags) {
+  if (!check_batch(n, H, W, levels, radius, iters, flags)) return 0;
+  size_t off = 0, tiles = 0, items = 0;
+  const int N = 2 * radius + 1, TW = strip_width_for(radius);
+  for (int l = 0; l < levels; ++l) {
+    size_t tl = 0, it = 0;
+    for (int p = 0; p < n; ++p) {
+      Geometry g = make_geometry(H[p], W[p], levels, radius, iters, flags);
+      if (l == 0) off += align256(g.bytes);
+      tl += (size_t)((g.W[l] + TW - 1) / TW) * ((g.H[l] + N - 1) / N);
+      if (l >= 1) it += 2 * (size_t)((g.W[l] + 63) / 64) * ((g.H[l] + 3) / 4);
+    }
+    tiles = std::max(tiles, tl);
+    items += align256(it * sizeof(int2));
+  }
+  return off + align256(tiles * sizeof(int4)) * levels + items + args_bytes(n, levels, iters);
+}
+
+of_batch* of_batch_create(int n, const int* H, const int* W, int levels, int radius, int iters,
+                          unsigned flags, void* workspace, size_t workspace_bytes) {
+  if (!check_batch(n, H, W, levels, radius, iters, flags)) return nullptr;
+  const size_t need = of_batch_workspace_bytes(n, H, W, levels, radius, iters, flags);
+  if (workspace && workspace_bytes < need) {
+    set_error("workspace smaller than of_batch_workspace_bytes()");
+    return nullptr;
+  }
+  if (workspace && ((uintptr_t)workspace & 255)) {
+    set_error("workspace must be 256-byte aligned");
+    return nullptr;
+  }
+  of_batch* b = new of_batch();
+  b->n = n;
+  b->L = levels;
+  b->R = radius;
+  b->K = iters;
+  b->flags = flags;
+  hipError_t e = hipGetDevice(&b->device);
+  if (e != hipSuccess) {
+    hip_fail("hipGetDevice", e);
+    delete b;
+    return nullptr;
+  }
+  size_t off = 0;
+  for (int p = 0; p < n; ++p) {
+    b->g.push_back(make_geometry(H[p], W[p], levels, radius, iters, flags));
+    b->pair_off.push_back(off);
+    off += align256(b->g.back().bytes);
+  }
+  const int N = 2 * radius + 1, TW = strip_width_for(radius);
+  size_t cap = 0;
+  for (int l = 0; l < levels; ++l) {
+    size_t tl = 0;
+    for (int p = 0; p < n; ++p)
+      tl += (size_t)((b->g[p].W[l] + TW - 1) / TW) * ((b->g[p].H[l] + N - 1) / N);
+    cap = std::max(cap, tl);
+  }
+  b->cap_tiles = align256(cap * sizeof(int4)) / sizeof(int4);
+  b->off_tiles = off;
+  off += b->cap_tiles * sizeof(int4) * levels;
+  b->off_items = off;
+  b->ntiles.assign(levels, 0);
+  b->nitems.assign(levels, 0);
+  b->items_at.assign(levels, 0);
+  std::vector<std::vector<int2>> items(levels);
+  for (int l = 1; l < levels; ++l) {
+    for (int p = 0; p < n; ++p) {
+      const int blocks = ((b->g[p].W[l] + 63) / 64) * ((b->g[p].H[l] + 3) / 4);
+      for (int f = 0; f < 2; ++f)
+        for (int k = 0; k < blocks; ++k) items[l].push_back(make_int2(2 * p + f, k));
+    }
+    b->items_at[l] = off;
+    b->nitems[l] = (int)items[l].size();
+    off += align256(items[l].size() * sizeof(int2));
+  }
+  b->off_args = off;
+  b->arg_bytes = args_bytes(n, levels, iters);
+  off += b->arg_bytes;
+  if (off != need) {
+    set_error("internal: workspace layout mismatch");
+    delete b;
+    return nullptr;
+  }
+  if (workspace) {
+    b->ws = (char*)workspace;
+  } else {
+    e = hipMalloc((void**)&b->ws, need);
+    if (e != hipSuccess) {
+      hip_fail("hipMalloc(batch workspace)", e);
+      delete b;
+      return nullptr;
+    }
+    b->owns_ws = true;
+  }
+  for (int l = 0; l < levels; ++l) b->cfg[l] = {default_batch_bands(b, l), 0};
+  e = upload_tiles(b);
+  for (int l = 1; l < levels && e == hipSuccess; ++l)
+    e = hipMemcpy(b->ws + b->items_at[l], items[l].data(), items[l].size() * sizeof(int2),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b->pinned, b->arg_bytes, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    hip_fail("batch set-up", e);
+    of_batch_destroy(b);
+    return nullptr;
+  }
+  return b;
+}
+
+of_status of_batch_compute(of_batch* b, const void* const* I1, const void* const* I2,
+                           float* const* u, float* const* v, void* stream) {
+  if (!b) return set_error("NULL batch"), OF_EINVAL;
+  if (!I1 || !I2 || !u || !v) return set_error("NULL pointer array"), OF_EINVAL;
+  for (int p = 0; p < b->n; ++p) {
+    if (!I1[p] || !I2[p] || !u[p] || !v[p])
+      return set_error("NULL buffer of pair " + std::to_string(p)), OF_EINVAL;
+    if (u[p] == v[p] || (((uintptr_t)u[p] | (uintptr_t)v[p]) & 3))
+      return set_error("bad output planes of pair " + std::to_string(p)), OF_EINVAL;
+  }
+  DeviceGuard guard(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (b->timer.on || (b->flags & OF_FLAG_NO_GRAPH)) {
+    e = run_eager(b, I1, I2, u, v, s, &b->timer);
+  } else {
+    std::vector<uintptr_t> key;
+    key.reserve(4 * (size_t)b->n);
+    for (int p = 0; p < b->n; ++p) {
+      key.push_back((uintptr_t)I1[p]);
+      key.push_back((uintptr_t)I2[p]);
+      key.push_back((uintptr_t)u[p]);
+      key.push_back((uintptr_t)v[p]);
+    }
+    char* blk = nullptr;
+    e = hipSuccess;
+    if (!b->graphs.contains(key)) {
+      // A new pointer set: the graph gets its own argument block, uploaded before capture.
+      if (b->graphs.entries.size() >= b->graphs.max_entries) drop_graphs(b);
+      e = hipMalloc((void**)&blk, b->arg_bytes);
+      if (e == hipSuccess) {
+        b->graph_args.push_back(blk);
+        b->staging_host.resize(b->arg_bytes);
+        fill_args(b, b->staging_host.data(), I1, I2, u, v);
+        e = hipMemcpy(blk, b->staging_host.data(), b->arg_bytes, hipMemcpyHostToDevice);
+      }
+    }
+    if (e == hipSuccess)
+      e = b->graphs.run(key, s, [&](hipStream_t cs) { return enqueue_batch(b, blk, u, v, cs, nullptr); });
+  }
+  if (e != hipSuccess) return hip_fail("batch launch", e), OF_EHIP;
+  return OF_OK;
+}
+
+void of_batch_destroy(of_batch* b) {
+  if (!b) return;
+  DeviceGuard guard(b->device);
+  hipDeviceSynchronize();
+  drop_graphs(b);
+  if (b->staged) hipEventDestroy(b->staged);
+  if (b->pinned) hipHostFree(b->pinned);
+  if (b->owns_ws) hipFree(b->ws);
+  delete b;
+}
+
+of_status of_batch_set_timing(of_batch* b, int enable) {
+  if (!b) return set_error("NULL batch"), OF_EINVAL;
+  b->timer.on = enable != 0;
+  return OF_OK;
+}
+
+of_status of_batch_read_timing(of_batch* b, int kernel, double* total_ms, long long* launches,
+                               double* units, double* bytes) {
+  if (!b) return set_error("NULL batch"), OF_EINVAL;
+  if (kernel != OF_KERNEL_ITERATE && kernel != OF_KERNEL_REDUCE)
+    return set_error("unknown kernel id"), OF_EINVAL;
+  DeviceGuard guard(b->device);
+  hipError_t e = b->timer.read(kernel, total_ms, launches, units, bytes);
+  if (e != hipSuccess) return hip_fail("timing events", e);
+  return OF_OK;
+}
+
+of_status of_batch_get_config(const of_batch* b, int* bands, int* grid) {
+  if (!b || !bands || !grid) return set_error("NULL argument"), OF_EINVAL;
+  for (int l = 0; l < b->L; ++l) {
+    bands[l] = b->cfg[l].nb;
+    grid[l] = b->cfg[l].grid;
+  }
+  return OF_OK;
+}
+
+of_status of_batch_set_config(of_batch* b, const int* bands, const int* grid) {
+  if (!b || !bands || !grid) return set_error("NULL argument"), OF_EINVAL;
+  for (int l = 0; l < b->L; ++l)
+    if (bands[l] < 1 || bands[l] > 64 || grid[l] < 0)
+      return set_error("config out of range"), OF_EINVAL;
+  DeviceGuard guard(b->device);
+  drop_graphs(b);
+  for (int l = 0; l < b->L; ++l) b->cfg[l] = {bands[l], grid[l]};
+  hipError_t e = upload_tiles(b);
+  if (e != hipSuccess) return hip_fail("tile lists", e);
+  return OF_OK;
+}
+
+of_status of_batch_autotune(of_batch* b, const void* const* I1, const void* const* I2,
+                            float* const* u, float* const* v, void* stream, int reps) {
+  if (!b || !I1 || !I2 || !u || !v) return set_error("NULL argument"), OF_EINVAL;
+  if (reps < 1) reps = 1;
+  DeviceGuard guard(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  const bool was_on = b->timer.on;
+  b->timer.on = true;
+  static const int kBands[] = {1, 2, 4, 8};
+  static const int kGrid[] = {0, 256, 512, 1024, 2048};
+  hipError_t e = hipSuccess;
+  // Coordinate descent, one level at a time: the iteration time of that level only.
+  for (int l = 0; l < b->L && e == hipSuccess; ++l) {
+    int maxH = 0;
+    for (int p = 0; p < b->n; ++p) maxH = std::max(maxH, b->g[p].H[l]);
+    double best = 1e30;
+    LevelCfg bestc = b->cfg[l];
+    for (int nb : kBands) {
+      if (nb > 1 && (2 * b->R + 1) * nb > 2 * maxH) continue;
+      for (int gr : kGrid) {
+        b->cfg[l] = {nb, gr};
+        e = upload_tiles(b);
+        if (e != hipSuccess) break;
+        double tl = 1e30;
+        for (int r = 0; r < reps + 1 && e == hipSuccess; ++r) {
+          e = run_eager(b, I1, I2, u, v, s, &b->timer);
+          if (e != hipSuccess) break;
+          // Launch k of level l is the ((L-1-l)*K + k)-th iteration launch of the run.
+          std::vector<KernelTimer::Rec> mine;
+          e = hipStreamSynchronize(s);
+          if (e != hipSuccess) break;
+          int idx = 0;
+          double sum = 0;
+          const int first = (b->L - 1 - l) * b->K;
+          for (const KernelTimer::Rec& rc : b->timer.recs) {
+            if (rc.kernel != OF_KERNEL_ITERATE) continue;
+            if (idx >= first && idx < first + b->K) {
+              float ms = 0;
+              hipEventElapsedTime(&ms, rc.a, rc.b);
+              sum += ms;
+            }
+            ++idx;
+          }
+          double d1, d2, d3;
+          long long n1;
+          b->timer.read(OF_KERNEL_ITERATE, &d1, &n1, &d2, &d3);
+          b->timer.read(OF_KERNEL_REDUCE, &d1, &n1, &d2, &d3);
+          if (r > 0) tl = std::min(tl, sum);
+        }
+        if (e == hipSuccess && tl < best) {
+          best = tl;
+          bestc = {nb, gr};
+        }
+      }
+    }
+    b->cfg[l] = bestc;
+    if (e == hipSuccess) e = upload_tiles(b);
+  }
+  b->timer.on = was_on;
+  drop_graphs(b);
+  if (e != hipSuccess) return hip_fail("autotune", e);
+  return OF_OK;
+}
+
+}  // extern "C"

@@ -12,12 +12,39 @@ enum class Elem : int { U8 = 0, F32 = 1, F16 = 2 };
 
 inline size_t elem_bytes(Elem e) { return e == Elem::U8 ? 1 : (e == Elem::F16 ? 2 : 4); }
 
+// One plane reduction job of a batched pyramid step.
+struct ReduceJob {
+  const void* in;
+  void* out;
+  int H, W, Ho, Wo;
+};
+
+// Batched pyramid step over (job, 64x4 output block) work items.
+hipError_t launch_reduce_batch(Elem tin, Elem tout, const ReduceJob* jobs, const int2* items,
+                               int nitems, int grid, hipStream_t s);
+
 // One pyramid reduction of up to two frames of the same geometry (out = reduce(in)).
 hipError_t launch_reduce(Elem tin, Elem tout, const void* in1, const void* in2, int H, int W,
                          void* out1, void* out2, int Ho, int Wo, hipStream_t s);
 
-// One fused Gauss-Newton iteration at one level (frames of element type `t`).
-hipError_t launch_iter(Elem t, const IterArgs& a, int R, hipStream_t s);
+// Batched iteration launch: `grid` workgroups stride over `ntiles` work items
+// (pair, tile x, tile y, tile height) with per-pair arguments args[pair] (device arrays).
+struct BatchLaunch {
+  const IterArgs* args;
+  const int4* tiles;
+  int ntiles;
+  int grid;
+};
+
+// Strip width (output columns per tile) and band height of the iteration kernel for radius R.
+int strip_width_for(int R);
+
+// One fused Gauss-Newton iteration at one level (frames of element type `t`), tiles of height
+// (2R+1)*nb.
+hipError_t launch_iter(Elem t, const IterArgs& a, int R, int nb, hipStream_t s);
+
+// The same over a work list of many pairs' tiles at one (level, iteration) phase.
+hipError_t launch_iter_batch(Elem t, const BatchLaunch& b, int R, int mode, hipStream_t s);
 
 // u = v = 0 over n elements (a fill kernel, safe under stream capture).
 hipError_t launch_zero(float* u, float* v, size_t n, hipStream_t s);

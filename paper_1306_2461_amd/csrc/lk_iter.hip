@@ -3,9 +3,14 @@
 
 namespace ofmi {
 
-hipError_t launch_iter_u8(const IterArgs& a, int R, hipStream_t s);
-hipError_t launch_iter_f32(const IterArgs& a, int R, hipStream_t s);
-hipError_t launch_iter_f16(const IterArgs& a, int R, hipStream_t s);
+hipError_t launch_iter_u8(const IterArgs* a, const BatchLaunch* b, int R, int mode, int nb, hipStream_t s);
+hipError_t launch_iter_f32(const IterArgs* a, const BatchLaunch* b, int R, int mode, int nb, hipStream_t s);
+hipError_t launch_iter_f16(const IterArgs* a, const BatchLaunch* b, int R, int mode, int nb, hipStream_t s);
+
+int strip_width_for(int R) {
+  // Mirrors strip_width<R>(): 64 columns while the LDS footprint fits in 64 KB.
+  return R <= 8 ? 64 : 32;
+}
 
 namespace {
 
@@ -19,11 +24,21 @@ __global__ void zero_kernel(float* u, float* v, size_t n) {
 
 }  // namespace
 
-hipError_t launch_iter(Elem t, const IterArgs& a, int R, hipStream_t s) {
+hipError_t launch_iter(Elem t, const IterArgs& a, int R, int nb, hipStream_t s) {
   switch (t) {
-    case Elem::U8: return launch_iter_u8(a, R, s);
-    case Elem::F32: return launch_iter_f32(a, R, s);
-    case Elem::F16: return launch_iter_f16(a, R, s);
+    case Elem::U8: return launch_iter_u8(&a, nullptr, R, a.mode, nb, s);
+    case Elem::F32: return launch_iter_f32(&a, nullptr, R, a.mode, nb, s);
+    case Elem::F16: return launch_iter_f16(&a, nullptr, R, a.mode, nb, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_iter_batch(Elem t, const BatchLaunch& b, int R, int mode, hipStream_t s) {
+  if (b.ntiles <= 0) return hipSuccess;
+  switch (t) {
+    case Elem::U8: return launch_iter_u8(nullptr, &b, R, mode, 0, s);
+    case Elem::F32: return launch_iter_f32(nullptr, &b, R, mode, 0, s);
+    case Elem::F16: return launch_iter_f16(nullptr, &b, R, mode, 0, s);
   }
   return hipErrorInvalidValue;
 }

@@ -3,6 +3,9 @@
 
 namespace ofmi {
 
-hipError_t launch_iter_f16(const IterArgs& a, int R, hipStream_t s) { return launch_iter_t<__half>(a, R, s); }
+hipError_t launch_iter_f16(const IterArgs* a, const BatchLaunch* b, int R, int mode, int nb,
+                            hipStream_t s) {
+  return launch_iter_t<__half>(a, b, R, mode, nb, s);
+}
 
 }  // namespace ofmi

@@ -46,12 +46,14 @@ struct Cfg {
   static constexpr size_t LDS_FLOATS = 5 * (size_t)N * PP + 5 * (size_t)N * TW + (size_t)RING * WP;
 };
 
+// One tile: TW output columns from x0 = bx*TW and TH output rows from y0 = by*TH, walked in
+// nbands bands (TH is a multiple of N; nbands = TH/N + 1).  `sm4` is the workgroup's LDS.
 template <typename T, int R, int TW, int MODE>
-__global__ __launch_bounds__(5 * TW) void lk_iter_strip(IterArgs a, int TH, int nbands) {
+__device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands, int bx, int by,
+                                           float4* sm4) {
   using C = Cfg<R, TW>;
   constexpr int N = C::N, NT = C::NT, PC = C::PC, WC = C::WC, PP = C::PP, WP = C::WP;
   constexpr int RMASK = C::RING - 1;
-  extern __shared__ float4 sm4[];
   float* sm = reinterpret_cast<float*>(sm4);
   float* pr = sm;                               // [5][N][PP] products (16-byte aligned rows)
   float* hs = pr + 5 * N * PP;                  // [5][N][TW] horizontal, then window sums
@@ -59,8 +61,8 @@ __global__ __launch_bounds__(5 * TW) void lk_iter_strip(IterArgs a, int TH, int 
 
   const int tid = threadIdx.x;
   const int H = a.H, W = a.W;
-  const int x0 = blockIdx.x * TW;
-  const int y0 = blockIdx.y * TH;
+  const int x0 = bx * TW;
+  const int y0 = by * TH;
   const T* __restrict__ I1 = (const T*)a.I1;
   const T* __restrict__ I2 = (const T*)a.I2;
 
@@ -223,56 +225,96 @@ __global__ __launch_bounds__(5 * TW) void lk_iter_strip(IterArgs a, int TH, int 
   }
 }
 
+// Workgroup index -> work index so that the workgroups one XCD runs (hardware dispatch is
+// round-robin over the 8 XCDs) take a contiguous range of tiles, which share halos in L2.
+__device__ __forceinline__ int xcd_order(int b, int nblocks) {
+  constexpr int kXcd = 8;
+  const int per = (nblocks + kXcd - 1) / kXcd;
+  return (b % kXcd) * per + b / kXcd;
+}
+
 template <typename T, int R, int TW, int MODE>
-hipError_t go_strip(const IterArgs& a, int TH, hipStream_t s) {
+__global__ __launch_bounds__(5 * TW) void lk_iter_strip(IterArgs a, int TH, int nbands, int tiles_x,
+                                                        int ntiles) {
+  extern __shared__ float4 sm4[];
+  const int t = xcd_order(blockIdx.x, gridDim.x);
+  if (t >= ntiles) return;
+  strip_tile<T, R, TW, MODE>(a, TH, nbands, t % tiles_x, t / tiles_x, sm4);
+}
+
+// Batched form: workgroups stride over a work list of tiles of many pairs at the same
+// (level, iteration) phase.  Work item = (pair, tile x, tile y, tile height).
+template <typename T, int R, int TW, int MODE>
+__global__ __launch_bounds__(5 * TW) void lk_iter_batch(const IterArgs* __restrict__ args,
+                                                        const int4* __restrict__ tiles,
+                                                        int ntiles) {
+  extern __shared__ float4 sm4[];
   using C = Cfg<R, TW>;
-  const int nbands = TH / C::N + 1;
-  dim3 grid((a.W + TW - 1) / TW, (a.H + TH - 1) / TH);
-  const size_t lds = C::LDS_FLOATS * sizeof(float);
-  hipLaunchKernelGGL((lk_iter_strip<T, R, TW, MODE>), grid, dim3(C::NT), lds, s, a, TH, nbands);
+  const int stride = (int)gridDim.x;
+  for (int t = xcd_order(blockIdx.x, gridDim.x); t < ntiles; t += stride) {
+    const int4 w = tiles[t];
+    const IterArgs a = args[w.x];
+    strip_tile<T, R, TW, MODE>(a, w.w, w.w / C::N + 1, w.y, w.z, sm4);
+    __syncthreads();
+  }
+}
+
+// 64-column strips while the LDS footprint stays within 64 KB, else 32-column strips.
+template <int R>
+constexpr int strip_width() {
+  return Cfg<R, 64>::LDS_FLOATS * sizeof(float) <= 65536 ? 64 : 32;
+}
+
+template <typename T, int R, int MODE>
+hipError_t go_plain(const IterArgs& a, int nb, hipStream_t s) {
+  constexpr int TW = strip_width<R>();
+  using C = Cfg<R, TW>;
+  const int TH = C::N * nb;
+  const int tx = (a.W + TW - 1) / TW, ty = (a.H + TH - 1) / TH;
+  const int ntiles = tx * ty;
+  const int grid = (ntiles + 7) / 8 * 8;
+  hipLaunchKernelGGL((lk_iter_strip<T, R, TW, MODE>), dim3(grid), dim3(C::NT),
+                     C::LDS_FLOATS * sizeof(float), s, a, TH, nb + 1, tx, ntiles);
   return hipGetLastError();
 }
 
 template <typename T, int R, int MODE>
-hipError_t go_rm(const IterArgs& a, hipStream_t s) {
-  constexpr int N = 2 * R + 1;
-  // Tile height: a multiple of the band height; short tiles on small levels for parallelism.
-  const long long px = (long long)a.H * a.W;
-  const int nb = px >= (1 << 22) ? 4 : (px >= (1 << 18) ? 2 : 1);
-  const int TH = N * nb;
-  // 64-column strips while the LDS footprint stays within 64 KB, else 32-column strips.
-  if constexpr (Cfg<R, 64>::LDS_FLOATS * sizeof(float) <= 65536)
-    return go_strip<T, R, 64, MODE>(a, TH, s);
-  else
-    return go_strip<T, R, 32, MODE>(a, TH, s);
+hipError_t go_batch(const BatchLaunch& b, hipStream_t s) {
+  constexpr int TW = strip_width<R>();
+  using C = Cfg<R, TW>;
+  hipLaunchKernelGGL((lk_iter_batch<T, R, TW, MODE>), dim3(b.grid), dim3(C::NT),
+                     C::LDS_FLOATS * sizeof(float), s, b.args, b.tiles, b.ntiles);
+  return hipGetLastError();
 }
 
 template <typename T, int R>
-hipError_t go_r(const IterArgs& a, hipStream_t s) {
-  switch (a.mode) {
-    case kFlowSame: return go_rm<T, R, kFlowSame>(a, s);
-    case kFlowCoarse: return go_rm<T, R, kFlowCoarse>(a, s);
-    case kFlowZero: return go_rm<T, R, kFlowZero>(a, s);
+hipError_t go_r(const IterArgs* a, const BatchLaunch* b, int mode, int nb, hipStream_t s) {
+  switch (mode) {
+    case kFlowSame: return a ? go_plain<T, R, kFlowSame>(*a, nb, s) : go_batch<T, R, kFlowSame>(*b, s);
+    case kFlowCoarse: return a ? go_plain<T, R, kFlowCoarse>(*a, nb, s) : go_batch<T, R, kFlowCoarse>(*b, s);
+    case kFlowZero: return a ? go_plain<T, R, kFlowZero>(*a, nb, s) : go_batch<T, R, kFlowZero>(*b, s);
   }
   return hipErrorInvalidValue;
 }
 
+// Plain launch (a != nullptr; tile height N*nb) or batched launch (b != nullptr).
 template <typename T>
-hipError_t launch_iter_t(const IterArgs& a, int R, hipStream_t s) {
+hipError_t launch_iter_t(const IterArgs* a, const BatchLaunch* b, int R, int mode, int nb,
+                         hipStream_t s) {
   switch (R) {
-    case 0: return go_r<T, 0>(a, s);
-    case 1: return go_r<T, 1>(a, s);
-    case 2: return go_r<T, 2>(a, s);
-    case 3: return go_r<T, 3>(a, s);
-    case 4: return go_r<T, 4>(a, s);
-    case 5: return go_r<T, 5>(a, s);
-    case 6: return go_r<T, 6>(a, s);
-    case 7: return go_r<T, 7>(a, s);
-    case 8: return go_r<T, 8>(a, s);
-    case 9: return go_r<T, 9>(a, s);
-    case 10: return go_r<T, 10>(a, s);
-    case 11: return go_r<T, 11>(a, s);
-    case 12: return go_r<T, 12>(a, s);
+    case 0: return go_r<T, 0>(a, b, mode, nb, s);
+    case 1: return go_r<T, 1>(a, b, mode, nb, s);
+    case 2: return go_r<T, 2>(a, b, mode, nb, s);
+    case 3: return go_r<T, 3>(a, b, mode, nb, s);
+    case 4: return go_r<T, 4>(a, b, mode, nb, s);
+    case 5: return go_r<T, 5>(a, b, mode, nb, s);
+    case 6: return go_r<T, 6>(a, b, mode, nb, s);
+    case 7: return go_r<T, 7>(a, b, mode, nb, s);
+    case 8: return go_r<T, 8>(a, b, mode, nb, s);
+    case 9: return go_r<T, 9>(a, b, mode, nb, s);
+    case 10: return go_r<T, 10>(a, b, mode, nb, s);
+    case 11: return go_r<T, 11>(a, b, mode, nb, s);
+    case 12: return go_r<T, 12>(a, b, mode, nb, s);
   }
   return hipErrorInvalidValue;
 }

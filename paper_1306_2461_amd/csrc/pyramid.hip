@@ -34,6 +34,45 @@ __global__ __launch_bounds__(256) void reduce_kernel(const Tin* __restrict__ in1
   st(out, (unsigned)i * (unsigned)Wo + (unsigned)j, acc);
 }
 
+// Batched reduction: workgroups stride over a list of (job, block) items; a block is 64x4
+// output pixels of one job's output plane.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void reduce_batch_kernel(const ReduceJob* __restrict__ jobs,
+                                                            const int2* __restrict__ items,
+                                                            int nitems) {
+  const float k[5] = {kB0, kB1, kB2, kB1, kB0};
+  for (int t = blockIdx.x; t < nitems; t += gridDim.x) {
+    const int2 it = items[t];
+    const ReduceJob jb = jobs[it.x];
+    const int bxn = (jb.Wo + 63) / 64;
+    const int j = (it.y % bxn) * 64 + (threadIdx.x & 63);
+    const int i = (it.y / bxn) * 4 + (threadIdx.x >> 6);
+    if (i >= jb.Ho || j >= jb.Wo) continue;
+    const Tin* in = (const Tin*)jb.in;
+    unsigned rows[5];
+#pragma unroll
+    for (int a = 0; a < 5; ++a)
+      rows[a] = (unsigned)min(max(2 * i + a - 2, 0), jb.H - 1) * (unsigned)jb.W;
+    float acc = 0.f;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      const unsigned xx = (unsigned)min(max(2 * j + b - 2, 0), jb.W - 1);
+      float col = 0.f;
+#pragma unroll
+      for (int a = 0; a < 5; ++a) col = fmaf(k[a], ld(in, rows[a] + xx), col);
+      acc = fmaf(k[b], col, acc);
+    }
+    st((Tout*)jb.out, (unsigned)i * (unsigned)jb.Wo + (unsigned)j, acc);
+  }
+}
+
+template <typename Tin, typename Tout>
+hipError_t go_batch(const ReduceJob* jobs, const int2* items, int nitems, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((reduce_batch_kernel<Tin, Tout>), dim3(grid), dim3(256), 0, s, jobs, items,
+                     nitems);
+  return hipGetLastError();
+}
+
 template <typename Tin, typename Tout>
 hipError_t go(const void* in1, const void* in2, int H, int W, void* out1, void* out2, int Ho,
               int Wo, hipStream_t s) {
@@ -44,6 +83,20 @@ hipError_t go(const void* in1, const void* in2, int H, int W, void* out1, void* 
 }
 
 }  // namespace
+
+hipError_t launch_reduce_batch(Elem tin, Elem tout, const ReduceJob* jobs, const int2* items,
+                               int nitems, int grid, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  if (tout == Elem::F32) {
+    if (tin == Elem::U8) return go_batch<uint8_t, float>(jobs, items, nitems, grid, s);
+    if (tin == Elem::F32) return go_batch<float, float>(jobs, items, nitems, grid, s);
+  } else if (tout == Elem::F16) {
+    if (tin == Elem::U8) return go_batch<uint8_t, __half>(jobs, items, nitems, grid, s);
+    if (tin == Elem::F32) return go_batch<float, __half>(jobs, items, nitems, grid, s);
+    if (tin == Elem::F16) return go_batch<__half, __half>(jobs, items, nitems, grid, s);
+  }
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_reduce(Elem tin, Elem tout, const void* in1, const void* in2, int H, int W,
                          void* out1, void* out2, int Ho, int Wo, hipStream_t s) {

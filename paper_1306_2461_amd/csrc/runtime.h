@@ -2,6 +2,7 @@
 #pragma once
 
 #include <stddef.h>
+#include <stdint.h>
 
 #include <string>
 #include <vector>
@@ -20,6 +21,7 @@ struct Geometry {
   size_t off_p1[OF_MAX_LEVELS];     // workspace offsets of the pyramid levels (>= 1)
   size_t off_p2[OF_MAX_LEVELS];
   size_t off_flow[4];               // ping-pong u0, u1, v0, v1 (level-0 size each)
+  int nb[OF_MAX_LEVELS];            // iteration tile height per level, in bands of 2R+1 rows
   size_t bytes;
   Elem elem(int l) const;
 };
@@ -40,7 +42,69 @@ struct KernelTimer {
   ~KernelTimer();
 };
 
+// Captured schedules replayed with hipGraphLaunch, keyed by the caller's buffer pointers.
+// Capture runs on a private stream; a replay is enqueued on the caller's stream.
+struct GraphCache {
+  struct Entry {
+    std::vector<uintptr_t> key;
+    hipGraphExec_t exec;
+    unsigned long long used;
+  };
+  std::vector<Entry> entries;
+  hipStream_t cap = nullptr;
+  unsigned long long tick = 0;
+  size_t max_entries = 64;
+  template <class F>
+  hipError_t run(const std::vector<uintptr_t>& key, hipStream_t s, F&& enqueue);
+  bool contains(const std::vector<uintptr_t>& key) const {
+    for (const Entry& e : entries)
+      if (e.key == key) return true;
+    return false;
+  }
+  void clear();
+  ~GraphCache();
+};
+
+template <class F>
+hipError_t GraphCache::run(const std::vector<uintptr_t>& key, hipStream_t s, F&& enqueue) {
+  for (Entry& e : entries) {
+    if (e.key == key) {
+      e.used = ++tick;
+      return hipGraphLaunch(e.exec, s);
+    }
+  }
+  hipError_t err;
+  if (!cap) {
+    err = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (err != hipSuccess) return err;
+  }
+  err = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+  if (err != hipSuccess) return err;
+  hipError_t eq = enqueue(cap);
+  hipGraph_t graph = nullptr;
+  err = hipStreamEndCapture(cap, &graph);
+  if (eq != hipSuccess || err != hipSuccess) {
+    if (graph) hipGraphDestroy(graph);
+    return eq != hipSuccess ? eq : err;
+  }
+  hipGraphExec_t exec = nullptr;
+  err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (err != hipSuccess) return err;
+  if (entries.size() >= max_entries) {
+    hipDeviceSynchronize();   // the evicted graph may still be in flight
+    size_t lru = 0;
+    for (size_t i = 1; i < entries.size(); ++i)
+      if (entries[i].used < entries[lru].used) lru = i;
+    hipGraphExecDestroy(entries[lru].exec);
+    entries.erase(entries.begin() + lru);
+  }
+  entries.push_back({key, exec, ++tick});
+  return hipGraphLaunch(exec, s);
+}
+
 void set_error(const std::string& s);
+int default_bands(int H, int W, int R);
 bool check_params(int H, int W, int levels, int radius, int iters, unsigned flags);
 Geometry make_geometry(int H, int W, int levels, int radius, int iters, unsigned flags);
 hipError_t enqueue_pair(const Geometry& g, char* ws, const void* I1, const void* I2, float* u,

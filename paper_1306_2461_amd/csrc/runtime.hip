@@ -27,8 +27,17 @@ bool check_params(int H, int W, int levels, int radius, int iters, unsigned flag
   if (levels > maxl) return set_error("levels > 1 + floor(log2(min(H, W)))"), false;
   if (radius < 0 || radius > OF_MAX_RADIUS) return set_error("radius out of range"), false;
   if (iters < 0 || iters > OF_MAX_ITERS) return set_error("iters out of range"), false;
-  if (flags & ~(OF_FLAG_FP16_STORAGE | OF_FLAG_INPUT_F32)) return set_error("unknown flags"), false;
+  if (flags & ~(OF_FLAG_FP16_STORAGE | OF_FLAG_INPUT_F32 | OF_FLAG_NO_GRAPH))
+    return set_error("unknown flags"), false;
   return true;
+}
+
+// Tile height (in bands of 2R+1 rows) of the iteration kernel for one image of a level:
+// taller tiles cut the vertical halo, shorter ones give more workgroups to small levels.
+int default_bands(int H, int W, int R) {
+  const long long px = (long long)H * W;
+  (void)R;
+  return px >= (1 << 22) ? 4 : (px >= (1 << 18) ? 2 : 1);
 }
 
 Geometry make_geometry(int H, int W, int levels, int radius, int iters, unsigned flags) {
@@ -43,6 +52,7 @@ Geometry make_geometry(int H, int W, int levels, int radius, int iters, unsigned
     g.H[l] = (g.H[l - 1] + 1) / 2;
     g.W[l] = (g.W[l - 1] + 1) / 2;
   }
+  for (int l = 0; l < levels; ++l) g.nb[l] = default_bands(g.H[l], g.W[l], radius);
   g.e0 = (flags & OF_FLAG_INPUT_F32) ? Elem::F32 : Elem::U8;
   g.ep = (flags & OF_FLAG_FP16_STORAGE) ? Elem::F16 : Elem::F32;
   size_t off = 0;
@@ -121,6 +131,16 @@ hipError_t KernelTimer::read(int kernel, double* ms, long long* n, double* units
   return hipSuccess;
 }
 
+void GraphCache::clear() {
+  for (Entry& e : entries) hipGraphExecDestroy(e.exec);
+  entries.clear();
+}
+
+GraphCache::~GraphCache() {
+  clear();
+  if (cap) hipStreamDestroy(cap);
+}
+
 KernelTimer::~KernelTimer() {
   for (const Rec& r : recs) {
     hipEventDestroy(r.a);
@@ -176,7 +196,7 @@ hipError_t enqueue_pair(const Geometry& g, char* ws, const void* I1, const void*
       a.vout = last ? v : fv[buf];
       hipEvent_t ev;
       hipError_t e = t ? t->begin(s, &ev) : hipSuccess;
-      if (e == hipSuccess) e = launch_iter(g.elem(l), a, g.R, s);
+      if (e == hipSuccess) e = launch_iter(g.elem(l), a, g.R, g.nb[l], s);
       if (e == hipSuccess && t) {
         const double n = (double)a.H * a.W;
         e = t->end(s, ev, OF_KERNEL_ITERATE, n, n * (2.0 * elem_bytes(g.elem(l)) + 16.0));
@@ -202,6 +222,7 @@ struct of_plan {
   bool owns_ws;
   int device;
   KernelTimer timer;
+  GraphCache graphs;
 };
 
 namespace {
@@ -260,7 +281,7 @@ of_plan* of_plan_create_ex(int H, int W, int levels, int radius, int iters, unsi
     }
     owns = true;
   }
-  of_plan* p = new of_plan{g, ws, owns, dev, {}};
+  of_plan* p = new of_plan{g, ws, owns, dev, {}, {}};
   return p;
 }
 
@@ -277,7 +298,15 @@ of_status of_compute(of_plan* p, const void* I1, const void* I2, float* u, float
   if ((p->g.flags & OF_FLAG_INPUT_F32) && (((uintptr_t)I1 | (uintptr_t)I2) & 3))
     return set_error("float32 frames must be 4-byte aligned"), OF_EINVAL;
   DeviceGuard guard(p->device);
-  hipError_t e = enqueue_pair(p->g, p->ws, I1, I2, u, v, (hipStream_t)stream, &p->timer);
+  hipError_t e;
+  if (p->timer.on || (p->g.flags & OF_FLAG_NO_GRAPH)) {
+    e = enqueue_pair(p->g, p->ws, I1, I2, u, v, (hipStream_t)stream, &p->timer);
+  } else {
+    const std::vector<uintptr_t> key = {(uintptr_t)I1, (uintptr_t)I2, (uintptr_t)u, (uintptr_t)v};
+    e = p->graphs.run(key, (hipStream_t)stream, [&](hipStream_t cs) {
+      return enqueue_pair(p->g, p->ws, I1, I2, u, v, cs, nullptr);
+    });
+  }
   if (e != hipSuccess) return hip_fail("kernel launch", e);
   return OF_OK;
 }
@@ -286,6 +315,7 @@ void of_plan_destroy(of_plan* p) {
   if (!p) return;
   DeviceGuard guard(p->device);
   hipDeviceSynchronize();
+  p->graphs.clear();
   if (p->owns_ws) hipFree(p->ws);
   delete p;
 }
@@ -336,7 +366,7 @@ of_status of_debug_stage(of_plan* p, int stage, int level, const void* const* in
     a.H = g.H[level];
     a.W = g.W[level];
     a.mode = kFlowSame;
-    e = launch_iter(g.elem(level), a, g.R, s);
+    e = launch_iter(g.elem(level), a, g.R, g.nb[level], s);
   } else {
     return set_error("unknown stage"), OF_EINVAL;
   }

@@ -1,0 +1,107 @@
+"""The batched form (one launch per phase over many pairs) against the per-pair path and
+the oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import announce, dev, flow_error, report, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _pairs(sizes, seed_item=0):
+    out = []
+    for H, W, I1, I2, _, _ in synth.batch_items(len(sizes), sizes=sizes):
+        out.append((I1, I2))
+    return out
+
+
+SIZES = [(96, 130), (200, 170), (64, 64), (257, 190), (130, 96)]
+
+
+def test_batch_equals_per_pair_bitwise_and_oracle(gpu_lib):
+    import torch
+    ofmi = gpu_lib
+    pairs = _pairs(SIZES)
+    d1 = [to_dev(p[0]) for p in pairs]
+    d2 = [to_dev(p[1]) for p in pairs]
+    announce(f"batch {SIZES} L=3 r=4 K=3")
+    b = ofmi.Batch(SIZES, 3, 4, 3, device=dev())
+    us, vs = b.compute(d1, d2)
+    torch.cuda.synchronize()
+    for i, (H, W) in enumerate(SIZES):
+        plan = ofmi.Plan(H, W, 3, 4, 3, device=dev())
+        u, v = plan.compute(d1[i], d2[i])
+        torch.cuda.synchronize()
+        assert np.array_equal(us[i].cpu().numpy(), u.cpu().numpy()), f"pair {i} u"
+        assert np.array_equal(vs[i].cpu().numpy(), v.cpu().numpy()), f"pair {i} v"
+        plan.close()
+        ou, ov = oracle.flow(pairs[i][0], pairs[i][1], 3, 4, 3)
+        d = flow_error(us[i].cpu().numpy(), vs[i].cpu().numpy(), ou, ov)
+        assert d.max() <= 1e-3, report(d, 1e-3)
+    b.close()
+
+
+def test_batch_graph_replays_and_configs(gpu_lib):
+    import torch
+    ofmi = gpu_lib
+    pairs = _pairs(SIZES)
+    d1 = [to_dev(p[0]) for p in pairs]
+    d2 = [to_dev(p[1]) for p in pairs]
+    eager = ofmi.Batch(SIZES, 3, 4, 3, device=dev(), graph=False)
+    ue, ve = eager.compute(d1, d2)
+    torch.cuda.synchronize()
+    ref = [(u.cpu().numpy(), v.cpu().numpy()) for u, v in zip(ue, ve)]
+    g = ofmi.Batch(SIZES, 3, 4, 3, device=dev(), graph=True)
+    us, vs = g.outputs()
+    announce("batch graph replays x3")
+    for rep in range(3):
+        for t in us + vs:
+            t.fill_(float("nan"))
+        g.compute(d1, d2, us, vs)
+        eager.compute(d2, d1)
+        torch.cuda.synchronize()
+        for i in range(len(SIZES)):
+            assert np.array_equal(us[i].cpu().numpy(), ref[i][0]), (rep, i)
+            assert np.array_equal(vs[i].cpu().numpy(), ref[i][1]), (rep, i)
+    # other tile heights / persistent grids give the same bits
+    for bands, grid in [([1, 1, 1], [0, 0, 0]), ([2, 4, 8], [256, 512, 8])]:
+        announce(f"batch config bands={bands} grid={grid}")
+        g.set_config({"bands": bands, "grid": grid})
+        g.compute(d1, d2, us, vs)
+        torch.cuda.synchronize()
+        for i in range(len(SIZES)):
+            assert np.array_equal(us[i].cpu().numpy(), ref[i][0]), (bands, grid, i)
+            assert np.array_equal(vs[i].cpu().numpy(), ref[i][1]), (bands, grid, i)
+    announce("batch autotune")
+    cfg = g.autotune(d1, d2, us, vs, reps=1)
+    assert len(cfg["bands"]) == 3
+    g.compute(d1, d2, us, vs)
+    torch.cuda.synchronize()
+    for i in range(len(SIZES)):
+        assert np.array_equal(us[i].cpu().numpy(), ref[i][0]), ("autotuned", i)
+    g.close()
+    eager.close()
+
+
+def test_batch_fp16_and_zero_iterations(gpu_lib):
+    import torch
+    ofmi = gpu_lib
+    pairs = _pairs(SIZES[:3])
+    d1 = [to_dev(p[0]) for p in pairs]
+    d2 = [to_dev(p[1]) for p in pairs]
+    announce("batch fp16 r=8 L=2 K=2")
+    b = ofmi.Batch(SIZES[:3], 2, 8, 2, fp16=True, device=dev())
+    us, vs = b.compute(d1, d2)
+    torch.cuda.synchronize()
+    for i in range(3):
+        ou, ov = oracle.flow(pairs[i][0], pairs[i][1], 2, 8, 2)
+        d = flow_error(us[i].cpu().numpy(), vs[i].cpu().numpy(), ou, ov)
+        assert d.max() <= 2e-2, report(d, 2e-2)
+    b.close()
+    b0 = ofmi.Batch(SIZES[:2], 2, 4, 0, device=dev())
+    us, vs = b0.compute(d1[:2], d2[:2])
+    torch.cuda.synchronize()
+    assert all(np.all(t.cpu().numpy() == 0) for t in us + vs)
+    b0.close()

@@ -184,3 +184,30 @@ def test_repeat_run_bitwise(gpu_lib):
     a = gpu_flow(gpu_lib, I1, I2, 3, 4, 4)
     b = gpu_flow(gpu_lib, I1, I2, 3, 4, 4)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_graph_replay_matches_eager(gpu_lib):
+    """Replays of the captured schedule equal eager launches bitwise, replay after replay,
+    with eager work and synchronisations in between."""
+    import torch
+    ofmi = gpu_lib
+    I1, I2, _, _ = synth.make_pair("c1", 9)
+    d1, d2 = to_dev(I1), to_dev(I2)
+    eager = ofmi.Plan(256, 256, 3, 4, 4, device=dev(), graph=False)
+    graph = ofmi.Plan(256, 256, 3, 4, 4, device=dev(), graph=True)
+    ue, ve = eager.compute(d1, d2)
+    torch.cuda.synchronize()
+    ref_u, ref_v = ue.cpu().numpy(), ve.cpu().numpy()
+    ug = torch.empty_like(ue)
+    vg = torch.empty_like(ve)
+    announce("graph replay x4 vs eager")
+    for rep in range(4):
+        ug.fill_(float("nan"))
+        vg.fill_(float("nan"))
+        graph.compute(d1, d2, ug, vg)
+        eager.compute(d2, d1)                 # eager work between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(ug.cpu().numpy(), ref_u), f"replay {rep}"
+        assert np.array_equal(vg.cpu().numpy(), ref_v), f"replay {rep}"
+    eager.close()
+    graph.close()
