@@ -177,6 +177,58 @@ OF_API of_status of_batch_read_timing(of_batch* b, int kernel, double* total_ms,
 /* Releases the batch (synchronises the device first).  NULL-safe. */
 OF_API void of_batch_destroy(of_batch* b);
 
+/* --------------------------------------------------------------------- serving form
+ * Frame streams (e.g. a camera sequence) processed pair by pair: each stream is a session that
+ * keeps its previous frame's pyramid resident on the device, so a new frame costs one new
+ * pyramid plus the iterations (the paper's first computing scheme, Sec. 2.4: "each field
+ * computation requires only one image to be processed").  A server holds the sessions of one
+ * parameter set, admits new streams against an HBM budget, and pushes the new frames of many
+ * streams together (one launch per pyramid step and per (level, iteration) phase over all of
+ * their tiles).  Pushes of one server must be ordered on one stream; the server is internally
+ * locked, so concurrent calls from several threads serialise. */
+typedef struct of_server of_server;
+typedef struct of_session of_session;
+
+/* Device bytes one session of an H x W stream keeps resident (two frame pyramids including
+ * level 0, four level-0 FP32 field planes); 0 on invalid parameters. */
+OF_API size_t of_session_bytes(int H, int W, int levels, int radius, int iters, unsigned flags);
+
+/* Server for streams sharing levels, radius, iters and flags (OF_FLAG_NO_GRAPH ignored).
+ * hbm_budget_bytes bounds the resident bytes of all open sessions (0 = unbounded). */
+OF_API of_server* of_server_create(int levels, int radius, int iters, unsigned flags,
+                                   size_t hbm_budget_bytes);
+
+/* Opens a session for an H x W stream.  Returns NULL (of_last_error says why) when the
+ * parameters are invalid, when admitting it would exceed the HBM budget, or on allocation
+ * failure.  The session memory is allocated here (hipMalloc). */
+OF_API of_session* of_server_open(of_server* s, int H, int W);
+
+/* Pushes the next frame of each of n distinct sessions of server s (host arrays of n
+ * entries; frames[i] a device plane of session i's size and the server's frame type).  For a
+ * session that already holds a frame, u[i], v[i] (device float32 planes) receive the flow
+ * from its previous frame to frames[i] and has_flow[i] = 1; for a session's first frame only
+ * its pyramid is built, u[i], v[i] are not touched (may be NULL) and has_flow[i] = 0.
+ * frames[i] may be reused by the caller once the push's work on `stream` has completed.
+ * Errors: OF_EINVAL (nothing enqueued) for NULL arguments, a session of another server or a
+ * session listed twice; OF_EHIP on launch failure. */
+OF_API of_status of_server_push(of_server* s, of_session* const* sessions, int n,
+                                const void* const* frames, float* const* u, float* const* v,
+                                int* has_flow, void* stream);
+
+/* of_server_push for one session. */
+OF_API of_status of_session_push(of_session* session, const void* frame, float* u, float* v,
+                                 void* stream, int* has_flow);
+
+/* Resident bytes of one session / of all open sessions of a server. */
+OF_API size_t of_session_resident_bytes(const of_session* session);
+OF_API size_t of_server_resident_bytes(const of_server* s);
+
+/* Closes one session (synchronises the device, frees its memory, returns its budget). */
+OF_API of_status of_server_close(of_server* s, of_session* session);
+
+/* Destroys the server and every session still open.  NULL-safe. */
+OF_API void of_server_destroy(of_server* s);
+
 /* --------------------------------------------------------------------- stage entry points
  * One step of the method on caller buffers, for stage-by-stage checking.
  *   OF_STAGE_REDUCE:  one pyramid reduction (Sec. 2.4, factor 4 in area): in[0] is a level-`level`

@@ -44,6 +44,15 @@ SIGNATURES = {
                                       ctypes.POINTER(ctypes.c_longlong),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "of_batch_destroy": (None, [_vp]),
+    "of_session_bytes": (_c_size, [_c_int, _c_int, _c_int, _c_int, _c_int, _c_uint]),
+    "of_server_create": (_vp, [_c_int, _c_int, _c_int, _c_uint, _c_size]),
+    "of_server_open": (_vp, [_vp, _c_int, _c_int]),
+    "of_server_push": (_c_int, [_vp, _VPP, _c_int, _VPP, _VPP, _VPP, _INTP, _vp]),
+    "of_session_push": (_c_int, [_vp, _vp, _vp, _vp, _vp, _INTP]),
+    "of_session_resident_bytes": (_c_size, [_vp]),
+    "of_server_resident_bytes": (_c_size, [_vp]),
+    "of_server_close": (_c_int, [_vp, _vp]),
+    "of_server_destroy": (None, [_vp]),
     "of_plan_set_timing": (_c_int, [_vp, _c_int]),
     "of_plan_read_timing": (_c_int, [_vp, _c_int, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_longlong),

@@ -1,0 +1,375 @@
+// Serving form: frame streams whose previous frame's pyramid stays resident on the device, so
+// each new pair builds one new pyramid (the paper's first computing scheme, Sec. 2.4: each
+// field needs only one new image processed).  A server admits streams against an HBM budget
+// and pushes the new frames of many streams together: one batched launch per pyramid step
+// and per (level, iteration) phase over the tiles of every stream in the push.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ofmi.h"
+#include "kernels.h"
+#include "runtime.h"
+
+using namespace ofmi;
+
+namespace {
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) hipSetDevice(prev);
+  }
+};
+
+of_status hip_fail(const char* what, hipError_t e) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return OF_EHIP;
+}
+
+}  // namespace
+
+struct of_server;
+
+struct of_session {
+  of_server* server = nullptr;
+  int H = 0, W = 0;
+  Geometry g;                     // level sizes; flow offsets are relative to `flow`
+  char* mem = nullptr;            // slots and flow planes (server allocation)
+  size_t bytes = 0;
+  size_t slot_off[2][OF_MAX_LEVELS];  // pyramid planes of the two frame slots
+  char* flow = nullptr;           // four level-0 FP32 planes
+  int cur = 0;                    // slot that receives the next frame
+  bool has_prev = false;
+  bool closed = false;
+};
+
+struct of_server {
+  int L = 0, R = 0, K = 0;
+  unsigned flags = 0;
+  int device = 0;
+  size_t budget = 0;
+  size_t resident = 0;
+  std::vector<of_session*> sessions;
+  // per-push argument block (grown on demand) and its pinned staging
+  char* blk = nullptr;
+  size_t blk_bytes = 0;
+  char* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t staged = nullptr;
+  bool staged_pending = false;
+  std::mutex mu;
+};
+
+namespace {
+
+size_t session_bytes(int H, int W, int L, int R, int K, unsigned flags, Geometry* gout,
+                     size_t slot_off[2][OF_MAX_LEVELS], size_t* flow_off) {
+  Geometry g = make_geometry(H, W, L, R, K, flags);
+  size_t off = 0;
+  for (int s = 0; s < 2; ++s)
+    for (int l = 0; l < L; ++l) {
+      if (slot_off) slot_off[s][l] = off;
+      off += align256((size_t)g.H[l] * g.W[l] * elem_bytes(g.elem(l)));
+    }
+  if (flow_off) *flow_off = off;
+  off += 4 * align256((size_t)H * W * sizeof(float));
+  if (gout) *gout = g;
+  return off;
+}
+
+// Host-side description of one push, packed into one argument block.
+struct Push {
+  std::vector<std::vector<ReduceJob>> jobs;   // per output level 1..L-1
+  std::vector<std::vector<int2>> items;
+  std::vector<std::vector<IterArgs>> args;    // per phase, one per flowing session
+  std::vector<std::vector<int4>> tiles;       // per level, over flowing sessions
+  size_t bytes = 0;
+  std::vector<size_t> off_jobs, off_items, off_args, off_tiles;
+};
+
+void layout(Push& p) {
+  size_t off = 0;
+  auto put = [&](size_t n) {
+    const size_t o = off;
+    off += align256(n);
+    return o;
+  };
+  for (auto& j : p.jobs) p.off_jobs.push_back(put(j.size() * sizeof(ReduceJob)));
+  for (auto& i : p.items) p.off_items.push_back(put(i.size() * sizeof(int2)));
+  for (auto& a : p.args) p.off_args.push_back(put(a.size() * sizeof(IterArgs)));
+  for (auto& t : p.tiles) p.off_tiles.push_back(put(t.size() * sizeof(int4)));
+  p.bytes = off;
+}
+
+void pack(const Push& p, char* dst) {
+  for (size_t i = 0; i < p.jobs.size(); ++i)
+    memcpy(dst + p.off_jobs[i], p.jobs[i].data(), p.jobs[i].size() * sizeof(ReduceJob));
+  for (size_t i = 0; i < p.items.size(); ++i)
+    memcpy(dst + p.off_items[i], p.items[i].data(), p.items[i].size() * sizeof(int2));
+  for (size_t i = 0; i < p.args.size(); ++i)
+    memcpy(dst + p.off_args[i], p.args[i].data(), p.args[i].size() * sizeof(IterArgs));
+  for (size_t i = 0; i < p.tiles.size(); ++i)
+    memcpy(dst + p.off_tiles[i], p.tiles[i].data(), p.tiles[i].size() * sizeof(int4));
+}
+
+// Tile height (bands) of a push level: taller tiles when many pixels fill the device.
+int push_bands(long long px) { return px >= (24ll << 20) ? 4 : (px >= (4ll << 20) ? 2 : 1); }
+
+}  // namespace
+
+extern "C" {
+
+size_t of_session_bytes(int H, int W, int levels, int radius, int iters, unsigned flags) {
+  if (!check_params(H, W, levels, radius, iters, flags)) return 0;
+  return session_bytes(H, W, levels, radius, iters, flags, nullptr, nullptr, nullptr);
+}
+
+of_server* of_server_create(int levels, int radius, int iters, unsigned flags,
+                            size_t hbm_budget_bytes) {
+  if (flags & OF_FLAG_NO_GRAPH) flags &= ~OF_FLAG_NO_GRAPH;
+  if (!check_params(1 << (levels > 0 ? levels - 1 : 0), 1 << (levels > 0 ? levels - 1 : 0), levels,
+                    radius, iters, flags))
+    return nullptr;
+  of_server* s = new of_server();
+  s->L = levels;
+  s->R = radius;
+  s->K = iters;
+  s->flags = flags;
+  s->budget = hbm_budget_bytes;
+  hipError_t e = hipGetDevice(&s->device);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->staged, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    hip_fail("server set-up", e);
+    delete s;
+    return nullptr;
+  }
+  return s;
+}
+
+size_t of_server_resident_bytes(const of_server* s) { return s ? s->resident : 0; }
+
+of_session* of_server_open(of_server* s, int H, int W) {
+  if (!s) return set_error("NULL server"), nullptr;
+  if (!check_params(H, W, s->L, s->R, s->K, s->flags)) return nullptr;
+  std::lock_guard<std::mutex> lock(s->mu);
+  of_session* ss = new of_session();
+  size_t flow_off = 0;
+  ss->bytes = session_bytes(H, W, s->L, s->R, s->K, s->flags, &ss->g, ss->slot_off, &flow_off);
+  if (s->budget && s->resident + ss->bytes > s->budget) {
+    set_error("HBM budget exceeded: stream needs " + std::to_string(ss->bytes) + " bytes, " +
+              std::to_string(s->budget - s->resident) + " left");
+    delete ss;
+    return nullptr;
+  }
+  DeviceGuard guard(s->device);
+  hipError_t e = hipMalloc((void**)&ss->mem, ss->bytes);
+  if (e != hipSuccess) {
+    hip_fail("hipMalloc(session)", e);
+    delete ss;
+    return nullptr;
+  }
+  ss->server = s;
+  ss->H = H;
+  ss->W = W;
+  ss->flow = ss->mem + flow_off;
+  s->resident += ss->bytes;
+  s->sessions.push_back(ss);
+  return ss;
+}
+
+size_t of_session_resident_bytes(const of_session* ss) { return ss ? ss->bytes : 0; }
+
+of_status of_server_close(of_server* s, of_session* ss) {
+  if (!s || !ss || ss->server != s) return set_error("bad server or session"), OF_EINVAL;
+  std::lock_guard<std::mutex> lock(s->mu);
+  DeviceGuard guard(s->device);
+  hipDeviceSynchronize();
+  hipFree(ss->mem);
+  s->resident -= ss->bytes;
+  s->sessions.erase(std::remove(s->sessions.begin(), s->sessions.end(), ss), s->sessions.end());
+  delete ss;
+  return OF_OK;
+}
+
+of_status of_server_push(of_server* s, of_session* const* ss, int n, const void* const* frames,
+                         float* const* u, float* const* v, int* has_flow, void* stream) {
+  if (!s || !ss || !frames || !u || !v || !has_flow) return set_error("NULL argument"), OF_EINVAL;
+  if (n < 1) return set_error("n must be >= 1"), OF_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!ss[i] || ss[i]->server != s) return set_error("session of another server"), OF_EINVAL;
+    if (!frames[i]) return set_error("NULL frame"), OF_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (ss[j] == ss[i]) return set_error("a session appears twice in one push"), OF_EINVAL;
+    if (ss[i]->has_prev && (!u[i] || !v[i] || u[i] == v[i] || (((uintptr_t)u[i] | (uintptr_t)v[i]) & 3)))
+      return set_error("bad output planes"), OF_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(s->mu);
+  DeviceGuard guard(s->device);
+  hipStream_t st = (hipStream_t)stream;
+  const int L = s->L, K = s->K, R = s->R;
+  const Geometry& gg = ss[0]->g;
+  hipError_t e = hipSuccess;
+  // 1. new frames into their slots (level 0)
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    of_session* x = ss[i];
+    e = hipMemcpyAsync(x->mem + x->slot_off[x->cur][0], frames[i],
+                       (size_t)x->H * x->W * elem_bytes(x->g.e0), hipMemcpyDeviceToDevice, st);
+  }
+  if (e != hipSuccess) return hip_fail("frame copy", e);
+  // 2. describe the push
+  Push p;
+  p.jobs.resize(L > 1 ? L - 1 : 0);
+  p.items.resize(L > 1 ? L - 1 : 0);
+  for (int l = 1; l < L; ++l)
+    for (int i = 0; i < n; ++i) {
+      of_session* x = ss[i];
+      const int job = (int)p.jobs[l - 1].size();
+      p.jobs[l - 1].push_back({x->mem + x->slot_off[x->cur][l - 1], x->mem + x->slot_off[x->cur][l],
+                               x->g.H[l - 1], x->g.W[l - 1], x->g.H[l], x->g.W[l]});
+      const int blocks = ((x->g.W[l] + 63) / 64) * ((x->g.H[l] + 3) / 4);
+      for (int k = 0; k < blocks; ++k) p.items[l - 1].push_back(make_int2(job, k));
+    }
+  std::vector<int> flowing;
+  for (int i = 0; i < n; ++i)
+    if (ss[i]->has_prev && K > 0) flowing.push_back(i);
+  const int TW = strip_width_for(R), N = 2 * R + 1;
+  p.args.resize((size_t)L * (K > 0 ? K : 0));
+  p.tiles.resize(L);
+  for (int l = L - 1; l >= 0; --l) {
+    long long px = 0;
+    for (int i : flowing) px += (long long)ss[i]->g.H[l] * ss[i]->g.W[l];
+    const int TH = N * push_bands(px);
+    for (int q = 0; q < (int)flowing.size(); ++q) {
+      const of_session* x = ss[flowing[q]];
+      const int tx = (x->g.W[l] + TW - 1) / TW, ty = (x->g.H[l] + TH - 1) / TH;
+      for (int yy = 0; yy < ty; ++yy)
+        for (int xx = 0; xx < tx; ++xx) p.tiles[l].push_back(make_int4(q, xx, yy, TH));
+    }
+  }
+  for (int q = 0; q < (int)flowing.size(); ++q) {
+    const int i = flowing[q];
+    of_session* x = ss[i];
+    const int prev = x->cur ^ 1;
+    float* fu[2] = {(float*)(x->flow), (float*)(x->flow + align256((size_t)x->H * x->W * 4))};
+    float* fv[2] = {(float*)(x->flow + 2 * align256((size_t)x->H * x->W * 4)),
+                    (float*)(x->flow + 3 * align256((size_t)x->H * x->W * 4))};
+    const float* cu = nullptr;
+    const float* cv = nullptr;
+    int cH = 0, cW = 0, buf = 0, phase = 0;
+    for (int l = L - 1; l >= 0; --l)
+      for (int k = 0; k < K; ++k, ++phase) {
+        IterArgs a{};
+        a.I1 = x->mem + x->slot_off[prev][l];
+        a.I2 = x->mem + x->slot_off[x->cur][l];
+        a.H = x->g.H[l];
+        a.W = x->g.W[l];
+        a.uin = cu;
+        a.vin = cv;
+        a.Hc = cH;
+        a.Wc = cW;
+        a.mode = k > 0 ? kFlowSame : (l == L - 1 ? kFlowZero : kFlowCoarse);
+        const bool last = (l == 0 && k == K - 1);
+        a.uout = last ? u[i] : fu[buf];
+        a.vout = last ? v[i] : fv[buf];
+        p.args[phase].push_back(a);
+        cu = a.uout;
+        cv = a.vout;
+        cH = a.H;
+        cW = a.W;
+        buf ^= 1;
+      }
+  }
+  layout(p);
+  // 3. upload through pinned staging (wait until the previous push consumed it)
+  if (s->staged_pending) {
+    e = hipEventSynchronize(s->staged);
+    if (e != hipSuccess) return hip_fail("staging wait", e);
+    s->staged_pending = false;
+  }
+  if (p.bytes > s->pinned_bytes) {
+    if (s->pinned) hipHostFree(s->pinned);
+    s->pinned = nullptr;
+    e = hipHostMalloc((void**)&s->pinned, p.bytes * 2, hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail("hipHostMalloc(staging)", e);
+    s->pinned_bytes = p.bytes * 2;
+  }
+  if (p.bytes > s->blk_bytes) {
+    // The old block may still be read by earlier pushes on this stream.
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail("stream sync", e);
+    if (s->blk) hipFree(s->blk);
+    s->blk = nullptr;
+    e = hipMalloc((void**)&s->blk, p.bytes * 2);
+    if (e != hipSuccess) return hip_fail("hipMalloc(arguments)", e);
+    s->blk_bytes = p.bytes * 2;
+  }
+  pack(p, s->pinned);
+  e = hipMemcpyAsync(s->blk, s->pinned, p.bytes, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipEventRecord(s->staged, st);
+  if (e != hipSuccess) return hip_fail("argument upload", e);
+  s->staged_pending = true;
+  // 4. new pyramids, then the iterations of the flowing sessions
+  for (int l = 1; l < L && e == hipSuccess; ++l) {
+    const int ni = (int)p.items[l - 1].size();
+    e = launch_reduce_batch(gg.elem(l - 1), gg.ep, (const ReduceJob*)(s->blk + p.off_jobs[l - 1]),
+                            (const int2*)(s->blk + p.off_items[l - 1]), ni, std::min(ni, 8192), st);
+  }
+  int phase = 0;
+  for (int l = L - 1; l >= 0 && e == hipSuccess && !flowing.empty(); --l)
+    for (int k = 0; k < K && e == hipSuccess; ++k, ++phase) {
+      BatchLaunch bl;
+      bl.args = (const IterArgs*)(s->blk + p.off_args[phase]);
+      bl.tiles = (const int4*)(s->blk + p.off_tiles[l]);
+      bl.ntiles = (int)p.tiles[l].size();
+      bl.grid = (bl.ntiles + 7) / 8 * 8;
+      const int mode = k > 0 ? kFlowSame : (l == L - 1 ? kFlowZero : kFlowCoarse);
+      e = launch_iter_batch(gg.elem(l), bl, R, mode, st);
+    }
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    of_session* x = ss[i];
+    if (x->has_prev && K == 0) e = launch_zero(u[i], v[i], (size_t)x->H * x->W, st);
+  }
+  if (e != hipSuccess) return hip_fail("push launch", e);
+  // 5. the new frame becomes the previous one
+  for (int i = 0; i < n; ++i) {
+    of_session* x = ss[i];
+    has_flow[i] = x->has_prev ? 1 : 0;
+    x->has_prev = true;
+    x->cur ^= 1;
+  }
+  return OF_OK;
+}
+
+of_status of_session_push(of_session* ss, const void* frame, float* u, float* v, void* stream,
+                          int* has_flow) {
+  if (!ss) return set_error("NULL session"), OF_EINVAL;
+  return of_server_push(ss->server, &ss, 1, &frame, &u, &v, has_flow, stream);
+}
+
+void of_server_destroy(of_server* s) {
+  if (!s) return;
+  DeviceGuard guard(s->device);
+  hipDeviceSynchronize();
+  for (of_session* ss : s->sessions) {
+    hipFree(ss->mem);
+    delete ss;
+  }
+  if (s->blk) hipFree(s->blk);
+  if (s->pinned) hipHostFree(s->pinned);
+  if (s->staged) hipEventDestroy(s->staged);
+  delete s;
+}
+
+}  // extern "C"

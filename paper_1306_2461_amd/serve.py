@@ -1,0 +1,308 @@
+"""Serving loop: frame-stream requests, admission by HBM budget, continuous batching.
+
+Frames of many streams arrive over time (the paper's real-time setting, Sec. 2.2 and Sec. 2.4:
+each new camera frame yields one field).  ``Server`` keeps a queue of requests; every
+``step`` takes the oldest pending frame of each admitted stream (at most one frame per stream
+per push, so a stream's frames stay in order) and launches them together through an executor.
+Requests that arrive while earlier pushes run on the device join the next push (continuous
+batching); their work overlaps on the device stream.  Streams are admitted when their
+resident memory fits the HBM budget; a stream that can never fit is rejected.  Completion is
+observed by polling the pushes' events; each request records arrival and completion times.
+
+Executors implement ``open(H, W) -> handle`` (raising ``BudgetExceeded``),
+``session_bytes(H, W)``, ``budget``, ``close(handle)``, ``submit([(handle, frame)]) -> token``,
+``ready(token) -> bool`` and ``finish(token) -> [(u, v, has_flow)]``.  ``GpuExecutor`` runs the
+HIP library (``of_server_*``).
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Any
+
+import numpy as np
+
+
+class BudgetExceeded(RuntimeError):
+    """Opening a stream would exceed the executor's HBM budget."""
+
+
+@dataclasses.dataclass
+class Request:
+    stream_id: int
+    frame: Any
+    t_arrival: float
+    t_launch: float | None = None
+    t_done: float | None = None
+    has_flow: bool | None = None
+    u: Any = None
+    v: Any = None
+    error: str | None = None
+
+    @property
+    def latency(self):
+        return None if self.t_done is None else self.t_done - self.t_arrival
+
+
+class Server:
+    """Continuous-batching request loop over an executor."""
+
+    def __init__(self, executor, max_batch: int = 64, clock=time.perf_counter):
+        self.ex = executor
+        self.max_batch = max_batch
+        self.clock = clock
+        self.pending: collections.deque[Request] = collections.deque()
+        self.inflight: collections.deque = collections.deque()
+        self.sessions: dict[int, Any] = {}
+        self.sizes: dict[int, tuple] = {}
+        self.done: list[Request] = []
+        self.rejected: list[Request] = []
+        self.admission_log: list[tuple] = []
+
+    # ------------------------------------------------------------------ requests
+    def submit(self, stream_id: int, frame, t_arrival: float | None = None) -> Request:
+        shape = tuple(frame.shape)
+        if stream_id in self.sizes and self.sizes[stream_id] != shape:
+            req = Request(stream_id, frame, self.clock() if t_arrival is None else t_arrival)
+            req.error = f"frame size {shape} differs from the stream's {self.sizes[stream_id]}"
+            self.rejected.append(req)
+            return req
+        self.sizes.setdefault(stream_id, shape)
+        req = Request(stream_id, frame, self.clock() if t_arrival is None else t_arrival)
+        self.pending.append(req)
+        return req
+
+    def close_stream(self, stream_id: int):
+        """Closes a stream's session once its pushes are done; frees its budget."""
+        self.drain(stream_id)
+        h = self.sessions.pop(stream_id, None)
+        if h is not None:
+            self.ex.close(h)
+            self.admission_log.append((self.clock(), "close", stream_id))
+
+    # ------------------------------------------------------------------ loop
+    def _admit(self, req: Request):
+        h = self.sessions.get(req.stream_id)
+        if h is not None:
+            return h
+        H, W = req.frame.shape
+        need = self.ex.session_bytes(H, W)
+        if self.ex.budget and need > self.ex.budget:
+            req.error = f"stream needs {need} bytes, more than the whole budget {self.ex.budget}"
+            return "reject"
+        try:
+            h = self.ex.open(H, W)
+        except BudgetExceeded:
+            return None
+        self.sessions[req.stream_id] = h
+        self.admission_log.append((self.clock(), "open", req.stream_id))
+        return h
+
+    def step(self) -> int:
+        """Launch one push with the oldest pending frame of every admitted stream."""
+        batch, seen, keep = [], set(), collections.deque()
+        while self.pending:
+            req = self.pending.popleft()
+            if req.stream_id in seen or len(batch) >= self.max_batch:
+                keep.append(req)
+                continue
+            h = self._admit(req)
+            if h == "reject":
+                self.rejected.append(req)
+                continue
+            seen.add(req.stream_id)          # later frames of this stream wait for a later push
+            if h is None:
+                keep.append(req)             # waits for budget
+                continue
+            batch.append((h, req))
+        self.pending = keep
+        if not batch:
+            return 0
+        t = self.clock()
+        for _, r in batch:
+            r.t_launch = t
+        token = self.ex.submit([(h, r.frame) for h, r in batch])
+        self.inflight.append((token, [r for _, r in batch]))
+        return len(batch)
+
+    def poll(self) -> int:
+        """Complete finished pushes in launch order; returns the number completed."""
+        n = 0
+        while self.inflight and self.ex.ready(self.inflight[0][0]):
+            token, reqs = self.inflight.popleft()
+            t = self.clock()
+            for r, (u, v, has) in zip(reqs, self.ex.finish(token)):
+                r.t_done, r.u, r.v, r.has_flow = t, u, v, bool(has)
+                self.done.append(r)
+                n += 1
+        return n
+
+    def drain(self, stream_id: int | None = None):
+        """Run until no request (of `stream_id`, or at all) is pending or in flight."""
+        def busy():
+            if stream_id is None:
+                return bool(self.pending or self.inflight)
+            return any(r.stream_id == stream_id for r in self.pending) or any(
+                r.stream_id == stream_id for _, rs in self.inflight for r in rs)
+        while busy():
+            launched = self.step()
+            if not self.poll() and not launched:
+                if self.inflight:
+                    self.ex.wait(self.inflight[0][0])
+                elif self.pending:
+                    raise RuntimeError("pending requests cannot be admitted (HBM budget)")
+
+    def replay(self, arrivals, realtime: bool = True):
+        """Serve (t, stream_id, frame) arrivals (sorted by t), optionally paced in real time.
+
+        Returns per-pair latency percentiles and throughput over the flows computed."""
+        t0 = self.clock()
+        i = 0
+        while i < len(arrivals) or self.pending or self.inflight:
+            now = self.clock() - t0
+            while i < len(arrivals) and (not realtime or arrivals[i][0] <= now):
+                ta, sid, frame = arrivals[i]
+                self.submit(sid, frame, t0 + ta if realtime else self.clock())
+                i += 1
+            launched = self.step() if self.pending else 0
+            completed = self.poll()
+            if not launched and not completed:
+                if self.inflight and (i >= len(arrivals) or not realtime):
+                    self.ex.wait(self.inflight[0][0])
+                elif realtime and i < len(arrivals):
+                    time.sleep(max(0.0, min(2e-4, arrivals[i][0] - (self.clock() - t0))))
+                elif self.pending and not self.inflight:
+                    raise RuntimeError("pending requests cannot be admitted (HBM budget)")
+        return self.stats()
+
+    def stats(self):
+        flows = [r for r in self.done if r.has_flow]
+        lat = sorted(r.latency for r in flows)
+        out = {"requests": len(self.done), "flows": len(flows), "rejected": len(self.rejected)}
+        if lat:
+            out["p50_ms"] = 1e3 * lat[len(lat) // 2]
+            out["p99_ms"] = 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))]
+            t_first = min(r.t_arrival for r in self.done)
+            t_last = max(r.t_done for r in flows)
+            out["pairs_per_s"] = len(flows) / max(t_last - t_first, 1e-9)
+        return out
+
+
+class GpuExecutor:
+    """Executor over the HIP server ABI (``of_server_*``) on one device stream."""
+
+    def __init__(self, levels, radius, iters, fp16=False, budget_bytes=0, device=None,
+                 keep_on_device=True):
+        import torch
+
+        from . import _binding as B
+        self.torch = torch
+        self.B = B
+        self.lib = B.load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.levels, self.radius, self.iters = levels, radius, iters
+        self.flags = B.OF_FLAG_FP16_STORAGE if fp16 else 0
+        self.budget = int(budget_bytes)
+        self.keep_on_device = keep_on_device
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.Stream(self.device)
+            h = self.lib.of_server_create(levels, radius, iters, self.flags, self.budget)
+        if not h:
+            raise B.OfError(f"of_server_create failed: {B.last_error()}")
+        self._h = h
+        self._pinned: dict[tuple, list] = collections.defaultdict(list)
+
+    def session_bytes(self, H, W):
+        return int(self.lib.of_session_bytes(H, W, self.levels, self.radius, self.iters, self.flags))
+
+    def open(self, H, W):
+        with self.torch.cuda.device(self.device):
+            s = self.lib.of_server_open(self._h, H, W)
+        if not s:
+            msg = self.B.last_error()
+            if "budget" in msg:
+                raise BudgetExceeded(msg)
+            raise self.B.OfError(f"of_server_open failed: {msg}")
+        return s
+
+    def close(self, handle):
+        self.B.check(self.lib.of_server_close(self._h, handle), "of_server_close")
+
+    def resident_bytes(self):
+        return int(self.lib.of_server_resident_bytes(self._h))
+
+    def _host_buffer(self, shape):
+        pool = self._pinned[shape]
+        if pool:
+            return pool.pop()
+        return self.torch.empty(shape, dtype=self.torch.uint8, pin_memory=True)
+
+    def submit(self, items):
+        import ctypes
+        torch = self.torch
+        n = len(items)
+        frames_host, frames_dev, us, vs = [], [], [], []
+        with torch.cuda.stream(self.stream):
+            for _, f in items:
+                hb = self._host_buffer(tuple(f.shape))
+                hb.numpy()[...] = f
+                frames_host.append(hb)
+                frames_dev.append(hb.to(self.device, non_blocking=True))
+                us.append(torch.empty(tuple(f.shape), dtype=torch.float32, device=self.device))
+                vs.append(torch.empty(tuple(f.shape), dtype=torch.float32, device=self.device))
+        sess = (ctypes.c_void_p * n)(*[h for h, _ in items])
+        pf, _a = self.B.ptr_array([t.data_ptr() for t in frames_dev])
+        pu, _b = self.B.ptr_array([t.data_ptr() for t in us])
+        pv, _c = self.B.ptr_array([t.data_ptr() for t in vs])
+        has = (ctypes.c_int * n)()
+        st = self.lib.of_server_push(self._h, ctypes.cast(sess, self.B._VPP), n, pf, pu, pv, has,
+                                     self.stream.cuda_stream)
+        self.B.check(st, "of_server_push")
+        ev = torch.cuda.Event()
+        ev.record(self.stream)
+        return {"event": ev, "us": us, "vs": vs, "has": list(has), "keep": (frames_host, frames_dev)}
+
+    def ready(self, token):
+        return token["event"].query()
+
+    def wait(self, token):
+        token["event"].synchronize()
+
+    def finish(self, token):
+        for hb in token["keep"][0]:
+            self._pinned[tuple(hb.shape)].append(hb)
+        out = []
+        for u, v, has in zip(token["us"], token["vs"], token["has"]):
+            if not has:
+                out.append((None, None, 0))
+            elif self.keep_on_device:
+                out.append((u, v, 1))
+            else:
+                out.append((u.cpu().numpy(), v.cpu().numpy(), 1))
+        return out
+
+    def close_all(self):
+        if getattr(self, "_h", None):
+            self.lib.of_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close_all()
+        except Exception:
+            pass
+
+
+def poisson_arrivals(streams, rate_per_stream: float, seed: int = 2461):
+    """Merge per-stream frame lists into (t, stream, frame) arrivals, each stream an
+    independent Poisson process of the given rate (frames of a stream keep their order)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for sid, frames in enumerate(streams):
+        t = 0.0
+        for f in frames:
+            t += rng.exponential(1.0 / rate_per_stream)
+            out.append((t, sid, f))
+    out.sort(key=lambda a: a[0])
+    return out

@@ -1,0 +1,107 @@
+"""Serving loop logic on the CPU with a fake executor (oracle flows, scripted delays)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_1306_2461_amd.serve import Server, poisson_arrivals
+from serve_fake import FakeClock, FakeExecutor
+
+
+def _frames(stream, n, size):
+    return [f for f, _, _ in synth.stream_frames(stream, n, size=size)]
+
+
+def test_stream_order_and_results_match_oracle():
+    clock = FakeClock()
+    ex = FakeExecutor(2, 3, 2, clock=clock)
+    srv = Server(ex, clock=clock)
+    fr = {s: _frames(s, 4, (40, 48)) for s in (0, 1)}
+    reqs = {s: [srv.submit(s, f) for f in fr[s]] for s in (0, 1)}
+    srv.drain()
+    for s in (0, 1):
+        assert [r.has_flow for r in reqs[s]] == [False, True, True, True]
+        for t in range(1, 4):
+            u, v = oracle.flow(fr[s][t - 1], fr[s][t], 2, 3, 2)
+            assert np.array_equal(reqs[s][t].u, u) and np.array_equal(reqs[s][t].v, v)
+    # one frame per stream per push: 4 pushes of 2
+    assert ex.pushes == [2, 2, 2, 2]
+
+
+def test_late_arrivals_join_next_push():
+    clock = FakeClock()
+    ex = FakeExecutor(1, 2, 1, delay=1.0, clock=clock)
+    srv = Server(ex, clock=clock)
+    frames = [_frames(s, 2, (24, 24)) for s in range(3)]
+    srv.submit(0, frames[0][0])
+    assert srv.step() == 1                      # push 1 in flight
+    clock.advance(0.5)
+    srv.submit(1, frames[1][0])
+    srv.submit(2, frames[2][0])
+    srv.submit(0, frames[0][1])
+    assert srv.step() == 3                      # arrivals during push 1 batch together
+    assert len(srv.inflight) == 2 and srv.poll() == 0
+    clock.advance(0.5)
+    assert srv.poll() == 1
+    clock.advance(0.5)
+    assert srv.poll() == 3
+
+
+def test_admission_by_budget_waits_then_admits():
+    clock = FakeClock()
+    per = FakeExecutor(1, 2, 1).session_bytes(32, 32)
+    ex = FakeExecutor(1, 2, 1, budget_bytes=2 * per + 10, delay=0.5, clock=clock)
+    srv = Server(ex, clock=clock)
+    f = {s: _frames(s, 2, (32, 32)) for s in range(3)}
+    for s in range(3):
+        srv.submit(s, f[s][0])
+    assert srv.step() == 2                      # third stream waits for budget
+    assert len(srv.pending) == 1 and ex.resident == 2 * per
+    srv.drain(0)
+    srv.close_stream(0)
+    assert ex.resident == per
+    assert srv.step() == 1                      # now admitted
+    assert [a[1] for a in srv.admission_log].count("open") == 3
+
+
+def test_rejections_do_not_poison_other_streams():
+    clock = FakeClock()
+    per = FakeExecutor(1, 2, 1).session_bytes(32, 32)
+    ex = FakeExecutor(1, 2, 1, budget_bytes=per + 1, clock=clock)
+    srv = Server(ex, clock=clock)
+    good = _frames(0, 3, (32, 32))
+    big = np.zeros((64, 64), np.uint8)           # needs more than the whole budget
+    rq = [srv.submit(0, good[0]), srv.submit(1, big), srv.submit(0, good[1])]
+    bad_size = srv.submit(0, np.zeros((16, 16), np.uint8))
+    rq.append(srv.submit(0, good[2]))
+    srv.drain()
+    assert bad_size.error and "differs" in bad_size.error
+    assert rq[1].error and "budget" in rq[1].error
+    assert [r.has_flow for r in (rq[0], rq[2], rq[3])] == [False, True, True]
+    assert len(srv.rejected) == 2
+
+
+def test_slow_executor_grows_queue_and_p99():
+    clock = FakeClock()
+    ex = FakeExecutor(1, 2, 1, delay=0.05, clock=clock)
+    srv = Server(ex, clock=clock)
+    streams = [_frames(s, 6, (24, 24)) for s in range(2)]
+    arr = poisson_arrivals(streams, rate_per_stream=100.0, seed=1)
+    for t, s, f in arr:                          # everything arrives before any completion
+        srv.submit(s, f, t)
+    clock.t = max(a[0] for a in arr)
+    while srv.pending or srv.inflight:
+        srv.step()
+        if not srv.poll():
+            srv.ex.wait(srv.inflight[0][0])
+    st = srv.stats()
+    assert st["flows"] == 10 and st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_poisson_arrivals_keep_stream_order():
+    streams = [[np.full((2, 2), i, np.uint8) for i in range(5)] for _ in range(3)]
+    arr = poisson_arrivals(streams, 250.0)
+    assert len(arr) == 15 and all(a[0] <= b[0] for a, b in zip(arr, arr[1:]))
+    for s in range(3):
+        vals = [int(f[0, 0]) for t, sid, f in arr if sid == s]
+        assert vals == sorted(vals)
