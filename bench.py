@@ -94,6 +94,118 @@ def latency(torch, plan, d1, d2, us, vs, n_calls):
     return {"p50_ms": round(out[len(out) // 2], 4), "p99_ms": round(out[min(len(out) - 1, int(0.99 * len(out)))], 4)}
 
 
+def _gen_c4(i_and_size):
+    import synth
+    i, size = i_and_size
+    H, W, I1, I2, _, _ = next(synth.batch_items(1, sizes=[size]))
+    return I1, I2
+
+
+def _gen_stream(args):
+    import synth
+    sid, n, size = args
+    return [f for f, _, _ in synth.stream_frames(sid, n, size=size)]
+
+
+def bench_batched(torch, ofmi, dev, pairs, wl, fp16, reps, tag):
+    """The 1024x1024 workload as one batch of all resident pairs per graph replay."""
+    n = len(pairs)
+    b = ofmi.Batch([(wl.H, wl.W)] * n, wl.levels, wl.radius, wl.iters, fp16=fp16, device=dev)
+    d1 = [torch.from_numpy(p[0]).to(dev) for p in pairs]
+    d2 = [torch.from_numpy(p[1]).to(dev) for p in pairs]
+    us, vs = b.outputs()
+    cfg = b.autotune(d1, d2, us, vs, reps=2)
+    arrs = b.pointer_arrays(d1, d2, us, vs)
+    st = torch.cuda.current_stream().cuda_stream
+    for _ in range(3):
+        b.compute_raw(arrs, st)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        b.compute_raw(arrs, st)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    b.set_timing(True)
+    b.compute(d1, d2, us, vs)
+    torch.cuda.synchronize()
+    it = b.read_timing(ofmi.OF_KERNEL_ITERATE)
+    b.read_timing(ofmi.OF_KERNEL_REDUCE)
+    b.set_timing(False)
+    b.close()
+    ach = it[3] / it[0] / 1e6 if it[0] > 0 else 0.0
+    log(f"batched {tag}: {n * reps / el:.1f} pairs/s ({el / reps * 1e3:.3f} ms per batch of {n}), "
+        f"iterate {ach:.0f} GB/s, config {cfg}")
+    return {"value": round(n * reps / el, 3), "unit": "frame pairs/s", "pairs_per_batch": n,
+            "ms_per_batch": round(el / reps * 1e3, 4), "config": cfg,
+            "iterate_achieved_GBs": round(ach, 1), "iterate_frac_hbm": round(ach / HBM_PEAK_GBS, 4),
+            "iterate_avg_launch_us": round(it[0] / max(it[1], 1) * 1e3, 3)}
+
+
+def bench_c4(torch, ofmi, dev, workers, reps):
+    """64 mixed-size pairs (16x 512^2, 32x 1024x768, 16x 2048^2), FP16 storage, one replay per batch."""
+    import synth
+    wl = synth.workload("c4")
+    sizes = synth.particles.batch_sizes(64)
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        pairs = list(ex.map(_gen_c4, list(enumerate(sizes))))
+    b = ofmi.Batch(sizes, wl.levels, wl.radius, wl.iters, fp16=True, device=dev)
+    d1 = [torch.from_numpy(p[0]).to(dev) for p in pairs]
+    d2 = [torch.from_numpy(p[1]).to(dev) for p in pairs]
+    us, vs = b.outputs()
+    cfg = b.autotune(d1, d2, us, vs, reps=1)
+    arrs = b.pointer_arrays(d1, d2, us, vs)
+    st = torch.cuda.current_stream().cuda_stream
+    b.compute_raw(arrs, st)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        b.compute_raw(arrs, st)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    b.set_timing(True)
+    b.compute(d1, d2, us, vs)
+    torch.cuda.synchronize()
+    it = b.read_timing(ofmi.OF_KERNEL_ITERATE)
+    rd = b.read_timing(ofmi.OF_KERNEL_REDUCE)
+    b.set_timing(False)
+    b.close()
+    alg = it[3] + rd[3]
+    ach = it[3] / it[0] / 1e6 if it[0] > 0 else 0.0
+    log(f"c4: {64 * reps / el:.1f} pairs/s, {el / reps * 1e3:.2f} ms per batch, iterate {ach:.0f} GB/s")
+    return {"value": round(64 * reps / el, 3), "unit": "frame pairs/s", "ms_per_batch": round(el / reps * 1e3, 3),
+            "algorithmic_GB_per_batch": round(alg / 1e9, 3),
+            "effective_frac_hbm": round(alg / (el / reps) / 1e9 / HBM_PEAK_GBS, 4),
+            "iterate_achieved_GBs": round(ach, 1), "iterate_frac_hbm": round(ach / HBM_PEAK_GBS, 4),
+            "config": cfg}
+
+
+def bench_serving(torch, ofmi, dev, workers, frames_per_stream):
+    """8 streams (sizes from {640x480, 1024^2, 2048^2}), Poisson arrivals at 250 frames/s each."""
+    import synth
+    from paper_1306_2461_amd.serve import GpuExecutor, Server, poisson_arrivals
+    wl = synth.workload("c5")
+    sizes = synth.particles.stream_sizes(8)
+    with cf.ProcessPoolExecutor(max_workers=min(8, workers)) as ex:
+        streams = list(ex.map(_gen_stream, [(s, frames_per_stream, sizes[s]) for s in range(8)]))
+    arrivals = poisson_arrivals(streams, 250.0)
+    exe = GpuExecutor(wl.levels, wl.radius, wl.iters, fp16=True, budget_bytes=8 << 30, device=dev)
+    warm = Server(exe)                       # opens sessions, builds first pyramids, warms up
+    for sid in range(8):
+        for f in streams[sid][:2]:
+            warm.submit(sid, f)
+    warm.drain()
+    for sid in range(8):
+        warm.close_stream(sid)
+    srv = Server(exe)
+    st = srv.replay(arrivals, realtime=True)
+    exe.close_all()
+    st = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+    st.update({"streams": [f"{w}x{h}" for h, w in sizes], "frames_per_stream": frames_per_stream,
+               "offered_frames_per_s": 2000})
+    log(f"serving: {st}")
+    return st
+
+
 def kernel_timing(torch, ofmi, plan, d1, d2, us, vs, steps):
     """Average duration of each kernel from hipEvents recorded around its launches."""
     n = len(d1)
@@ -116,6 +228,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=8)
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched, mixed-batch and serving runs")
+    ap.add_argument("--serve-frames", type=int, default=24)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); pairs are "
@@ -173,6 +287,18 @@ def main():
             f"latency {lat}, iterate kernel avg {it[0] / max(it[1], 1) * 1e3:.2f} us over {it[1]} launches, "
             f"max |err| {err}")
 
+    extra = {}
+    if not args.no_extra:
+        for name, fn in (("batched_1024_fp32", lambda: bench_batched(torch, ofmi, dev, pairs, wl, False, 20, "fp32")),
+                         ("batched_1024_fp16", lambda: bench_batched(torch, ofmi, dev, pairs, wl, True, 20, "fp16")),
+                         ("mixed_batch_64", lambda: bench_c4(torch, ofmi, dev, workers, 5)),
+                         ("serving_8_streams", lambda: bench_serving(torch, ofmi, dev, workers, args.serve_frames))):
+            try:
+                extra[name] = fn()
+            except Exception as e:  # report, keep the main line
+                extra[name] = {"error": repr(e)}
+                log(f"{name} failed: {e!r}")
+
     r32 = results["fp32"]
     ms_it, n_it, units_it, bytes_it = r32["it"]
     achieved = bytes_it / ms_it / 1e6 if ms_it > 0 else 0.0
@@ -207,6 +333,7 @@ def main():
                  "iterate_avg_launch_us": round(results["fp16"]["it"][0] / max(results["fp16"]["it"][1], 1) * 1e3, 3)},
         "cpu_baseline": cpu,
     }
+    line.update(extra)
     print(json.dumps(line), flush=True)
 
 

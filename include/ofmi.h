@@ -66,10 +66,16 @@ typedef enum {
 #define OF_FLAG_INPUT_F32    (1u << 1) /* frames are float32 instead of uint8 */
 #define OF_FLAG_NO_GRAPH     (1u << 2) /* launch kernels one by one instead of replaying a
                                           captured hipGraph of the schedule */
+#define OF_FLAG_NORMALIZE    (1u << 3) /* plans only: equalise both frames locally (see
+                                          of_normalize; radius OF_NORMALIZE_RADIUS, eps
+                                          OF_NORMALIZE_EPS) before the pyramid */
 
 #define OF_MAX_LEVELS 12
 #define OF_MAX_RADIUS 12
 #define OF_MAX_ITERS 1000
+#define OF_MAX_NORMALIZE_RADIUS 16
+#define OF_NORMALIZE_RADIUS 5      /* the paper's local radius (Sec. 2.4) */
+#define OF_NORMALIZE_EPS 1.0f      /* added to the local standard deviation (frame units) */
 
 typedef struct of_plan of_plan;
 
@@ -228,6 +234,32 @@ OF_API of_status of_server_close(of_server* s, of_session* session);
 
 /* Destroys the server and every session still open.  NULL-safe. */
 OF_API void of_server_destroy(of_server* s);
+
+/* --------------------------------------------------------------------- around the flow
+ * Local equalisation of a raw frame (Sec. 2.4, eq. 2; the printed denominator is the root of
+ * minus the variance, the text says "divided by the local intensity standard deviation"):
+ * out = (in - m) / (sd + eps), m and sd the mean and standard deviation of `in` over the
+ * (2r+1)^2 window truncated at the border (in-image pixels only), accumulated in FP64.
+ * in: H x W uint8 (float32 with OF_FLAG_INPUT_F32) device plane; out: H x W float32 device
+ * plane, distinct from in.  0 <= radius <= OF_MAX_NORMALIZE_RADIUS, eps >= 0.
+ * Errors: OF_EINVAL on bad arguments (nothing enqueued). */
+OF_API of_status of_normalize(const void* in, float* out, int H, int W, int radius, float eps,
+                              unsigned flags, void* stream);
+
+/* Field statistics for the recirculation-bubble surface (Sec. 3.2, eq. 3; denominator read
+ * as the number of vectors, as the text says).  All pointers are device pointers.
+ *   of_field_mean_update: mean <- mean + (x - mean) / (t + 1) over n elements (the mean of
+ *     t + 1 fields from the mean of the first t).
+ *   of_field_minmax: out2[0] = min x, out2[1] = max x; `work` is a caller-owned device
+ *     scratch of 2 unsigned ints.
+ *   of_count_at_most: *count (device uint64) = number of x[i] <= threshold.
+ * The bubble surface is count / n with threshold (min + max) / 2 of the mean field. */
+OF_API of_status of_field_mean_update(float* mean, const float* x, long long n, int t,
+                                      void* stream);
+OF_API of_status of_field_minmax(const float* x, long long n, float* out2, void* work,
+                                 void* stream);
+OF_API of_status of_count_at_most(const float* x, long long n, float threshold,
+                                  unsigned long long* count, void* stream);
 
 /* --------------------------------------------------------------------- stage entry points
  * One step of the method on caller buffers, for stage-by-stage checking.

@@ -7,3 +7,6 @@ from .lk import (  # noqa: F401
     TAU, bilinear, blur5, box_sum, flow, gradients, lk_iteration, pyr_reduce, pyramid,
     solve, upsample_flow, warp,
 )
+from .extras import (  # noqa: F401,E402
+    bubble_surface, bubble_threshold, levels_for_displacement, local_normalize, running_mean,
+)

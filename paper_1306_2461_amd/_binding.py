@@ -16,6 +16,7 @@ OF_OK, OF_EINVAL, OF_ENOMEM, OF_EHIP, OF_ESTATE = range(5)
 OF_FLAG_FP16_STORAGE = 1 << 0
 OF_FLAG_INPUT_F32 = 1 << 1
 OF_FLAG_NO_GRAPH = 1 << 2
+OF_FLAG_NORMALIZE = 1 << 3
 OF_STAGE_REDUCE = 0
 OF_STAGE_ITERATE = 1
 OF_KERNEL_ITERATE = 0
@@ -53,6 +54,10 @@ SIGNATURES = {
     "of_server_resident_bytes": (_c_size, [_vp]),
     "of_server_close": (_c_int, [_vp, _vp]),
     "of_server_destroy": (None, [_vp]),
+    "of_normalize": (_c_int, [_vp, _vp, _c_int, _c_int, _c_int, ctypes.c_float, _c_uint, _vp]),
+    "of_field_mean_update": (_c_int, [_vp, _vp, ctypes.c_longlong, _c_int, _vp]),
+    "of_field_minmax": (_c_int, [_vp, ctypes.c_longlong, _vp, _vp, _vp]),
+    "of_count_at_most": (_c_int, [_vp, ctypes.c_longlong, ctypes.c_float, _vp, _vp]),
     "of_plan_set_timing": (_c_int, [_vp, _c_int]),
     "of_plan_read_timing": (_c_int, [_vp, _c_int, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_longlong),

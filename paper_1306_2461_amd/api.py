@@ -31,11 +31,11 @@ class Plan:
     """
 
     def __init__(self, H, W, levels, radius, iters, fp16=False, input_f32=False, device=None,
-                 graph=True):
+                 graph=True, normalize=False):
         lib = B.load()
         self.H, self.W, self.levels, self.radius, self.iters = H, W, levels, radius, iters
         self.flags = ((B.OF_FLAG_FP16_STORAGE if fp16 else 0) | (B.OF_FLAG_INPUT_F32 if input_f32 else 0)
-                      | (0 if graph else B.OF_FLAG_NO_GRAPH))
+                      | (0 if graph else B.OF_FLAG_NO_GRAPH) | (B.OF_FLAG_NORMALIZE if normalize else 0))
         self.frame_dtype = torch.float32 if input_f32 else torch.uint8
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         nbytes = lib.of_plan_workspace_bytes(H, W, levels, radius, iters, self.flags)
@@ -216,3 +216,51 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def normalize(I, radius: int = 5, eps: float = 1.0, out=None, stream=None):
+    """Local equalisation of one frame (eq. 2 reading): (I - mean) / (std + eps) over the
+    (2r+1)^2 window truncated at the border.  uint8 or float32 in, float32 out."""
+    if I.dtype not in (torch.uint8, torch.float32) or not I.is_contiguous() or I.dim() != 2:
+        raise B.OfError("normalize takes a contiguous 2-D uint8 or float32 tensor")
+    H, W = I.shape
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=I.device)
+    flags = B.OF_FLAG_INPUT_F32 if I.dtype == torch.float32 else 0
+    B.check(B.load().of_normalize(I.data_ptr(), out.data_ptr(), H, W, radius, float(eps), flags,
+                                  _stream_handle(I.device, stream)), "of_normalize")
+    return out
+
+
+class BubbleMonitor:
+    """Recirculation-bubble surface of a sequence of fields (Sec. 3.2, eq. 3): keeps the running
+    mean of the streamwise component on the device; ``update(u)`` folds in a field and returns
+    the fraction of its vectors at or below T_v = (min + max) / 2 of the mean field."""
+
+    def __init__(self, H, W, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.mean = torch.zeros((H, W), dtype=torch.float32, device=self.device)
+        self.t = 0
+        self._mm = torch.empty(2, dtype=torch.float32, device=self.device)
+        self._work = torch.empty(2, dtype=torch.int32, device=self.device)
+        self._count = torch.empty(1, dtype=torch.int64, device=self.device)
+
+    def threshold(self, stream=None):
+        lib = B.load()
+        n = self.mean.numel()
+        B.check(lib.of_field_minmax(self.mean.data_ptr(), n, self._mm.data_ptr(), self._work.data_ptr(),
+                                    _stream_handle(self.device, stream)), "of_field_minmax")
+        lo, hi = self._mm.tolist()
+        return 0.5 * (lo + hi)
+
+    def update(self, u, stream=None):
+        lib = B.load()
+        n = u.numel()
+        st = _stream_handle(self.device, stream)
+        B.check(lib.of_field_mean_update(self.mean.data_ptr(), u.data_ptr(), n, self.t, st),
+                "of_field_mean_update")
+        self.t += 1
+        thr = self.threshold(stream)
+        B.check(lib.of_count_at_most(u.data_ptr(), n, float(thr), self._count.data_ptr(), st),
+                "of_count_at_most")
+        return int(self._count.item()) / n

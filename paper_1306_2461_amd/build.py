@@ -15,7 +15,7 @@ LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libofmi.so")
 
 SOURCES = ["pyramid.hip", "lk_iter.hip", "lk_iter_u8.hip", "lk_iter_f32.hip", "lk_iter_f16.hip",
-           "runtime.hip", "batch.hip", "serve.hip"]
+           "runtime.hip", "batch.hip", "serve.hip", "extras.hip"]
 
 # Packed FP32 arithmetic is disabled for every HIP translation unit.
 HIPFLAGS = [

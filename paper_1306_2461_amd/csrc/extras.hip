@@ -1,0 +1,210 @@
+// Steps around the flow: local equalisation of raw frames (Sec. 2.4, eq. 2 read as
+// (I - local mean) / (local standard deviation + eps) over a (2r+1)^2 window truncated at the
+// border) and the field statistics behind the recirculation-bubble surface (Sec. 3.2, eq. 3:
+// running mean field, its extremes, and the count of vectors at or below a threshold).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ofmi.h"
+#include "kernels.h"
+#include "runtime.h"
+
+namespace ofmi {
+
+namespace {
+
+constexpr int NTW = 64, NTH = 16;    // output tile of the normalisation kernel
+
+// Window sums in FP64 (exact for 8-bit input), separable: row sums of the tile's rows into
+// LDS, then column sums per output pixel.
+template <typename T>
+__global__ __launch_bounds__(256) void normalize_kernel(const T* __restrict__ in, float* __restrict__ out,
+                                                        int H, int W, int r, float eps) {
+  extern __shared__ double rs[];     // [(NTH + 2r) * NTW] sums, then the same of squares
+  const int x0 = blockIdx.x * NTW, y0 = blockIdx.y * NTH;
+  const int rows = NTH + 2 * r;
+  double* s1 = rs;
+  double* s2 = rs + rows * NTW;
+  for (int i = threadIdx.x; i < rows * NTW; i += 256) {
+    const int ly = i / NTW, lx = i - ly * NTW;
+    const int gy = y0 - r + ly, gx = x0 + lx;
+    double a = 0.0, b = 0.0;
+    if (gy >= 0 && gy < H && gx < W) {
+      const unsigned base = (unsigned)gy * (unsigned)W;
+      const int xa = max(gx - r, 0), xb = min(gx + r, W - 1);
+      for (int x = xa; x <= xb; ++x) {
+        const double v = (double)ld(in, base + (unsigned)x);
+        a += v;
+        b += v * v;
+      }
+    }
+    s1[i] = a;
+    s2[i] = b;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < NTH * NTW; i += 256) {
+    const int ly = i / NTW, lx = i - ly * NTW;
+    const int gy = y0 + ly, gx = x0 + lx;
+    if (gy >= H || gx >= W) continue;
+    double a = 0.0, b = 0.0;
+    for (int dy = 0; dy <= 2 * r; ++dy) {
+      a += s1[(ly + dy) * NTW + lx];
+      b += s2[(ly + dy) * NTW + lx];
+    }
+    const int nx = min(gx + r, W - 1) - max(gx - r, 0) + 1;
+    const int ny = min(gy + r, H - 1) - max(gy - r, 0) + 1;
+    const double n = (double)nx * ny;
+    const double m = a / n, m2 = b / n;
+    const double sd = sqrt(fmax(m2 - m * m, 0.0));
+    const unsigned o = (unsigned)gy * (unsigned)W + (unsigned)gx;
+    at(out, o) = (float)(((double)ld(in, o) - m) / (sd + (double)eps));
+  }
+}
+
+__global__ void mean_update_kernel(float* __restrict__ mean, const float* __restrict__ x,
+                                   long long n, float inv) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    mean[i] = fmaf(x[i] - mean[i], inv, mean[i]);
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Monotone map of a float onto unsigned ints (for atomic min/max on floats).
+__device__ __forceinline__ unsigned ordered(float f) {
+  const unsigned b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float unordered(unsigned u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+__global__ void stats_init_kernel(unsigned* mm, unsigned long long* cnt) {
+  if (threadIdx.x == 0) {
+    if (mm) {
+      mm[0] = 0xffffffffu;    // min
+      mm[1] = 0u;             // max
+    }
+    if (cnt) *cnt = 0ull;
+  }
+}
+
+__global__ __launch_bounds__(256) void minmax_kernel(const float* __restrict__ x, long long n,
+                                                     unsigned* mm) {
+  float lo = INFINITY, hi = -INFINITY;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    lo = fminf(lo, x[i]);
+    hi = fmaxf(hi, x[i]);
+  }
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&mm[0], ordered(lo));
+    atomicMax(&mm[1], ordered(hi));
+  }
+}
+
+__global__ void minmax_finish_kernel(unsigned* mm, float* out) {
+  if (threadIdx.x == 0) {
+    out[0] = unordered(mm[0]);
+    out[1] = unordered(mm[1]);
+  }
+}
+
+__global__ __launch_bounds__(256) void count_kernel(const float* __restrict__ x, long long n,
+                                                    float thr, unsigned long long* cnt) {
+  unsigned long long c = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    c += x[i] <= thr ? 1ull : 0ull;
+  c = wave_sum(c);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
+}
+
+unsigned grid_for(long long n) {
+  const long long b = (n + 255) / 256;
+  return (unsigned)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
+}
+
+}  // namespace
+
+hipError_t launch_normalize(Elem t, const void* in, float* out, int H, int W, int r, float eps,
+                            hipStream_t s) {
+  dim3 grid((W + NTW - 1) / NTW, (H + NTH - 1) / NTH);
+  const size_t lds = 2 * sizeof(double) * (size_t)(NTH + 2 * r) * NTW;
+  if (t == Elem::U8)
+    hipLaunchKernelGGL(normalize_kernel<uint8_t>, grid, dim3(256), lds, s, (const uint8_t*)in, out,
+                       H, W, r, eps);
+  else if (t == Elem::F32)
+    hipLaunchKernelGGL(normalize_kernel<float>, grid, dim3(256), lds, s, (const float*)in, out, H,
+                       W, r, eps);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace ofmi
+
+using namespace ofmi;
+
+extern "C" {
+
+of_status of_normalize(const void* in, float* out, int H, int W, int radius, float eps,
+                       unsigned flags, void* stream) {
+  if (!in || !out) return set_error("NULL plane"), OF_EINVAL;
+  if (H < 1 || W < 1 || (long long)H * W >= (1ll << 30)) return set_error("bad size"), OF_EINVAL;
+  if (radius < 0 || radius > OF_MAX_NORMALIZE_RADIUS) return set_error("radius out of range"), OF_EINVAL;
+  if (!(eps >= 0.f)) return set_error("eps must be >= 0"), OF_EINVAL;
+  if (flags & ~OF_FLAG_INPUT_F32) return set_error("unknown flags"), OF_EINVAL;
+  if ((void*)out == in) return set_error("in and out must differ"), OF_EINVAL;
+  hipError_t e = launch_normalize((flags & OF_FLAG_INPUT_F32) ? Elem::F32 : Elem::U8, in, out, H,
+                                  W, radius, eps, (hipStream_t)stream);
+  if (e != hipSuccess) return set_error(std::string("normalize: ") + hipGetErrorString(e)), OF_EHIP;
+  return OF_OK;
+}
+
+of_status of_field_mean_update(float* mean, const float* x, long long n, int t, void* stream) {
+  if (!mean || !x || n < 1 || t < 0) return set_error("bad argument"), OF_EINVAL;
+  hipLaunchKernelGGL(mean_update_kernel, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
+                     mean, x, n, 1.0f / (float)(t + 1));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(hipGetErrorString(e)), OF_EHIP;
+  return OF_OK;
+}
+
+of_status of_field_minmax(const float* x, long long n, float* out2, void* work, void* stream) {
+  if (!x || !out2 || !work || n < 1) return set_error("bad argument"), OF_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned* mm = (unsigned*)work;
+  hipLaunchKernelGGL(stats_init_kernel, dim3(1), dim3(64), 0, s, mm, (unsigned long long*)nullptr);
+  hipLaunchKernelGGL(minmax_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, mm);
+  hipLaunchKernelGGL(minmax_finish_kernel, dim3(1), dim3(64), 0, s, mm, out2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(hipGetErrorString(e)), OF_EHIP;
+  return OF_OK;
+}
+
+of_status of_count_at_most(const float* x, long long n, float threshold,
+                           unsigned long long* count, void* stream) {
+  if (!x || !count || n < 1) return set_error("bad argument"), OF_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(stats_init_kernel, dim3(1), dim3(64), 0, s, (unsigned*)nullptr, count);
+  hipLaunchKernelGGL(count_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, threshold, count);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(hipGetErrorString(e)), OF_EHIP;
+  return OF_OK;
+}
+
+}  // extern "C"

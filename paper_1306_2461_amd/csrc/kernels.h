@@ -46,6 +46,10 @@ hipError_t launch_iter(Elem t, const IterArgs& a, int R, int nb, hipStream_t s);
 // The same over a work list of many pairs' tiles at one (level, iteration) phase.
 hipError_t launch_iter_batch(Elem t, const BatchLaunch& b, int R, int mode, hipStream_t s);
 
+// Local equalisation of one frame (uint8 or float32 in, float32 out).
+hipError_t launch_normalize(Elem t, const void* in, float* out, int H, int W, int r, float eps,
+                            hipStream_t s);
+
 // u = v = 0 over n elements (a fill kernel, safe under stream capture).
 hipError_t launch_zero(float* u, float* v, size_t n, hipStream_t s);
 

@@ -16,7 +16,9 @@ struct Geometry {
   int L, R, K;
   unsigned flags;
   int H[OF_MAX_LEVELS], W[OF_MAX_LEVELS];
-  Elem e0;                          // level-0 frame element type (uint8 or float32)
+  Elem ein;                         // element type of the caller's frames
+  Elem e0;                          // level-0 plane element type (float32 when normalised)
+  size_t off_norm[2];               // normalised level-0 planes (OF_FLAG_NORMALIZE)
   Elem ep;                          // element type of pyramid levels >= 1
   size_t off_p1[OF_MAX_LEVELS];     // workspace offsets of the pyramid levels (>= 1)
   size_t off_p2[OF_MAX_LEVELS];

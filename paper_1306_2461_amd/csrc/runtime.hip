@@ -27,7 +27,7 @@ bool check_params(int H, int W, int levels, int radius, int iters, unsigned flag
   if (levels > maxl) return set_error("levels > 1 + floor(log2(min(H, W)))"), false;
   if (radius < 0 || radius > OF_MAX_RADIUS) return set_error("radius out of range"), false;
   if (iters < 0 || iters > OF_MAX_ITERS) return set_error("iters out of range"), false;
-  if (flags & ~(OF_FLAG_FP16_STORAGE | OF_FLAG_INPUT_F32 | OF_FLAG_NO_GRAPH))
+  if (flags & ~(OF_FLAG_FP16_STORAGE | OF_FLAG_INPUT_F32 | OF_FLAG_NO_GRAPH | OF_FLAG_NORMALIZE))
     return set_error("unknown flags"), false;
   return true;
 }
@@ -53,9 +53,16 @@ Geometry make_geometry(int H, int W, int levels, int radius, int iters, unsigned
     g.W[l] = (g.W[l - 1] + 1) / 2;
   }
   for (int l = 0; l < levels; ++l) g.nb[l] = default_bands(g.H[l], g.W[l], radius);
-  g.e0 = (flags & OF_FLAG_INPUT_F32) ? Elem::F32 : Elem::U8;
+  g.ein = (flags & OF_FLAG_INPUT_F32) ? Elem::F32 : Elem::U8;
+  g.e0 = (flags & OF_FLAG_NORMALIZE) ? Elem::F32 : g.ein;
   g.ep = (flags & OF_FLAG_FP16_STORAGE) ? Elem::F16 : Elem::F32;
   size_t off = 0;
+  if (flags & OF_FLAG_NORMALIZE) {
+    for (int i = 0; i < 2; ++i) {
+      g.off_norm[i] = off;
+      off += align256((size_t)H * W * sizeof(float));
+    }
+  }
   for (int l = 1; l < levels; ++l) {
     const size_t b = align256((size_t)g.H[l] * g.W[l] * elem_bytes(g.ep));
     g.off_p1[l] = off;
@@ -158,6 +165,17 @@ hipError_t enqueue_pair(const Geometry& g, char* ws, const void* I1, const void*
   const void* P2[OF_MAX_LEVELS];
   P1[0] = I1;
   P2[0] = I2;
+  if (g.flags & OF_FLAG_NORMALIZE) {
+    float* n1 = (float*)(ws + g.off_norm[0]);
+    float* n2 = (float*)(ws + g.off_norm[1]);
+    hipError_t e = launch_normalize(g.ein, I1, n1, g.H[0], g.W[0], OF_NORMALIZE_RADIUS,
+                                    OF_NORMALIZE_EPS, s);
+    if (e == hipSuccess)
+      e = launch_normalize(g.ein, I2, n2, g.H[0], g.W[0], OF_NORMALIZE_RADIUS, OF_NORMALIZE_EPS, s);
+    if (e != hipSuccess) return e;
+    P1[0] = n1;
+    P2[0] = n2;
+  }
   for (int l = 1; l < g.L; ++l) {
     P1[l] = ws + g.off_p1[l];
     P2[l] = ws + g.off_p2[l];

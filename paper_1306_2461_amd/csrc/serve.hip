@@ -139,6 +139,7 @@ size_t of_session_bytes(int H, int W, int levels, int radius, int iters, unsigne
 of_server* of_server_create(int levels, int radius, int iters, unsigned flags,
                             size_t hbm_budget_bytes) {
   if (flags & OF_FLAG_NO_GRAPH) flags &= ~OF_FLAG_NO_GRAPH;
+  if (flags & OF_FLAG_NORMALIZE) return set_error("OF_FLAG_NORMALIZE applies to plans only"), nullptr;
   if (!check_params(1 << (levels > 0 ? levels - 1 : 0), 1 << (levels > 0 ? levels - 1 : 0), levels,
                     radius, iters, flags))
     return nullptr;

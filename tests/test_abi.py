@@ -51,8 +51,10 @@ def test_workspace_bytes_and_validation(lib):
     expect16 = sum(2 * a(h * w * 2) for h, w in sizes) + 4 * a(H * W * 4)
     assert lib.of_plan_workspace_bytes(H, W, 3, 4, 4, 1) == expect16
     for bad in [(0, 5, 1, 1, 1, 0), (5, 5, 0, 1, 1, 0), (4, 4, 4, 1, 1, 0), (64, 64, 2, -1, 1, 0),
-                (64, 64, 2, 99, 1, 0), (64, 64, 2, 2, -1, 0), (64, 64, 2, 2, 1, 8)]:
+                (64, 64, 2, 99, 1, 0), (64, 64, 2, 2, -1, 0), (64, 64, 2, 2, 1, 16)]:
         assert lib.of_plan_workspace_bytes(*bad) == 0
+    # OF_FLAG_NORMALIZE adds two level-0 float32 planes
+    assert lib.of_plan_workspace_bytes(H, W, 3, 4, 4, 8) == expect + 2 * a(H * W * 4)
     assert lib.of_plan_create(0, 5, 1, 1, 1) is None
     assert b"H and W" in lib.of_last_error()
     assert lib.of_compute(None, None, None, None, None, None) == 1
