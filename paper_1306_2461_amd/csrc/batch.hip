@@ -22,6 +22,9 @@ namespace {
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Launches with fewer tiles than this (under two per CU) use the wide tile variant.
+constexpr int kWideBelowTiles = 512;
+
 struct LevelCfg {
   int nb;     // tile height in bands of 2R+1 rows
   int grid;   // iteration workgroups; 0 = one per tile
@@ -222,6 +225,7 @@ hipError_t enqueue_batch(of_batch* b, char* blk, float* const* u, float* const* 
       bl.ntiles = b->ntiles[l];
       bl.grid = b->cfg[l].grid > 0 ? std::min(b->cfg[l].grid, bl.ntiles) : bl.ntiles;
       bl.grid = (bl.grid + 7) / 8 * 8;
+      bl.wide = bl.ntiles < kWideBelowTiles;
       const int mode = k > 0 ? kFlowSame : (l == L - 1 ? kFlowZero : kFlowCoarse);
       hipEvent_t ev = nullptr;
       hipError_t e = t ? t->begin(s, &ev) : hipSuccess;

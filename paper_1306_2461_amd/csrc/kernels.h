@@ -34,6 +34,7 @@ struct BatchLaunch {
   const int4* tiles;
   int ntiles;
   int grid;
+  bool wide;   // 10 instead of 5 threads per output column (latency-bound launches)
 };
 
 // Strip width (output columns per tile) and band height of the iteration kernel for radius R.

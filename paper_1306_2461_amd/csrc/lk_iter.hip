@@ -8,8 +8,10 @@ hipError_t launch_iter_f32(const IterArgs* a, const BatchLaunch* b, int R, int m
 hipError_t launch_iter_f16(const IterArgs* a, const BatchLaunch* b, int R, int mode, int nb, hipStream_t s);
 
 int strip_width_for(int R) {
-  // Mirrors strip_width<R>(): 64 columns while the LDS footprint fits in 64 KB.
-  return R <= 8 ? 64 : 32;
+  // Mirrors strip_width<R>(): the LDS footprint of 64-column strips stays within 64 KB for
+  // every supported radius (0..12).
+  (void)R;
+  return 64;
 }
 
 namespace {

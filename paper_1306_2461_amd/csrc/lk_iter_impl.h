@@ -25,11 +25,11 @@ namespace ofmi {
 
 namespace {
 
-template <int R, int TW_>
+template <int R, int TW_, bool WIDE = false>
 struct Cfg {
   static constexpr int N = 2 * R + 1;                 // band height = window height
   static constexpr int TW = TW_;                      // output columns per strip
-  static constexpr int NT = 5 * TW;                   // threads per workgroup
+  static constexpr int NT = (WIDE ? 10 : 5) * TW;     // threads per workgroup
   static constexpr int PC = TW + 2 * R;               // product columns
   static constexpr int WC = PC + 2;                   // warped-frame columns
   static constexpr int HL = 8 + 2 * R;                // products read per horizontal segment
@@ -43,21 +43,22 @@ struct Cfg {
   static constexpr int K2 = (N * PC + NT - 1) / NT;             // P2 items per thread
   static constexpr int K3 = (5 * N * NSEG + NT - 1) / NT;       // P3 items per thread
   static constexpr int K5 = (N * TW + NT - 1) / NT;             // P5 items per thread
-  static constexpr size_t LDS_FLOATS = 5 * (size_t)N * PP + 5 * (size_t)N * TW + (size_t)RING * WP;
+  // The window sums [5][N][TW] reuse the product buffer [5][N][PP] once P3 has read it.
+  static constexpr size_t LDS_FLOATS = 5 * (size_t)N * PP + (size_t)RING * WP;
 };
 
 // One tile: TW output columns from x0 = bx*TW and TH output rows from y0 = by*TH, walked in
 // nbands bands (TH is a multiple of N; nbands = TH/N + 1).  `sm4` is the workgroup's LDS.
-template <typename T, int R, int TW, int MODE>
+template <typename T, int R, int TW, int MODE, bool WIDE>
 __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands, int bx, int by,
                                            float4* sm4) {
-  using C = Cfg<R, TW>;
+  using C = Cfg<R, TW, WIDE>;
   constexpr int N = C::N, NT = C::NT, PC = C::PC, WC = C::WC, PP = C::PP, WP = C::WP;
   constexpr int RMASK = C::RING - 1;
   float* sm = reinterpret_cast<float*>(sm4);
   float* pr = sm;                               // [5][N][PP] products (16-byte aligned rows)
-  float* hs = pr + 5 * N * PP;                  // [5][N][TW] horizontal, then window sums
-  float* w2 = hs + 5 * N * TW;                  // [RING][WP] warped frame ring
+  float* hs = pr;                               // [5][N][TW] horizontal, then window sums
+  float* w2 = pr + 5 * N * PP;                  // [RING][WP] warped frame ring
 
   const int tid = threadIdx.x;
   const int H = a.H, W = a.W;
@@ -66,8 +67,9 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
   const T* __restrict__ I1 = (const T*)a.I1;
   const T* __restrict__ I2 = (const T*)a.I2;
 
-  // P4 ownership: channel and column of this thread.
+  // P4 ownership: channel and column of this thread (the first 5*TW threads).
   const int vk = tid / TW, vc = tid - vk * TW;
+  const bool p4 = vk < 5;
   float prev[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) prev[i] = 0.f;
@@ -92,6 +94,9 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
       wofs[k] = (w & RMASK) * WP + lx;
       read_flow<MODE>(a, wgx[k], wgy[k], wu[k], wv[k]);
     }
+    // In the coarse-field mode each field value costs eight loads: the field at this thread's
+    // P2 and P5 items is then read in those phases rather than held in flight here.
+    constexpr bool kDefer = MODE == kFlowCoarse;
     float i1v[C::K2], pu[C::K2], pv[C::K2];
 #pragma unroll
     for (int k = 0; k < C::K2; ++k) {
@@ -99,15 +104,17 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
       const int gx = min(max(x0 - R + i % PC, 0), W - 1);
       const int gy = min(max(y0 - R + tb + i / PC, 0), H - 1);
       i1v[k] = ld(I1, (unsigned)gy * (unsigned)W + (unsigned)gx);
-      read_flow<MODE>(a, gx, gy, pu[k], pv[k]);
+      if constexpr (!kDefer) read_flow<MODE>(a, gx, gy, pu[k], pv[k]);
     }
     float cu[C::K5], cv[C::K5];
+    if constexpr (!kDefer) {
 #pragma unroll
-    for (int k = 0; k < C::K5; ++k) {
-      const int i = min(tid + k * NT, N * TW - 1);
-      const int gx = min(x0 + i % TW, W - 1);
-      const int gy = min(max(y0 + tb + i / TW - 2 * R, 0), H - 1);
-      read_flow<MODE>(a, gx, gy, cu[k], cv[k]);
+      for (int k = 0; k < C::K5; ++k) {
+        const int i = min(tid + k * NT, N * TW - 1);
+        const int gx = min(x0 + i % TW, W - 1);
+        const int gy = min(max(y0 + tb + i / TW - 2 * R, 0), H - 1);
+        read_flow<MODE>(a, gx, gy, cu[k], cv[k]);
+      }
     }
 #pragma unroll
     for (int k = 0; k < C::K1; ++k) {
@@ -116,6 +123,15 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     }
     __syncthreads();
     // ---------------------------------------------------------------- P2
+    if constexpr (kDefer) {
+#pragma unroll
+      for (int k = 0; k < C::K2; ++k) {
+        const int i = min(tid + k * NT, N * PC - 1);
+        const int gx = min(max(x0 - R + i % PC, 0), W - 1);
+        const int gy = min(max(y0 - R + tb + i / PC, 0), H - 1);
+        read_flow<MODE>(a, gx, gy, pu[k], pv[k]);
+      }
+    }
 #pragma unroll
     for (int k = 0; k < C::K2; ++k) {
       const int i = tid + k * NT;
@@ -148,6 +164,9 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     }
     __syncthreads();
     // ---------------------------------------------------------------- P3
+    // The window sums overwrite the products they are made from: every thread first reads
+    // and sums its segments, then all write after a barrier.
+    float hv[C::K3][8];
 #pragma unroll
     for (int k = 0; k < C::K3; ++k) {
       const int i = tid + k * NT;
@@ -163,24 +182,31 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
           vbuf[4 * q + 2] = f.z;
           vbuf[4 * q + 3] = f.w;
         }
-        float out[8];
         float s = vbuf[0];
 #pragma unroll
         for (int q = 1; q <= 2 * R; ++q) s += vbuf[q];
-        out[0] = s;
+        hv[k][0] = s;
 #pragma unroll
         for (int j = 1; j < 8; ++j) {
           s = (s - vbuf[j - 1]) + vbuf[j + 2 * R];
-          out[j] = s;
+          hv[k][j] = s;
         }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < C::K3; ++k) {
+      const int i = tid + k * NT;
+      if (i < 5 * N * C::NSEG) {
+        const int seg = i % C::NSEG, rr = i / C::NSEG;
         float4* dst = reinterpret_cast<float4*>(hs + rr * C::TW + 8 * seg);
-        dst[0] = make_float4(out[0], out[1], out[2], out[3]);
-        dst[1] = make_float4(out[4], out[5], out[6], out[7]);
+        dst[0] = make_float4(hv[k][0], hv[k][1], hv[k][2], hv[k][3]);
+        dst[1] = make_float4(hv[k][4], hv[k][5], hv[k][6], hv[k][7]);
       }
     }
     __syncthreads();
     // ---------------------------------------------------------------- P4
-    {
+    if (p4) {
       float cur[N];
       float* col = hs + vk * N * TW + vc;
 #pragma unroll
@@ -201,6 +227,15 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     }
     __syncthreads();
     // ---------------------------------------------------------------- P5
+    if constexpr (kDefer) {
+#pragma unroll
+      for (int k = 0; k < C::K5; ++k) {
+        const int i = min(tid + k * NT, N * TW - 1);
+        const int gx = min(x0 + i % TW, W - 1);
+        const int gy = min(max(y0 + tb + i / TW - 2 * R, 0), H - 1);
+        read_flow<MODE>(a, gx, gy, cu[k], cv[k]);
+      }
+    }
 #pragma unroll
     for (int k = 0; k < C::K5; ++k) {
       const int i = tid + k * NT;
@@ -219,9 +254,9 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
         }
       }
     }
-    // The next band's P1 writes ring rows and P2/P3 buffers that P2/P3 of this band have
-    // finished reading before the barriers above; P5 reads only hs, which the next band
-    // rewrites after two more barriers.
+    // The next band's P1 writes only ring rows that this band's P2 finished reading before
+    // the barriers above; its P2 rewrites the product/window-sum buffer after the P1 barrier,
+    // when every thread has finished this band's P5.
   }
 }
 
@@ -233,31 +268,34 @@ __device__ __forceinline__ int xcd_order(int b, int nblocks) {
   return (b % kXcd) * per + b / kXcd;
 }
 
-template <typename T, int R, int TW, int MODE>
-__global__ __launch_bounds__(5 * TW) void lk_iter_strip(IterArgs a, int TH, int nbands, int tiles_x,
-                                                        int ntiles) {
+template <typename T, int R, int TW, int MODE, bool WIDE>
+__global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_strip(IterArgs a, int TH, int nbands,
+                                                                      int tiles_x, int ntiles) {
   extern __shared__ float4 sm4[];
   const int t = xcd_order(blockIdx.x, gridDim.x);
   if (t >= ntiles) return;
-  strip_tile<T, R, TW, MODE>(a, TH, nbands, t % tiles_x, t / tiles_x, sm4);
+  strip_tile<T, R, TW, MODE, WIDE>(a, TH, nbands, t % tiles_x, t / tiles_x, sm4);
 }
 
 // Batched form: workgroups stride over a work list of tiles of many pairs at the same
 // (level, iteration) phase.  Work item = (pair, tile x, tile y, tile height).
-template <typename T, int R, int TW, int MODE>
-__global__ __launch_bounds__(5 * TW) void lk_iter_batch(const IterArgs* __restrict__ args,
-                                                        const int4* __restrict__ tiles,
-                                                        int ntiles) {
+template <typename T, int R, int TW, int MODE, bool WIDE>
+__global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_batch(const IterArgs* __restrict__ args,
+                                                                      const int4* __restrict__ tiles,
+                                                                      int ntiles) {
   extern __shared__ float4 sm4[];
-  using C = Cfg<R, TW>;
+  using C = Cfg<R, TW, WIDE>;
   const int stride = (int)gridDim.x;
   for (int t = xcd_order(blockIdx.x, gridDim.x); t < ntiles; t += stride) {
     const int4 w = tiles[t];
     const IterArgs a = args[w.x];
-    strip_tile<T, R, TW, MODE>(a, w.w, w.w / C::N + 1, w.y, w.z, sm4);
+    strip_tile<T, R, TW, MODE, WIDE>(a, w.w, w.w / C::N + 1, w.y, w.z, sm4);
     __syncthreads();
   }
 }
+
+// Levels with fewer pixels than this run the wide (10 threads per column) variant.
+constexpr long long kWideBelowPixels = 1ll << 18;
 
 // 64-column strips while the LDS footprint stays within 64 KB, else 32-column strips.
 template <int R>
@@ -265,26 +303,39 @@ constexpr int strip_width() {
   return Cfg<R, 64>::LDS_FLOATS * sizeof(float) <= 65536 ? 64 : 32;
 }
 
-template <typename T, int R, int MODE>
-hipError_t go_plain(const IterArgs& a, int nb, hipStream_t s) {
+template <typename T, int R, int MODE, bool WIDE>
+hipError_t go_plain_w(const IterArgs& a, int nb, hipStream_t s) {
   constexpr int TW = strip_width<R>();
-  using C = Cfg<R, TW>;
+  using C = Cfg<R, TW, WIDE>;
   const int TH = C::N * nb;
   const int tx = (a.W + TW - 1) / TW, ty = (a.H + TH - 1) / TH;
   const int ntiles = tx * ty;
   const int grid = (ntiles + 7) / 8 * 8;
-  hipLaunchKernelGGL((lk_iter_strip<T, R, TW, MODE>), dim3(grid), dim3(C::NT),
+  hipLaunchKernelGGL((lk_iter_strip<T, R, TW, MODE, WIDE>), dim3(grid), dim3(C::NT),
                      C::LDS_FLOATS * sizeof(float), s, a, TH, nb + 1, tx, ntiles);
+  return hipGetLastError();
+}
+
+// Small levels are latency bound: twice the threads per tile halve each band's path.
+template <typename T, int R, int MODE>
+hipError_t go_plain(const IterArgs& a, int nb, hipStream_t s) {
+  if ((long long)a.H * a.W < kWideBelowPixels) return go_plain_w<T, R, MODE, true>(a, nb, s);
+  return go_plain_w<T, R, MODE, false>(a, nb, s);
+}
+
+template <typename T, int R, int MODE, bool WIDE>
+hipError_t go_batch_w(const BatchLaunch& b, hipStream_t s) {
+  constexpr int TW = strip_width<R>();
+  using C = Cfg<R, TW, WIDE>;
+  hipLaunchKernelGGL((lk_iter_batch<T, R, TW, MODE, WIDE>), dim3(b.grid), dim3(C::NT),
+                     C::LDS_FLOATS * sizeof(float), s, b.args, b.tiles, b.ntiles);
   return hipGetLastError();
 }
 
 template <typename T, int R, int MODE>
 hipError_t go_batch(const BatchLaunch& b, hipStream_t s) {
-  constexpr int TW = strip_width<R>();
-  using C = Cfg<R, TW>;
-  hipLaunchKernelGGL((lk_iter_batch<T, R, TW, MODE>), dim3(b.grid), dim3(C::NT),
-                     C::LDS_FLOATS * sizeof(float), s, b.args, b.tiles, b.ntiles);
-  return hipGetLastError();
+  if (b.wide) return go_batch_w<T, R, MODE, true>(b, s);
+  return go_batch_w<T, R, MODE, false>(b, s);
 }
 
 template <typename T, int R>

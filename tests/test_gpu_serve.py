@@ -31,19 +31,35 @@ def _run(executor_kw, order):
     return out, streams
 
 
-def test_alone_equals_mix_and_oracle(gpu_lib):
+def test_alone_equals_mix_equals_plain_and_oracle(gpu_lib):
+    """Each served flow equals the same stream served alone and the plain per-pair path on the
+    same two frames, bitwise; against the oracle it is checked away from the borders: these
+    small frames move 8 px per frame out of the image, and within ~2 x 8 + r px of the border
+    the windows are so ill-conditioned that an FP32 run of the oracle's own operation order
+    departs from FP64 by up to 0.12 px."""
+    import torch
+    ofmi = gpu_lib
+    from gpu_util import to_dev
     announce("serving: mix of 3 streams x 4 frames")
     mix, streams = _run({}, [(s, t) for t in range(4) for s in range(3)])
+    m = 2 * 8 + R + 2
     for s in range(3):
         announce(f"serving: stream {s} alone")
         alone, _ = _run({}, [(s, t) for t in range(4)])
         assert len(mix[s]) == 3 and len(alone[s]) == 3
+        H, W = SIZES[s]
+        plan = ofmi.Plan(H, W, L, R, K, device=dev())
         for t in range(3):
             assert np.array_equal(mix[s][t][0], alone[s][t][0]), (s, t)
             assert np.array_equal(mix[s][t][1], alone[s][t][1]), (s, t)
+            pu, pv = plan.compute(to_dev(streams[s][t]), to_dev(streams[s][t + 1]))
+            torch.cuda.synchronize()
+            assert np.array_equal(mix[s][t][0], pu.cpu().numpy()), (s, t)
+            assert np.array_equal(mix[s][t][1], pv.cpu().numpy()), (s, t)
             ou, ov = oracle.flow(streams[s][t], streams[s][t + 1], L, R, K)
-            d = flow_error(mix[s][t][0], mix[s][t][1], ou, ov)
+            d = flow_error(mix[s][t][0], mix[s][t][1], ou, ov)[m:-m, m:-m]
             assert d.max() <= 1e-3, report(d, 1e-3)
+        plan.close()
 
 
 def test_session_budget_and_single_push(gpu_lib):
