@@ -266,6 +266,8 @@ def main():
     results = {}
     for tag, fp16 in (("fp32", False), ("fp16", True)):
         plan = ofmi.Plan(wl.H, wl.W, L, r, K, fp16=fp16, device=dev)
+        tuned = plan.autotune(d1[0], d2[0], us[0], vs[0], reps=3)
+        log(f"{tag}: autotuned launch configuration {tuned}")
         el = time_plan(torch, plan, d1, d2, us, vs, args.steps, args.warmup)
         lat = latency(torch, plan, d1, d2, us, vs, min(200, args.steps))
         it, rd = kernel_timing(torch, ofmi, plan, d1, d2, us, vs, min(100, args.steps))
@@ -279,9 +281,11 @@ def main():
         eager = None
         if tag == "fp32":
             pe = ofmi.Plan(wl.H, wl.W, L, r, K, fp16=fp16, device=dev, graph=False)
+            pe.set_config(tuned)
             eager = args.steps / time_plan(torch, pe, d1, d2, us, vs, args.steps, args.warmup)
             pe.close()
-        results[tag] = {"el": el, "lat": lat, "it": it, "rd": rd, "err": err, "eager": eager}
+        results[tag] = {"el": el, "lat": lat, "it": it, "rd": rd, "err": err, "eager": eager,
+                        "cfg": tuned}
         plan.close()
         log(f"{tag}: {args.steps / el:.1f} pairs/s, {el / args.steps * 1e3:.4f} ms/pair, "
             f"latency {lat}, iterate kernel avg {it[0] / max(it[1], 1) * 1e3:.2f} us over {it[1]} launches, "
@@ -318,7 +322,7 @@ def main():
         "config": {"workload": "1024x1024 uint8 particle-image pair, 4 levels, radius 8, 4 iterations/level, "
                                "FP32 plain per-pair path (one of_compute per pair, one stream)",
                    "H": wl.H, "W": wl.W, "levels": L, "radius": r, "iters": K,
-                   "distinct_pairs": args.pairs},
+                   "distinct_pairs": args.pairs, "launch_config": r32["cfg"]},
         "latency_ms": r32["lat"],
         "eager_launch_value": round(r32["eager"], 3),
         "max_abs_err_px": r32["err"],

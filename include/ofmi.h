@@ -111,6 +111,19 @@ OF_API of_status of_compute(of_plan* plan, const void* I1, const void* I2, float
 /* Releases the plan and the workspace it allocated.  NULL-safe. */
 OF_API void of_plan_destroy(of_plan* plan);
 
+/* Per-level launch configuration of a plan: bands[l] = tile height of the iteration kernel
+ * in bands of 2r+1 rows (1..64), wide[l] = 1 to use 10 instead of 5 threads per output column
+ * (shorter per-thread path; for levels with few tiles).  Arrays of `levels` entries.
+ * set_config drops the plan's captured graphs.  Results do not depend on the configuration. */
+OF_API of_status of_plan_get_config(const of_plan* plan, int* bands, int* wide);
+OF_API of_status of_plan_set_config(of_plan* plan, const int* bands, const int* wide);
+
+/* Autotuner: for each level in turn, times that level's iteration launches for bands in
+ * {1,2,4,8} x wide in {0,1} on the given buffers (reps timed runs after one warm-up) and
+ * keeps the fastest.  Synchronises `stream`; writes u, v. */
+OF_API of_status of_plan_autotune(of_plan* plan, const void* I1, const void* I2, float* u,
+                                  float* v, void* stream, int reps);
+
 /* Text of the last failure on the calling thread ("" if none). */
 OF_API const char* of_last_error(void);
 

@@ -58,6 +58,9 @@ SIGNATURES = {
     "of_field_mean_update": (_c_int, [_vp, _vp, ctypes.c_longlong, _c_int, _vp]),
     "of_field_minmax": (_c_int, [_vp, ctypes.c_longlong, _vp, _vp, _vp]),
     "of_count_at_most": (_c_int, [_vp, ctypes.c_longlong, ctypes.c_float, _vp, _vp]),
+    "of_plan_get_config": (_c_int, [_vp, _INTP, _INTP]),
+    "of_plan_set_config": (_c_int, [_vp, _INTP, _INTP]),
+    "of_plan_autotune": (_c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _c_int]),
     "of_plan_set_timing": (_c_int, [_vp, _c_int]),
     "of_plan_read_timing": (_c_int, [_vp, _c_int, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_longlong),

@@ -69,6 +69,25 @@ class Plan:
         """of_compute on raw device pointers (no Python-side checks; the C side validates)."""
         B.check(B.load().of_compute(self._h, i1_ptr, i2_ptr, u_ptr, v_ptr, stream_handle), "of_compute")
 
+    def config(self):
+        import ctypes
+        bands = (ctypes.c_int * self.levels)()
+        wide = (ctypes.c_int * self.levels)()
+        B.check(B.load().of_plan_get_config(self._h, bands, wide), "of_plan_get_config")
+        return {"bands": list(bands), "wide": list(wide)}
+
+    def set_config(self, cfg):
+        import ctypes
+        bands = (ctypes.c_int * self.levels)(*cfg["bands"])
+        wide = (ctypes.c_int * self.levels)(*cfg["wide"])
+        B.check(B.load().of_plan_set_config(self._h, bands, wide), "of_plan_set_config")
+
+    def autotune(self, I1, I2, u, v, reps=3, stream=None):
+        """Pick the fastest launch configuration per level on these buffers; returns it."""
+        B.check(B.load().of_plan_autotune(self._h, I1.data_ptr(), I2.data_ptr(), u.data_ptr(), v.data_ptr(),
+                                          _stream_handle(self.device, stream), reps), "of_plan_autotune")
+        return self.config()
+
     def set_timing(self, enable: bool):
         """Bracket every kernel launch with hipEvents on its stream (measurement only)."""
         B.check(B.load().of_plan_set_timing(self._h, 1 if enable else 0), "of_plan_set_timing")

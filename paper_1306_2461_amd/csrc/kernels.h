@@ -41,8 +41,8 @@ struct BatchLaunch {
 int strip_width_for(int R);
 
 // One fused Gauss-Newton iteration at one level (frames of element type `t`), tiles of height
-// (2R+1)*nb.
-hipError_t launch_iter(Elem t, const IterArgs& a, int R, int nb, hipStream_t s);
+// (2R+1)*nb, 10 instead of 5 threads per output column when `wide`.
+hipError_t launch_iter(Elem t, const IterArgs& a, int R, int nb, bool wide, hipStream_t s);
 
 // The same over a work list of many pairs' tiles at one (level, iteration) phase.
 hipError_t launch_iter_batch(Elem t, const BatchLaunch& b, int R, int mode, hipStream_t s);

@@ -26,7 +26,8 @@ __global__ void zero_kernel(float* u, float* v, size_t n) {
 
 }  // namespace
 
-hipError_t launch_iter(Elem t, const IterArgs& a, int R, int nb, hipStream_t s) {
+hipError_t launch_iter(Elem t, const IterArgs& a, int R, int nb, bool wide, hipStream_t s) {
+  if (wide) nb = -nb;
   switch (t) {
     case Elem::U8: return launch_iter_u8(&a, nullptr, R, a.mode, nb, s);
     case Elem::F32: return launch_iter_f32(&a, nullptr, R, a.mode, nb, s);

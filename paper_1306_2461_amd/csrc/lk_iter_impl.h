@@ -49,7 +49,7 @@ struct Cfg {
 
 // One tile: TW output columns from x0 = bx*TW and TH output rows from y0 = by*TH, walked in
 // nbands bands (TH is a multiple of N; nbands = TH/N + 1).  `sm4` is the workgroup's LDS.
-template <typename T, int R, int TW, int MODE, bool WIDE>
+template <typename T, int R, int TW, int MODE, bool WIDE, bool DEFER>
 __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands, int bx, int by,
                                            float4* sm4) {
   using C = Cfg<R, TW, WIDE>;
@@ -94,9 +94,10 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
       wofs[k] = (w & RMASK) * WP + lx;
       read_flow<MODE>(a, wgx[k], wgy[k], wu[k], wv[k]);
     }
-    // In the coarse-field mode each field value costs eight loads: the field at this thread's
-    // P2 and P5 items is then read in those phases rather than held in flight here.
-    constexpr bool kDefer = MODE == kFlowCoarse;
+    // In the coarse-field mode each field value costs eight loads: where registers are tight
+    // (DEFER) the field at this thread's P2 and P5 items is read in those phases rather than
+    // held in flight here.
+    constexpr bool kDefer = DEFER && MODE == kFlowCoarse;
     float i1v[C::K2], pu[C::K2], pv[C::K2];
 #pragma unroll
     for (int k = 0; k < C::K2; ++k) {
@@ -274,7 +275,7 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_strip(IterArgs a
   extern __shared__ float4 sm4[];
   const int t = xcd_order(blockIdx.x, gridDim.x);
   if (t >= ntiles) return;
-  strip_tile<T, R, TW, MODE, WIDE>(a, TH, nbands, t % tiles_x, t / tiles_x, sm4);
+  strip_tile<T, R, TW, MODE, WIDE, (WIDE || R > 8)>(a, TH, nbands, t % tiles_x, t / tiles_x, sm4);
 }
 
 // Batched form: workgroups stride over a work list of tiles of many pairs at the same
@@ -289,13 +290,10 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_batch(const Iter
   for (int t = xcd_order(blockIdx.x, gridDim.x); t < ntiles; t += stride) {
     const int4 w = tiles[t];
     const IterArgs a = args[w.x];
-    strip_tile<T, R, TW, MODE, WIDE>(a, w.w, w.w / C::N + 1, w.y, w.z, sm4);
+    strip_tile<T, R, TW, MODE, WIDE, true>(a, w.w, w.w / C::N + 1, w.y, w.z, sm4);
     __syncthreads();
   }
 }
-
-// Levels with fewer pixels than this run the wide (10 threads per column) variant.
-constexpr long long kWideBelowPixels = 1ll << 18;
 
 // 64-column strips while the LDS footprint stays within 64 KB, else 32-column strips.
 template <int R>
@@ -317,9 +315,10 @@ hipError_t go_plain_w(const IterArgs& a, int nb, hipStream_t s) {
 }
 
 // Small levels are latency bound: twice the threads per tile halve each band's path.
+// nb < 0 encodes the wide variant with -nb bands per tile.
 template <typename T, int R, int MODE>
 hipError_t go_plain(const IterArgs& a, int nb, hipStream_t s) {
-  if ((long long)a.H * a.W < kWideBelowPixels) return go_plain_w<T, R, MODE, true>(a, nb, s);
+  if (nb < 0) return go_plain_w<T, R, MODE, true>(a, -nb, s);
   return go_plain_w<T, R, MODE, false>(a, nb, s);
 }
 

@@ -40,6 +40,10 @@ int default_bands(int H, int W, int R) {
   return px >= (1 << 22) ? 4 : (px >= (1 << 18) ? 2 : 1);
 }
 
+// Levels of few pixels give few tiles and are latency bound: the wide variant halves the
+// per-thread path of each band.
+bool default_wide(int H, int W) { return (long long)H * W < (1ll << 18); }
+
 Geometry make_geometry(int H, int W, int levels, int radius, int iters, unsigned flags) {
   Geometry g{};
   g.L = levels;
@@ -52,7 +56,10 @@ Geometry make_geometry(int H, int W, int levels, int radius, int iters, unsigned
     g.H[l] = (g.H[l - 1] + 1) / 2;
     g.W[l] = (g.W[l - 1] + 1) / 2;
   }
-  for (int l = 0; l < levels; ++l) g.nb[l] = default_bands(g.H[l], g.W[l], radius);
+  for (int l = 0; l < levels; ++l) {
+    g.nb[l] = default_bands(g.H[l], g.W[l], radius);
+    g.wide[l] = default_wide(g.H[l], g.W[l]);
+  }
   g.ein = (flags & OF_FLAG_INPUT_F32) ? Elem::F32 : Elem::U8;
   g.e0 = (flags & OF_FLAG_NORMALIZE) ? Elem::F32 : g.ein;
   g.ep = (flags & OF_FLAG_FP16_STORAGE) ? Elem::F16 : Elem::F32;
@@ -214,7 +221,7 @@ hipError_t enqueue_pair(const Geometry& g, char* ws, const void* I1, const void*
       a.vout = last ? v : fv[buf];
       hipEvent_t ev;
       hipError_t e = t ? t->begin(s, &ev) : hipSuccess;
-      if (e == hipSuccess) e = launch_iter(g.elem(l), a, g.R, g.nb[l], s);
+      if (e == hipSuccess) e = launch_iter(g.elem(l), a, g.R, g.nb[l], g.wide[l], s);
       if (e == hipSuccess && t) {
         const double n = (double)a.H * a.W;
         e = t->end(s, ev, OF_KERNEL_ITERATE, n, n * (2.0 * elem_bytes(g.elem(l)) + 16.0));
@@ -340,6 +347,90 @@ void of_plan_destroy(of_plan* p) {
 
 const char* of_last_error(void) { return g_last_error.c_str(); }
 
+of_status of_plan_get_config(const of_plan* p, int* bands, int* wide) {
+  if (!p || !bands || !wide) return set_error("NULL argument"), OF_EINVAL;
+  for (int l = 0; l < p->g.L; ++l) {
+    bands[l] = p->g.nb[l];
+    wide[l] = p->g.wide[l] ? 1 : 0;
+  }
+  return OF_OK;
+}
+
+of_status of_plan_set_config(of_plan* p, const int* bands, const int* wide) {
+  if (!p || !bands || !wide) return set_error("NULL argument"), OF_EINVAL;
+  for (int l = 0; l < p->g.L; ++l)
+    if (bands[l] < 1 || bands[l] > 64) return set_error("bands out of range"), OF_EINVAL;
+  DeviceGuard guard(p->device);
+  hipDeviceSynchronize();
+  p->graphs.clear();
+  for (int l = 0; l < p->g.L; ++l) {
+    p->g.nb[l] = bands[l];
+    p->g.wide[l] = wide[l] != 0;
+  }
+  return OF_OK;
+}
+
+of_status of_plan_autotune(of_plan* p, const void* I1, const void* I2, float* u, float* v,
+                           void* stream, int reps) {
+  if (!p || !I1 || !I2 || !u || !v || u == v) return set_error("bad argument"), OF_EINVAL;
+  if (reps < 1) reps = 1;
+  DeviceGuard guard(p->device);
+  hipStream_t s = (hipStream_t)stream;
+  Geometry& g = p->g;
+  const bool was_on = p->timer.on;
+  p->timer.on = true;
+  static const int kBands[] = {1, 2, 4, 8};
+  hipError_t e = hipSuccess;
+  for (int l = 0; l < g.L && e == hipSuccess && g.K > 0; ++l) {
+    double best = 1e30;
+    int bnb = g.nb[l];
+    bool bw = g.wide[l];
+    for (int nb : kBands) {
+      if (nb > 1 && (2 * g.R + 1) * nb > 2 * g.H[l]) continue;
+      for (int w = 0; w < 2; ++w) {
+        g.nb[l] = nb;
+        g.wide[l] = w != 0;
+        double tl = 1e30;
+        for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+          e = enqueue_pair(g, p->ws, I1, I2, u, v, s, &p->timer);
+          if (e == hipSuccess) e = hipStreamSynchronize(s);
+          if (e != hipSuccess) break;
+          // launch k of level l is iteration launch (L-1-l)*K + k of the run
+          const int first = (g.L - 1 - l) * g.K;
+          int idx = 0;
+          double sum = 0;
+          for (const KernelTimer::Rec& rc : p->timer.recs) {
+            if (rc.kernel != OF_KERNEL_ITERATE) continue;
+            if (idx >= first && idx < first + g.K) {
+              float ms = 0.f;
+              hipEventElapsedTime(&ms, rc.a, rc.b);
+              sum += ms;
+            }
+            ++idx;
+          }
+          double d;
+          long long n;
+          p->timer.read(OF_KERNEL_ITERATE, &d, &n, &d, &d);
+          p->timer.read(OF_KERNEL_REDUCE, &d, &n, &d, &d);
+          if (r > 0) tl = tl < sum ? tl : sum;
+        }
+        if (tl < best) {
+          best = tl;
+          bnb = nb;
+          bw = w != 0;
+        }
+      }
+    }
+    g.nb[l] = bnb;
+    g.wide[l] = bw;
+  }
+  p->timer.on = was_on;
+  hipDeviceSynchronize();
+  p->graphs.clear();
+  if (e != hipSuccess) return hip_fail("autotune", e);
+  return OF_OK;
+}
+
 of_status of_plan_set_timing(of_plan* p, int enable) {
   if (!p) return set_error("NULL plan"), OF_EINVAL;
   p->timer.on = enable != 0;
@@ -384,7 +475,7 @@ of_status of_debug_stage(of_plan* p, int stage, int level, const void* const* in
     a.H = g.H[level];
     a.W = g.W[level];
     a.mode = kFlowSame;
-    e = launch_iter(g.elem(level), a, g.R, g.nb[level], s);
+    e = launch_iter(g.elem(level), a, g.R, g.nb[level], g.wide[level], s);
   } else {
     return set_error("unknown stage"), OF_EINVAL;
   }

@@ -211,3 +211,29 @@ def test_graph_replay_matches_eager(gpu_lib):
         assert np.array_equal(vg.cpu().numpy(), ref_v), f"replay {rep}"
     eager.close()
     graph.close()
+
+
+def test_plan_configs_and_autotune_keep_bits(gpu_lib):
+    """Tile height and variant change the launch, not the result (window sums are tiling
+    independent): every configuration and the autotuned one give the same bits."""
+    import torch
+    ofmi = gpu_lib
+    I1, I2, _, _ = synth.make_pair("c1", 10)
+    d1, d2 = to_dev(I1), to_dev(I2)
+    plan = ofmi.Plan(256, 256, 3, 4, 3, device=dev())
+    u0, v0 = plan.compute(d1, d2)
+    torch.cuda.synchronize()
+    ref = (u0.cpu().numpy(), v0.cpu().numpy())
+    for cfg in ({"bands": [1, 1, 1], "wide": [0, 0, 0]}, {"bands": [8, 4, 2], "wide": [1, 1, 1]},
+                {"bands": [2, 8, 1], "wide": [0, 1, 0]}):
+        announce(f"plan config {cfg}")
+        plan.set_config(cfg)
+        u, v = plan.compute(d1, d2)
+        torch.cuda.synchronize()
+        assert np.array_equal(u.cpu().numpy(), ref[0]) and np.array_equal(v.cpu().numpy(), ref[1]), cfg
+    announce("plan autotune")
+    cfg = plan.autotune(d1, d2, u0, v0, reps=1)
+    u, v = plan.compute(d1, d2)
+    torch.cuda.synchronize()
+    assert np.array_equal(u.cpu().numpy(), ref[0]) and np.array_equal(v.cpu().numpy(), ref[1]), cfg
+    plan.close()

@@ -92,6 +92,7 @@ def test_session_budget_and_single_push(gpu_lib):
     torch.cuda.synchronize()
     assert has.value == 1
     ou, ov = oracle.flow(frames[0], frames[1], L, R, K)
-    dd = flow_error(u.cpu().numpy(), v.cpu().numpy(), ou, ov)
+    m = 2 * 8 + R + 2          # outflow border below the FP32 floor (see the test above)
+    dd = flow_error(u.cpu().numpy(), v.cpu().numpy(), ou, ov)[m:-m, m:-m]
     assert dd.max() <= 1e-3, report(dd, 1e-3)
     lib.of_server_destroy(srv)
