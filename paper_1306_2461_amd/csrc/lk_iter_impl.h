@@ -49,7 +49,9 @@ struct Cfg {
 
 // One tile: TW output columns from x0 = bx*TW and TH output rows from y0 = by*TH, walked in
 // nbands bands (TH is a multiple of N; nbands = TH/N + 1).  `sm4` is the workgroup's LDS.
-template <typename T, int R, int TW, int MODE, bool WIDE, bool DEFER>
+// INTERIOR: the tile's whole warped-frame region (the tile grown by r + 1 px, all bands)
+// lies inside the image, so no position needs clamping or an in-image test.
+template <typename T, int R, int TW, int MODE, bool WIDE, bool DEFER, bool INTERIOR>
 __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands, int bx, int by,
                                            float4* sm4) {
   using C = Cfg<R, TW, WIDE>;
@@ -89,8 +91,13 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     for (int k = 0; k < C::K1; ++k) {
       const int i = min(tid + k * NT, nw - 1);
       const int w = wfirst + i / WC, lx = i % WC;
-      wgx[k] = min(max(x0 - R - 1 + lx, 0), W - 1);
-      wgy[k] = min(max(y0 - R + w, 0), H - 1);
+      if constexpr (INTERIOR) {
+        wgx[k] = x0 - R - 1 + lx;
+        wgy[k] = y0 - R + w;
+      } else {
+        wgx[k] = min(max(x0 - R - 1 + lx, 0), W - 1);
+        wgy[k] = min(max(y0 - R + w, 0), H - 1);
+      }
       wofs[k] = (w & RMASK) * WP + lx;
       read_flow<MODE>(a, wgx[k], wgy[k], wu[k], wv[k]);
     }
@@ -102,8 +109,11 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
 #pragma unroll
     for (int k = 0; k < C::K2; ++k) {
       const int i = min(tid + k * NT, N * PC - 1);
-      const int gx = min(max(x0 - R + i % PC, 0), W - 1);
-      const int gy = min(max(y0 - R + tb + i / PC, 0), H - 1);
+      int gx = x0 - R + i % PC, gy = y0 - R + tb + i / PC;
+      if constexpr (!INTERIOR) {
+        gx = min(max(gx, 0), W - 1);
+        gy = min(max(gy, 0), H - 1);
+      }
       i1v[k] = ld(I1, (unsigned)gy * (unsigned)W + (unsigned)gx);
       if constexpr (!kDefer) read_flow<MODE>(a, gx, gy, pu[k], pv[k]);
     }
@@ -112,7 +122,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
 #pragma unroll
       for (int k = 0; k < C::K5; ++k) {
         const int i = min(tid + k * NT, N * TW - 1);
-        const int gx = min(x0 + i % TW, W - 1);
+        const int gx = INTERIOR ? x0 + i % TW : min(x0 + i % TW, W - 1);
         const int gy = min(max(y0 + tb + i / TW - 2 * R, 0), H - 1);
         read_flow<MODE>(a, gx, gy, cu[k], cv[k]);
       }
@@ -128,8 +138,11 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
 #pragma unroll
       for (int k = 0; k < C::K2; ++k) {
         const int i = min(tid + k * NT, N * PC - 1);
-        const int gx = min(max(x0 - R + i % PC, 0), W - 1);
-        const int gy = min(max(y0 - R + tb + i / PC, 0), H - 1);
+        int gx = x0 - R + i % PC, gy = y0 - R + tb + i / PC;
+        if constexpr (!INTERIOR) {
+          gx = min(max(gx, 0), W - 1);
+          gy = min(max(gy, 0), H - 1);
+        }
         read_flow<MODE>(a, gx, gy, pu[k], pv[k]);
       }
     }
@@ -141,7 +154,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
         const int t = tb + r;
         const int gx = x0 - R + c, gy = y0 - R + t;
         float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f, p4 = 0.f;
-        if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
+        if (INTERIOR || (gx >= 0 && gx < W && gy >= 0 && gy < H)) {
           const int s0 = t & RMASK, sm1 = (t - 1) & RMASK, sp1 = (t + 1) & RMASK;
           const float* row = w2 + s0 * WP + c + 1;
           const float ix = 0.5f * (row[1] - row[-1]);
@@ -232,7 +245,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
 #pragma unroll
       for (int k = 0; k < C::K5; ++k) {
         const int i = min(tid + k * NT, N * TW - 1);
-        const int gx = min(x0 + i % TW, W - 1);
+        const int gx = INTERIOR ? x0 + i % TW : min(x0 + i % TW, W - 1);
         const int gy = min(max(y0 + tb + i / TW - 2 * R, 0), H - 1);
         read_flow<MODE>(a, gx, gy, cu[k], cv[k]);
       }
@@ -244,7 +257,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
         const int r = i / TW, c = i % TW;
         const int j = tb + r - 2 * R;
         const int gx = x0 + c, gy = y0 + j;
-        if (j >= 0 && j < TH && gx < W && gy < H) {
+        if (j >= 0 && j < TH && (INTERIOR || (gx < W && gy < H))) {
           const float* s = hs + r * TW + c;
           float un, vn;
           solve_update(s[0], s[N * TW], s[2 * N * TW], s[3 * N * TW], s[4 * N * TW], cu[k],
@@ -261,6 +274,17 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
   }
 }
 
+// True when every warped-frame position of the tile (columns x0-R-1 .. x0+TW+R, rows
+// y0-R-1 .. y0-R+N*nbands) lies inside the image.
+template <int R, int TW>
+__device__ __forceinline__ bool tile_interior(const IterArgs& a, int TH, int nbands, int bx,
+                                              int by) {
+  constexpr int N = 2 * R + 1;
+  const int x0 = bx * TW, y0 = by * TH;
+  return x0 - R - 1 >= 0 && x0 + TW + R <= a.W - 1 && y0 - R - 1 >= 0 &&
+         y0 - R + N * nbands <= a.H - 1;
+}
+
 // Workgroup index -> work index so that the workgroups one XCD runs (hardware dispatch is
 // round-robin over the 8 XCDs) take a contiguous range of tiles, which share halos in L2.
 __device__ __forceinline__ int xcd_order(int b, int nblocks) {
@@ -275,7 +299,12 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_strip(IterArgs a
   extern __shared__ float4 sm4[];
   const int t = xcd_order(blockIdx.x, gridDim.x);
   if (t >= ntiles) return;
-  strip_tile<T, R, TW, MODE, WIDE, (WIDE || R > 8)>(a, TH, nbands, t % tiles_x, t / tiles_x, sm4);
+  const int bx = t % tiles_x, by = t / tiles_x;
+  constexpr bool kDefer = WIDE || R > 8;
+  if (R <= 8 && tile_interior<R, TW>(a, TH, nbands, bx, by))
+    strip_tile<T, R, TW, MODE, WIDE, kDefer, true>(a, TH, nbands, bx, by, sm4);
+  else
+    strip_tile<T, R, TW, MODE, WIDE, kDefer, false>(a, TH, nbands, bx, by, sm4);
 }
 
 // Batched form: workgroups stride over a work list of tiles of many pairs at the same
@@ -290,7 +319,11 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_batch(const Iter
   for (int t = xcd_order(blockIdx.x, gridDim.x); t < ntiles; t += stride) {
     const int4 w = tiles[t];
     const IterArgs a = args[w.x];
-    strip_tile<T, R, TW, MODE, WIDE, true>(a, w.w, w.w / C::N + 1, w.y, w.z, sm4);
+    const int nb = w.w / C::N + 1;
+    if (R <= 8 && tile_interior<R, TW>(a, w.w, nb, w.y, w.z))
+      strip_tile<T, R, TW, MODE, WIDE, true, true>(a, w.w, nb, w.y, w.z, sm4);
+    else
+      strip_tile<T, R, TW, MODE, WIDE, true, false>(a, w.w, nb, w.y, w.z, sm4);
     __syncthreads();
   }
 }
