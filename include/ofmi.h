@@ -113,8 +113,8 @@ OF_API void of_plan_destroy(of_plan* plan);
 
 /* Per-level launch configuration of a plan: bands[l] = tile height of the iteration kernel
  * in bands of 2r+1 rows (1..64), wide[l] = 1 to use 10 instead of 5 threads per output column
- * (shorter per-thread path; for levels with few tiles).  Arrays of `levels` entries.
- * set_config drops the plan's captured graphs.  Results do not depend on the configuration. */
+ * (the default: shorter per-thread path and twice the resident waves per CU).  Arrays of
+ * `levels` entries.  set_config drops the plan's captured graphs.  Results do not depend on the configuration. */
 OF_API of_status of_plan_get_config(const of_plan* plan, int* bands, int* wide);
 OF_API of_status of_plan_set_config(of_plan* plan, const int* bands, const int* wide);
 
@@ -176,14 +176,18 @@ OF_API of_status of_batch_compute(of_batch* b, const void* const* I1, const void
 
 /* Per-level launch configuration: bands[l] = tile height in bands of 2r+1 rows (1..64),
  * grid[l] = workgroups of the iteration launches (0 = one per tile, else a persistent grid
- * striding over the work list).  Arrays of `levels` entries.  set_config rebuilds the work
- * lists and drops captured graphs. */
-OF_API of_status of_batch_get_config(const of_batch* b, int* bands, int* grid);
-OF_API of_status of_batch_set_config(of_batch* b, const int* bands, const int* grid);
+ * striding over the work list), wide[l] = 1 for the wide tile variant (10 threads per output
+ * column), 0 for the narrow one (5), -1 for the default (wide: at 10 waves per workgroup it
+ * keeps about 30 waves per CU resident against 15 for the narrow one).
+ * Arrays of `levels` entries; `wide` may be NULL (get: not returned; set: -1 for every
+ * level).  set_config rebuilds the work lists and drops captured graphs. */
+OF_API of_status of_batch_get_config(const of_batch* b, int* bands, int* grid, int* wide);
+OF_API of_status of_batch_set_config(of_batch* b, const int* bands, const int* grid,
+                                     const int* wide);
 
 /* Autotuner: for each level in turn, times that level's iteration launches for every
- * candidate (bands in {1,2,4,8}, grid in {one per tile, 256, 512, 1024, 2048}) on the given
- * buffers (reps timed runs after one warm-up) and keeps the fastest.  Synchronises `stream`.
+ * candidate (bands in {1,2,4,8}, grid in {one per tile, 256, 512, 1024, 2048}, narrow or
+ * wide tiles) on the given buffers (reps timed runs after one warm-up) and keeps the fastest.  Synchronises `stream`.
  * The chosen configuration is read back with of_batch_get_config. */
 OF_API of_status of_batch_autotune(of_batch* b, const void* const* I1, const void* const* I2,
                                    float* const* u, float* const* v, void* stream, int reps);

@@ -37,8 +37,8 @@ SIGNATURES = {
     "of_batch_workspace_bytes": (_c_size, [_c_int, _INTP, _INTP, _c_int, _c_int, _c_int, _c_uint]),
     "of_batch_create": (_vp, [_c_int, _INTP, _INTP, _c_int, _c_int, _c_int, _c_uint, _vp, _c_size]),
     "of_batch_compute": (_c_int, [_vp, _VPP, _VPP, _VPP, _VPP, _vp]),
-    "of_batch_get_config": (_c_int, [_vp, _INTP, _INTP]),
-    "of_batch_set_config": (_c_int, [_vp, _INTP, _INTP]),
+    "of_batch_get_config": (_c_int, [_vp, _INTP, _INTP, _INTP]),
+    "of_batch_set_config": (_c_int, [_vp, _INTP, _INTP, _INTP]),
     "of_batch_autotune": (_c_int, [_vp, _VPP, _VPP, _VPP, _VPP, _vp, _c_int]),
     "of_batch_set_timing": (_c_int, [_vp, _c_int]),
     "of_batch_read_timing": (_c_int, [_vp, _c_int, ctypes.POINTER(ctypes.c_double),

@@ -206,14 +206,18 @@ class Batch:
         import ctypes
         bands = (ctypes.c_int * self.levels)()
         grid = (ctypes.c_int * self.levels)()
-        B.check(B.load().of_batch_get_config(self._h, bands, grid), "of_batch_get_config")
-        return {"bands": list(bands), "grid": list(grid)}
+        wide = (ctypes.c_int * self.levels)()
+        B.check(B.load().of_batch_get_config(self._h, bands, grid, wide), "of_batch_get_config")
+        return {"bands": list(bands), "grid": list(grid), "wide": list(wide)}
 
     def set_config(self, cfg):
+        """``cfg``: {"bands": [...], "grid": [...], "wide": [...] (optional; -1 = default
+        (wide), 0 = narrow, 1 = wide tiles)}, one entry per level."""
         import ctypes
         bands = (ctypes.c_int * self.levels)(*cfg["bands"])
         grid = (ctypes.c_int * self.levels)(*cfg["grid"])
-        B.check(B.load().of_batch_set_config(self._h, bands, grid), "of_batch_set_config")
+        wide = (ctypes.c_int * self.levels)(*cfg.get("wide", [-1] * self.levels))
+        B.check(B.load().of_batch_set_config(self._h, bands, grid, wide), "of_batch_set_config")
 
     def set_timing(self, enable: bool):
         B.check(B.load().of_batch_set_timing(self._h, 1 if enable else 0), "of_batch_set_timing")

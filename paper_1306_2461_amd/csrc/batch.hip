@@ -22,12 +22,11 @@ namespace {
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Launches with fewer tiles than this (under two per CU) use the wide tile variant.
-constexpr int kWideBelowTiles = 512;
 
 struct LevelCfg {
   int nb;     // tile height in bands of 2R+1 rows
   int grid;   // iteration workgroups; 0 = one per tile
+  int wide;   // 1 = wide tile variant, 0 = narrow, -1 = default (wide)
 };
 
 }  // namespace
@@ -225,7 +224,7 @@ hipError_t enqueue_batch(of_batch* b, char* blk, float* const* u, float* const* 
       bl.ntiles = b->ntiles[l];
       bl.grid = b->cfg[l].grid > 0 ? std::min(b->cfg[l].grid, bl.ntiles) : bl.ntiles;
       bl.grid = (bl.grid + 7) / 8 * 8;
-      bl.wide = bl.ntiles < kWideBelowTiles;
+      bl.wide = b->cfg[l].wide != 0;
       const int mode = k > 0 ? kFlowSame : (l == L - 1 ? kFlowZero : kFlowCoarse);
       hipEvent_t ev = nullptr;
       hipError_t e = t ? t->begin(s, &ev) : hipSuccess;
@@ -361,7 +360,7 @@ of_batch* of_batch_create(int n, const int* H, const int* W, int levels, int rad
     }
     b->owns_ws = true;
   }
-  for (int l = 0; l < levels; ++l) b->cfg[l] = {default_batch_bands(b, l), 0};
+  for (int l = 0; l < levels; ++l) b->cfg[l] = {default_batch_bands(b, l), 0, -1};
   e = upload_tiles(b);
   for (int l = 1; l < levels && e == hipSuccess; ++l)
     e = hipMemcpy(b->ws + b->items_at[l], items[l].data(), items[l].size() * sizeof(int2),
@@ -448,23 +447,24 @@ of_status of_batch_read_timing(of_batch* b, int kernel, double* total_ms, long l
   return OF_OK;
 }
 
-of_status of_batch_get_config(const of_batch* b, int* bands, int* grid) {
+of_status of_batch_get_config(const of_batch* b, int* bands, int* grid, int* wide) {
   if (!b || !bands || !grid) return set_error("NULL argument"), OF_EINVAL;
   for (int l = 0; l < b->L; ++l) {
     bands[l] = b->cfg[l].nb;
     grid[l] = b->cfg[l].grid;
+    if (wide) wide[l] = b->cfg[l].wide;
   }
   return OF_OK;
 }
 
-of_status of_batch_set_config(of_batch* b, const int* bands, const int* grid) {
+of_status of_batch_set_config(of_batch* b, const int* bands, const int* grid, const int* wide) {
   if (!b || !bands || !grid) return set_error("NULL argument"), OF_EINVAL;
   for (int l = 0; l < b->L; ++l)
-    if (bands[l] < 1 || bands[l] > 64 || grid[l] < 0)
+    if (bands[l] < 1 || bands[l] > 64 || grid[l] < 0 || (wide && (wide[l] < -1 || wide[l] > 1)))
       return set_error("config out of range"), OF_EINVAL;
   DeviceGuard guard(b->device);
   drop_graphs(b);
-  for (int l = 0; l < b->L; ++l) b->cfg[l] = {bands[l], grid[l]};
+  for (int l = 0; l < b->L; ++l) b->cfg[l] = {bands[l], grid[l], wide ? wide[l] : -1};
   hipError_t e = upload_tiles(b);
   if (e != hipSuccess) return hip_fail("tile lists", e);
   return OF_OK;
@@ -480,6 +480,7 @@ of_status of_batch_autotune(of_batch* b, const void* const* I1, const void* cons
   b->timer.on = true;
   static const int kBands[] = {1, 2, 4, 8};
   static const int kGrid[] = {0, 256, 512, 1024, 2048};
+  static const int kWide[] = {0, 1};
   hipError_t e = hipSuccess;
   // Coordinate descent, one level at a time: the iteration time of that level only.
   for (int l = 0; l < b->L && e == hipSuccess; ++l) {
@@ -489,8 +490,9 @@ of_status of_batch_autotune(of_batch* b, const void* const* I1, const void* cons
     LevelCfg bestc = b->cfg[l];
     for (int nb : kBands) {
       if (nb > 1 && (2 * b->R + 1) * nb > 2 * maxH) continue;
-      for (int gr : kGrid) {
-        b->cfg[l] = {nb, gr};
+      for (int gr : kGrid)
+      for (int wd : kWide) {
+        b->cfg[l] = {nb, gr, wd};
         e = upload_tiles(b);
         if (e != hipSuccess) break;
         double tl = 1e30;
@@ -521,7 +523,7 @@ of_status of_batch_autotune(of_batch* b, const void* const* I1, const void* cons
         }
         if (e == hipSuccess && tl < best) {
           best = tl;
-          bestc = {nb, gr};
+          bestc = {nb, gr, wd};
         }
       }
     }

@@ -27,23 +27,32 @@ struct IterArgs {
 };
 
 // Element access by an unsigned 32-bit element index whose byte offset is formed in 32 bits
-// (planes are below 4 GiB): with the base pointer in scalar registers this selects the
-// scalar-base + 32-bit vector-offset global addressing form.
+// (planes are below 4 GiB), through the global address space: with the base pointer in
+// scalar registers this selects the scalar-base + 32-bit vector-offset global addressing
+// form, also where the pointer itself was read from memory (work lists) and the compiler
+// could not infer the address space (it would otherwise emit flat accesses).
 template <typename T>
-__device__ __forceinline__ const T& at(const T* p, unsigned i) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + i * (unsigned)sizeof(T));
+using global_t = __attribute__((address_space(1))) T;
+
+template <typename T>
+__device__ __forceinline__ const global_t<T>& at(const T* p, unsigned i) {
+  return *((const global_t<T>*)((const global_t<char>*)p + i * (unsigned)sizeof(T)));
 }
 template <typename T>
-__device__ __forceinline__ T& at(T* p, unsigned i) {
-  return *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + i * (unsigned)sizeof(T));
+__device__ __forceinline__ global_t<T>& at(T* p, unsigned i) {
+  return *((global_t<T>*)((global_t<char>*)p + i * (unsigned)sizeof(T)));
 }
 
 __device__ __forceinline__ float ld(const uint8_t* p, unsigned i) { return (float)at(p, i); }
 __device__ __forceinline__ float ld(const float* p, unsigned i) { return at(p, i); }
-__device__ __forceinline__ float ld(const __half* p, unsigned i) { return __half2float(at(p, i)); }
+__device__ __forceinline__ float ld(const __half* p, unsigned i) {
+  return __half2float(__ushort_as_half(at(reinterpret_cast<const unsigned short*>(p), i)));
+}
 
 __device__ __forceinline__ void st(float* p, unsigned i, float x) { at(p, i) = x; }
-__device__ __forceinline__ void st(__half* p, unsigned i, float x) { at(p, i) = __float2half_rn(x); }
+__device__ __forceinline__ void st(__half* p, unsigned i, float x) {
+  at(reinterpret_cast<unsigned short*>(p), i) = __half_as_ushort(__float2half_rn(x));
+}
 
 // Integer base and fraction of the sample coordinate x + d along one axis of length n,
 // clamped into [0, n-1].  Splitting d = floor(d) + frac keeps the coordinate exact in FP32
