@@ -70,6 +70,16 @@ typedef enum {
                                           of_normalize; radius OF_NORMALIZE_RADIUS, eps
                                           OF_NORMALIZE_EPS) before the pyramid */
 
+/* Tile variants of the fused iteration kernel (launch configuration; results do not depend
+ * on them).  NARROW: 5 threads per output column.  WIDE: 10 threads per output column with
+ * per-thread item indices held in registers (shortest dependent path per band, for launches
+ * of about one tile per CU).  WIDE_LEAN: 10 threads per output column, indices recomputed
+ * every band (fewer live registers, so two workgroups share a CU, for launches of many
+ * tiles). */
+#define OF_TILE_NARROW 0
+#define OF_TILE_WIDE 1
+#define OF_TILE_WIDE_LEAN 2
+
 #define OF_MAX_LEVELS 12
 #define OF_MAX_RADIUS 12
 #define OF_MAX_ITERS 1000
@@ -112,15 +122,16 @@ OF_API of_status of_compute(of_plan* plan, const void* I1, const void* I2, float
 OF_API void of_plan_destroy(of_plan* plan);
 
 /* Per-level launch configuration of a plan: bands[l] = tile height of the iteration kernel
- * in bands of 2r+1 rows (1..64), wide[l] = 1 to use 10 instead of 5 threads per output column
- * (the default: shorter per-thread path and twice the resident waves per CU).  Arrays of
- * `levels` entries.  set_config drops the plan's captured graphs.  Results do not depend on the configuration. */
-OF_API of_status of_plan_get_config(const of_plan* plan, int* bands, int* wide);
-OF_API of_status of_plan_set_config(of_plan* plan, const int* bands, const int* wide);
+ * in bands of 2r+1 rows (1..64), variant[l] = OF_TILE_* (default: WIDE for levels of under
+ * 384 tiles, else WIDE_LEAN).  Arrays of `levels` entries.  set_config drops the plan's
+ * captured graphs; OF_EINVAL for values out of range.  Results do not depend on the
+ * configuration. */
+OF_API of_status of_plan_get_config(const of_plan* plan, int* bands, int* variant);
+OF_API of_status of_plan_set_config(of_plan* plan, const int* bands, const int* variant);
 
 /* Autotuner: for each level in turn, times that level's iteration launches for bands in
- * {1,2,4,8} x wide in {0,1} on the given buffers (reps timed runs after one warm-up) and
- * keeps the fastest.  Synchronises `stream`; writes u, v. */
+ * {1,2,4,8} x the three tile variants on the given buffers (reps timed runs after one
+ * warm-up) and keeps the fastest.  Synchronises `stream`; writes u, v. */
 OF_API of_status of_plan_autotune(of_plan* plan, const void* I1, const void* I2, float* u,
                                   float* v, void* stream, int reps);
 
@@ -176,19 +187,19 @@ OF_API of_status of_batch_compute(of_batch* b, const void* const* I1, const void
 
 /* Per-level launch configuration: bands[l] = tile height in bands of 2r+1 rows (1..64),
  * grid[l] = workgroups of the iteration launches (0 = one per tile, else a persistent grid
- * striding over the work list), wide[l] = 1 for the wide tile variant (10 threads per output
- * column), 0 for the narrow one (5), -1 for the default (wide: at 10 waves per workgroup it
- * keeps about 30 waves per CU resident against 15 for the narrow one).
- * Arrays of `levels` entries; `wide` may be NULL (get: not returned; set: -1 for every
- * level).  set_config rebuilds the work lists and drops captured graphs. */
-OF_API of_status of_batch_get_config(const of_batch* b, int* bands, int* grid, int* wide);
+ * striding over the work list), variant[l] = OF_TILE_* or -1 for the default (WIDE for
+ * launches of under 384 tiles, else WIDE_LEAN).  Arrays of `levels` entries; `variant` may
+ * be NULL (get: not returned; set: -1 for every level).  set_config rebuilds the work lists
+ * and drops captured graphs. */
+OF_API of_status of_batch_get_config(const of_batch* b, int* bands, int* grid, int* variant);
 OF_API of_status of_batch_set_config(of_batch* b, const int* bands, const int* grid,
-                                     const int* wide);
+                                     const int* variant);
 
 /* Autotuner: for each level in turn, times that level's iteration launches for every
- * candidate (bands in {1,2,4,8}, grid in {one per tile, 256, 512, 1024, 2048}, narrow or
- * wide tiles) on the given buffers (reps timed runs after one warm-up) and keeps the fastest.  Synchronises `stream`.
- * The chosen configuration is read back with of_batch_get_config. */
+ * candidate (bands in {1,2,4,8}, grid in {one per tile, 256, 512, 1024, 2048}, the three
+ * tile variants) on the given buffers (reps timed runs after one warm-up) and keeps the
+ * fastest.  Synchronises `stream`.  The chosen configuration is read back with
+ * of_batch_get_config. */
 OF_API of_status of_batch_autotune(of_batch* b, const void* const* I1, const void* const* I2,
                                    float* const* u, float* const* v, void* stream, int reps);
 

@@ -21,6 +21,9 @@ OF_STAGE_REDUCE = 0
 OF_STAGE_ITERATE = 1
 OF_KERNEL_ITERATE = 0
 OF_KERNEL_REDUCE = 1
+OF_TILE_NARROW = 0
+OF_TILE_WIDE = 1
+OF_TILE_WIDE_LEAN = 2
 
 # exported symbol -> (restype, argtypes)
 _c_int, _c_uint, _c_size, _vp = ctypes.c_int, ctypes.c_uint, ctypes.c_size_t, ctypes.c_void_p

@@ -72,15 +72,15 @@ class Plan:
     def config(self):
         import ctypes
         bands = (ctypes.c_int * self.levels)()
-        wide = (ctypes.c_int * self.levels)()
-        B.check(B.load().of_plan_get_config(self._h, bands, wide), "of_plan_get_config")
-        return {"bands": list(bands), "wide": list(wide)}
+        variant = (ctypes.c_int * self.levels)()
+        B.check(B.load().of_plan_get_config(self._h, bands, variant), "of_plan_get_config")
+        return {"bands": list(bands), "variant": list(variant)}
 
     def set_config(self, cfg):
         import ctypes
         bands = (ctypes.c_int * self.levels)(*cfg["bands"])
-        wide = (ctypes.c_int * self.levels)(*cfg["wide"])
-        B.check(B.load().of_plan_set_config(self._h, bands, wide), "of_plan_set_config")
+        variant = (ctypes.c_int * self.levels)(*cfg["variant"])
+        B.check(B.load().of_plan_set_config(self._h, bands, variant), "of_plan_set_config")
 
     def autotune(self, I1, I2, u, v, reps=3, stream=None):
         """Pick the fastest launch configuration per level on these buffers; returns it."""
@@ -206,18 +206,18 @@ class Batch:
         import ctypes
         bands = (ctypes.c_int * self.levels)()
         grid = (ctypes.c_int * self.levels)()
-        wide = (ctypes.c_int * self.levels)()
-        B.check(B.load().of_batch_get_config(self._h, bands, grid, wide), "of_batch_get_config")
-        return {"bands": list(bands), "grid": list(grid), "wide": list(wide)}
+        variant = (ctypes.c_int * self.levels)()
+        B.check(B.load().of_batch_get_config(self._h, bands, grid, variant), "of_batch_get_config")
+        return {"bands": list(bands), "grid": list(grid), "variant": list(variant)}
 
     def set_config(self, cfg):
-        """``cfg``: {"bands": [...], "grid": [...], "wide": [...] (optional; -1 = default
-        (wide), 0 = narrow, 1 = wide tiles)}, one entry per level."""
+        """``cfg``: {"bands": [...], "grid": [...], "variant": [...] (optional; -1 = by tile
+        count, else one of OF_TILE_NARROW, OF_TILE_WIDE, OF_TILE_WIDE_LEAN)}, one entry per level."""
         import ctypes
         bands = (ctypes.c_int * self.levels)(*cfg["bands"])
         grid = (ctypes.c_int * self.levels)(*cfg["grid"])
-        wide = (ctypes.c_int * self.levels)(*cfg.get("wide", [-1] * self.levels))
-        B.check(B.load().of_batch_set_config(self._h, bands, grid, wide), "of_batch_set_config")
+        variant = (ctypes.c_int * self.levels)(*cfg.get("variant", [-1] * self.levels))
+        B.check(B.load().of_batch_set_config(self._h, bands, grid, variant), "of_batch_set_config")
 
     def set_timing(self, enable: bool):
         B.check(B.load().of_batch_set_timing(self._h, 1 if enable else 0), "of_batch_set_timing")

@@ -26,7 +26,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct LevelCfg {
   int nb;     // tile height in bands of 2R+1 rows
   int grid;   // iteration workgroups; 0 = one per tile
-  int wide;   // 1 = wide tile variant, 0 = narrow, -1 = default (wide)
+  int variant;   // TileVariant, or -1: by tile count
 };
 
 }  // namespace
@@ -224,7 +224,7 @@ hipError_t enqueue_batch(of_batch* b, char* blk, float* const* u, float* const* 
       bl.ntiles = b->ntiles[l];
       bl.grid = b->cfg[l].grid > 0 ? std::min(b->cfg[l].grid, bl.ntiles) : bl.ntiles;
       bl.grid = (bl.grid + 7) / 8 * 8;
-      bl.wide = b->cfg[l].wide != 0;
+      bl.variant = b->cfg[l].variant >= 0 ? b->cfg[l].variant : default_tile_variant(bl.ntiles);
       const int mode = k > 0 ? kFlowSame : (l == L - 1 ? kFlowZero : kFlowCoarse);
       hipEvent_t ev = nullptr;
       hipError_t e = t ? t->begin(s, &ev) : hipSuccess;
@@ -447,24 +447,25 @@ of_status of_batch_read_timing(of_batch* b, int kernel, double* total_ms, long l
   return OF_OK;
 }
 
-of_status of_batch_get_config(const of_batch* b, int* bands, int* grid, int* wide) {
+of_status of_batch_get_config(const of_batch* b, int* bands, int* grid, int* variant) {
   if (!b || !bands || !grid) return set_error("NULL argument"), OF_EINVAL;
   for (int l = 0; l < b->L; ++l) {
     bands[l] = b->cfg[l].nb;
     grid[l] = b->cfg[l].grid;
-    if (wide) wide[l] = b->cfg[l].wide;
+    if (variant) variant[l] = b->cfg[l].variant;
   }
   return OF_OK;
 }
 
-of_status of_batch_set_config(of_batch* b, const int* bands, const int* grid, const int* wide) {
+of_status of_batch_set_config(of_batch* b, const int* bands, const int* grid, const int* variant) {
   if (!b || !bands || !grid) return set_error("NULL argument"), OF_EINVAL;
   for (int l = 0; l < b->L; ++l)
-    if (bands[l] < 1 || bands[l] > 64 || grid[l] < 0 || (wide && (wide[l] < -1 || wide[l] > 1)))
+    if (bands[l] < 1 || bands[l] > 64 || grid[l] < 0 ||
+        (variant && (variant[l] < -1 || variant[l] > kTileWideLean)))
       return set_error("config out of range"), OF_EINVAL;
   DeviceGuard guard(b->device);
   drop_graphs(b);
-  for (int l = 0; l < b->L; ++l) b->cfg[l] = {bands[l], grid[l], wide ? wide[l] : -1};
+  for (int l = 0; l < b->L; ++l) b->cfg[l] = {bands[l], grid[l], variant ? variant[l] : -1};
   hipError_t e = upload_tiles(b);
   if (e != hipSuccess) return hip_fail("tile lists", e);
   return OF_OK;
@@ -480,7 +481,7 @@ of_status of_batch_autotune(of_batch* b, const void* const* I1, const void* cons
   b->timer.on = true;
   static const int kBands[] = {1, 2, 4, 8};
   static const int kGrid[] = {0, 256, 512, 1024, 2048};
-  static const int kWide[] = {0, 1};
+  static const int kVariant[] = {kTileNarrow, kTileWide, kTileWideLean};
   hipError_t e = hipSuccess;
   // Coordinate descent, one level at a time: the iteration time of that level only.
   for (int l = 0; l < b->L && e == hipSuccess; ++l) {
@@ -491,7 +492,7 @@ of_status of_batch_autotune(of_batch* b, const void* const* I1, const void* cons
     for (int nb : kBands) {
       if (nb > 1 && (2 * b->R + 1) * nb > 2 * maxH) continue;
       for (int gr : kGrid)
-      for (int wd : kWide) {
+      for (int wd : kVariant) {
         b->cfg[l] = {nb, gr, wd};
         e = upload_tiles(b);
         if (e != hipSuccess) break;

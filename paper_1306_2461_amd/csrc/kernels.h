@@ -27,6 +27,14 @@ hipError_t launch_reduce_batch(Elem tin, Elem tout, const ReduceJob* jobs, const
 hipError_t launch_reduce(Elem tin, Elem tout, const void* in1, const void* in2, int H, int W,
                          void* out1, void* out2, int Ho, int Wo, hipStream_t s);
 
+// Tile variants of the iteration kernel:
+//   narrow     5 threads per output column, item indices recomputed every band;
+//   wide       10 threads per output column, item indices kept in registers (shortest
+//              dependent path per band: launches with about one tile per CU);
+//   wide lean  10 threads per output column, indices recomputed every band (fewer live
+//              registers, so more resident workgroups: launches with many tiles).
+enum TileVariant : int { kTileNarrow = 0, kTileWide = 1, kTileWideLean = 2 };
+
 // Batched iteration launch: `grid` workgroups stride over `ntiles` work items
 // (pair, tile x, tile y, tile height) with per-pair arguments args[pair] (device arrays).
 struct BatchLaunch {
@@ -34,15 +42,15 @@ struct BatchLaunch {
   const int4* tiles;
   int ntiles;
   int grid;
-  bool wide;   // 10 instead of 5 threads per output column (latency-bound launches)
+  int variant;   // TileVariant
 };
 
 // Strip width (output columns per tile) and band height of the iteration kernel for radius R.
 int strip_width_for(int R);
 
 // One fused Gauss-Newton iteration at one level (frames of element type `t`), tiles of height
-// (2R+1)*nb, 10 instead of 5 threads per output column when `wide`.
-hipError_t launch_iter(Elem t, const IterArgs& a, int R, int nb, bool wide, hipStream_t s);
+// (2R+1)*nb, tile variant `variant` (TileVariant).
+hipError_t launch_iter(Elem t, const IterArgs& a, int R, int nb, int variant, hipStream_t s);
 
 // The same over a work list of many pairs' tiles at one (level, iteration) phase.
 hipError_t launch_iter_batch(Elem t, const BatchLaunch& b, int R, int mode, hipStream_t s);

@@ -3,9 +3,12 @@
 
 namespace ofmi {
 
-hipError_t launch_iter_u8(const IterArgs* a, const BatchLaunch* b, int R, int mode, int nb, hipStream_t s);
-hipError_t launch_iter_f32(const IterArgs* a, const BatchLaunch* b, int R, int mode, int nb, hipStream_t s);
-hipError_t launch_iter_f16(const IterArgs* a, const BatchLaunch* b, int R, int mode, int nb, hipStream_t s);
+hipError_t launch_iter_u8(const IterArgs* a, const BatchLaunch* b, int R, int mode, int nb,
+                          int variant, hipStream_t s);
+hipError_t launch_iter_f32(const IterArgs* a, const BatchLaunch* b, int R, int mode, int nb,
+                          int variant, hipStream_t s);
+hipError_t launch_iter_f16(const IterArgs* a, const BatchLaunch* b, int R, int mode, int nb,
+                          int variant, hipStream_t s);
 
 int strip_width_for(int R) {
   // Mirrors strip_width<R>(): the LDS footprint of 64-column strips stays within 64 KB for
@@ -26,12 +29,11 @@ __global__ void zero_kernel(float* u, float* v, size_t n) {
 
 }  // namespace
 
-hipError_t launch_iter(Elem t, const IterArgs& a, int R, int nb, bool wide, hipStream_t s) {
-  if (wide) nb = -nb;
+hipError_t launch_iter(Elem t, const IterArgs& a, int R, int nb, int variant, hipStream_t s) {
   switch (t) {
-    case Elem::U8: return launch_iter_u8(&a, nullptr, R, a.mode, nb, s);
-    case Elem::F32: return launch_iter_f32(&a, nullptr, R, a.mode, nb, s);
-    case Elem::F16: return launch_iter_f16(&a, nullptr, R, a.mode, nb, s);
+    case Elem::U8: return launch_iter_u8(&a, nullptr, R, a.mode, nb, variant, s);
+    case Elem::F32: return launch_iter_f32(&a, nullptr, R, a.mode, nb, variant, s);
+    case Elem::F16: return launch_iter_f16(&a, nullptr, R, a.mode, nb, variant, s);
   }
   return hipErrorInvalidValue;
 }
@@ -39,9 +41,9 @@ hipError_t launch_iter(Elem t, const IterArgs& a, int R, int nb, bool wide, hipS
 hipError_t launch_iter_batch(Elem t, const BatchLaunch& b, int R, int mode, hipStream_t s) {
   if (b.ntiles <= 0) return hipSuccess;
   switch (t) {
-    case Elem::U8: return launch_iter_u8(nullptr, &b, R, mode, 0, s);
-    case Elem::F32: return launch_iter_f32(nullptr, &b, R, mode, 0, s);
-    case Elem::F16: return launch_iter_f16(nullptr, &b, R, mode, 0, s);
+    case Elem::U8: return launch_iter_u8(nullptr, &b, R, mode, 0, b.variant, s);
+    case Elem::F32: return launch_iter_f32(nullptr, &b, R, mode, 0, b.variant, s);
+    case Elem::F16: return launch_iter_f16(nullptr, &b, R, mode, 0, b.variant, s);
   }
   return hipErrorInvalidValue;
 }

@@ -4,8 +4,8 @@
 namespace ofmi {
 
 hipError_t launch_iter_f32(const IterArgs* a, const BatchLaunch* b, int R, int mode, int nb,
-                            hipStream_t s) {
-  return launch_iter_t<float>(a, b, R, mode, nb, s);
+                          int variant, hipStream_t s) {
+  return launch_iter_t<float>(a, b, R, mode, nb, variant, s);
 }
 
 }  // namespace ofmi

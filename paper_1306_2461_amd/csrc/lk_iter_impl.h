@@ -51,7 +51,11 @@ struct Cfg {
 // nbands bands (TH is a multiple of N; nbands = TH/N + 1).  `sm4` is the workgroup's LDS.
 // INTERIOR: the tile's whole warped-frame region (the tile grown by r + 1 px, all bands)
 // lies inside the image, so no position needs clamping or an in-image test.
-template <typename T, int R, int TW, int MODE, bool WIDE, bool DEFER, bool INTERIOR>
+// LEAN: the item indices are recomputed every band instead of being kept in registers
+// across the band loop: a few more VALU instructions per band for far fewer live registers,
+// i.e. more resident workgroups per CU (launches with many tiles); without it each band's
+// dependent path is shorter (launches with about one tile per CU).
+template <typename T, int R, int TW, int MODE, bool WIDE, bool DEFER, bool INTERIOR, bool LEAN>
 __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands, int bx, int by,
                                            float4* sm4) {
   using C = Cfg<R, TW, WIDE>;
@@ -62,7 +66,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
   float* hs = pr;                               // [5][N][TW] horizontal, then window sums
   float* w2 = pr + 5 * N * PP;                  // [RING][WP] warped frame ring
 
-  const int tid = threadIdx.x;
+  const int tid0 = threadIdx.x;
   const int H = a.H, W = a.W;
   const int x0 = bx * TW;
   const int y0 = by * TH;
@@ -70,7 +74,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
   const T* __restrict__ I2 = (const T*)a.I2;
 
   // P4 ownership: channel and column of this thread (the first 5*TW threads).
-  const int vk = tid / TW, vc = tid - vk * TW;
+  const int vk = tid0 / TW, vc = tid0 - vk * TW;
   const bool p4 = vk < 5;
   float prev[N];
 #pragma unroll
@@ -78,6 +82,10 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
 
   for (int b = 0; b < nbands; ++b) {
     const int tb = N * b;                        // first product row of the band
+    // LEAN: the thread index is re-materialised per band, opaque to the optimiser, so the
+    // item indices derived from it are not hoisted out of the loop.
+    int tid = tid0;
+    if constexpr (LEAN) asm volatile("" : "+v"(tid));
     // ---------------------------------------------------------------- P1
     // Every global load of the band is issued here, branch-free (clamped addresses; results
     // for items outside the image or the band are discarded), in two rounds: the field at the
@@ -221,22 +229,17 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     __syncthreads();
     // ---------------------------------------------------------------- P4
     if (p4) {
-      float cur[N];
       float* col = hs + vk * N * TW + vc;
+      // prev[r] <- prev[r] + ... + prev[N-1] (suffix sums of the previous band, in place)
 #pragma unroll
-      for (int r = 0; r < N; ++r) cur[r] = col[r * TW];
-      // suffix sums of the previous band: suf[r] = prev[r] + ... + prev[N-1]
-      float suf[N + 1];
-      suf[N] = 0.f;
-      suf[N - 1] = prev[N - 1];
-#pragma unroll
-      for (int r = N - 2; r >= 0; --r) suf[r] = suf[r + 1] + prev[r];
+      for (int r = N - 2; r >= 0; --r) prev[r] += prev[r + 1];
       float pre = 0.f;
 #pragma unroll
       for (int r = 0; r < N; ++r) {
-        pre = r == 0 ? cur[0] : pre + cur[r];
-        col[r * TW] = r + 1 < N ? suf[r + 1] + pre : pre;
-        prev[r] = cur[r];
+        const float c = col[r * TW];
+        pre = r == 0 ? c : pre + c;
+        col[r * TW] = r + 1 < N ? prev[r + 1] + pre : pre;
+        prev[r] = c;
       }
     }
     __syncthreads();
@@ -293,7 +296,7 @@ __device__ __forceinline__ int xcd_order(int b, int nblocks) {
   return (b % kXcd) * per + b / kXcd;
 }
 
-template <typename T, int R, int TW, int MODE, bool WIDE>
+template <typename T, int R, int TW, int MODE, bool WIDE, bool LEAN>
 __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_strip(IterArgs a, int TH, int nbands,
                                                                       int tiles_x, int ntiles) {
   extern __shared__ float4 sm4[];
@@ -302,14 +305,14 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_strip(IterArgs a
   const int bx = t % tiles_x, by = t / tiles_x;
   constexpr bool kDefer = WIDE || R > 8;
   if (R <= 8 && tile_interior<R, TW>(a, TH, nbands, bx, by))
-    strip_tile<T, R, TW, MODE, WIDE, kDefer, true>(a, TH, nbands, bx, by, sm4);
+    strip_tile<T, R, TW, MODE, WIDE, kDefer, true, LEAN>(a, TH, nbands, bx, by, sm4);
   else
-    strip_tile<T, R, TW, MODE, WIDE, kDefer, false>(a, TH, nbands, bx, by, sm4);
+    strip_tile<T, R, TW, MODE, WIDE, kDefer, false, LEAN>(a, TH, nbands, bx, by, sm4);
 }
 
 // Batched form: workgroups stride over a work list of tiles of many pairs at the same
 // (level, iteration) phase.  Work item = (pair, tile x, tile y, tile height).
-template <typename T, int R, int TW, int MODE, bool WIDE>
+template <typename T, int R, int TW, int MODE, bool WIDE, bool LEAN>
 __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_batch(const IterArgs* __restrict__ args,
                                                                       const int4* __restrict__ tiles,
                                                                       int ntiles) {
@@ -321,9 +324,9 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_batch(const Iter
     const IterArgs a = args[w.x];
     const int nb = w.w / C::N + 1;
     if (R <= 8 && tile_interior<R, TW>(a, w.w, nb, w.y, w.z))
-      strip_tile<T, R, TW, MODE, WIDE, true, true>(a, w.w, nb, w.y, w.z, sm4);
+      strip_tile<T, R, TW, MODE, WIDE, true, true, LEAN>(a, w.w, nb, w.y, w.z, sm4);
     else
-      strip_tile<T, R, TW, MODE, WIDE, true, false>(a, w.w, nb, w.y, w.z, sm4);
+      strip_tile<T, R, TW, MODE, WIDE, true, false, LEAN>(a, w.w, nb, w.y, w.z, sm4);
     __syncthreads();
   }
 }
@@ -334,70 +337,81 @@ constexpr int strip_width() {
   return Cfg<R, 64>::LDS_FLOATS * sizeof(float) <= 65536 ? 64 : 32;
 }
 
-template <typename T, int R, int MODE, bool WIDE>
-hipError_t go_plain_w(const IterArgs& a, int nb, hipStream_t s) {
+template <typename T, int R, int MODE, bool WIDE, bool LEAN>
+hipError_t go_plain_v(const IterArgs& a, int nb, hipStream_t s) {
   constexpr int TW = strip_width<R>();
   using C = Cfg<R, TW, WIDE>;
   const int TH = C::N * nb;
   const int tx = (a.W + TW - 1) / TW, ty = (a.H + TH - 1) / TH;
   const int ntiles = tx * ty;
   const int grid = (ntiles + 7) / 8 * 8;
-  hipLaunchKernelGGL((lk_iter_strip<T, R, TW, MODE, WIDE>), dim3(grid), dim3(C::NT),
+  hipLaunchKernelGGL((lk_iter_strip<T, R, TW, MODE, WIDE, LEAN>), dim3(grid), dim3(C::NT),
                      C::LDS_FLOATS * sizeof(float), s, a, TH, nb + 1, tx, ntiles);
   return hipGetLastError();
 }
 
-// Small levels are latency bound: twice the threads per tile halve each band's path.
-// nb < 0 encodes the wide variant with -nb bands per tile.
 template <typename T, int R, int MODE>
-hipError_t go_plain(const IterArgs& a, int nb, hipStream_t s) {
-  if (nb < 0) return go_plain_w<T, R, MODE, true>(a, -nb, s);
-  return go_plain_w<T, R, MODE, false>(a, nb, s);
+hipError_t go_plain(const IterArgs& a, int nb, int variant, hipStream_t s) {
+  switch (variant) {
+    case kTileNarrow: return go_plain_v<T, R, MODE, false, true>(a, nb, s);
+    case kTileWide: return go_plain_v<T, R, MODE, true, false>(a, nb, s);
+    case kTileWideLean: return go_plain_v<T, R, MODE, true, true>(a, nb, s);
+  }
+  return hipErrorInvalidValue;
 }
 
-template <typename T, int R, int MODE, bool WIDE>
-hipError_t go_batch_w(const BatchLaunch& b, hipStream_t s) {
+template <typename T, int R, int MODE, bool WIDE, bool LEAN>
+hipError_t go_batch_v(const BatchLaunch& b, hipStream_t s) {
   constexpr int TW = strip_width<R>();
   using C = Cfg<R, TW, WIDE>;
-  hipLaunchKernelGGL((lk_iter_batch<T, R, TW, MODE, WIDE>), dim3(b.grid), dim3(C::NT),
+  hipLaunchKernelGGL((lk_iter_batch<T, R, TW, MODE, WIDE, LEAN>), dim3(b.grid), dim3(C::NT),
                      C::LDS_FLOATS * sizeof(float), s, b.args, b.tiles, b.ntiles);
   return hipGetLastError();
 }
 
 template <typename T, int R, int MODE>
 hipError_t go_batch(const BatchLaunch& b, hipStream_t s) {
-  if (b.wide) return go_batch_w<T, R, MODE, true>(b, s);
-  return go_batch_w<T, R, MODE, false>(b, s);
-}
-
-template <typename T, int R>
-hipError_t go_r(const IterArgs* a, const BatchLaunch* b, int mode, int nb, hipStream_t s) {
-  switch (mode) {
-    case kFlowSame: return a ? go_plain<T, R, kFlowSame>(*a, nb, s) : go_batch<T, R, kFlowSame>(*b, s);
-    case kFlowCoarse: return a ? go_plain<T, R, kFlowCoarse>(*a, nb, s) : go_batch<T, R, kFlowCoarse>(*b, s);
-    case kFlowZero: return a ? go_plain<T, R, kFlowZero>(*a, nb, s) : go_batch<T, R, kFlowZero>(*b, s);
+  switch (b.variant) {
+    case kTileNarrow: return go_batch_v<T, R, MODE, false, true>(b, s);
+    case kTileWide: return go_batch_v<T, R, MODE, true, false>(b, s);
+    case kTileWideLean: return go_batch_v<T, R, MODE, true, true>(b, s);
   }
   return hipErrorInvalidValue;
 }
 
-// Plain launch (a != nullptr; tile height N*nb) or batched launch (b != nullptr).
+template <typename T, int R>
+hipError_t go_r(const IterArgs* a, const BatchLaunch* b, int mode, int nb, int variant,
+                hipStream_t s) {
+  switch (mode) {
+    case kFlowSame:
+      return a ? go_plain<T, R, kFlowSame>(*a, nb, variant, s) : go_batch<T, R, kFlowSame>(*b, s);
+    case kFlowCoarse:
+      return a ? go_plain<T, R, kFlowCoarse>(*a, nb, variant, s) : go_batch<T, R, kFlowCoarse>(*b, s);
+    case kFlowZero:
+      return a ? go_plain<T, R, kFlowZero>(*a, nb, variant, s) : go_batch<T, R, kFlowZero>(*b, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Plain launch (a != nullptr; tile height N*nb, tile variant `variant`) or batched launch
+// (b != nullptr; its own variant).
 template <typename T>
 hipError_t launch_iter_t(const IterArgs* a, const BatchLaunch* b, int R, int mode, int nb,
-                         hipStream_t s) {
+                         int variant, hipStream_t s) {
   switch (R) {
-    case 0: return go_r<T, 0>(a, b, mode, nb, s);
-    case 1: return go_r<T, 1>(a, b, mode, nb, s);
-    case 2: return go_r<T, 2>(a, b, mode, nb, s);
-    case 3: return go_r<T, 3>(a, b, mode, nb, s);
-    case 4: return go_r<T, 4>(a, b, mode, nb, s);
-    case 5: return go_r<T, 5>(a, b, mode, nb, s);
-    case 6: return go_r<T, 6>(a, b, mode, nb, s);
-    case 7: return go_r<T, 7>(a, b, mode, nb, s);
-    case 8: return go_r<T, 8>(a, b, mode, nb, s);
-    case 9: return go_r<T, 9>(a, b, mode, nb, s);
-    case 10: return go_r<T, 10>(a, b, mode, nb, s);
-    case 11: return go_r<T, 11>(a, b, mode, nb, s);
-    case 12: return go_r<T, 12>(a, b, mode, nb, s);
+    case 0: return go_r<T, 0>(a, b, mode, nb, variant, s);
+    case 1: return go_r<T, 1>(a, b, mode, nb, variant, s);
+    case 2: return go_r<T, 2>(a, b, mode, nb, variant, s);
+    case 3: return go_r<T, 3>(a, b, mode, nb, variant, s);
+    case 4: return go_r<T, 4>(a, b, mode, nb, variant, s);
+    case 5: return go_r<T, 5>(a, b, mode, nb, variant, s);
+    case 6: return go_r<T, 6>(a, b, mode, nb, variant, s);
+    case 7: return go_r<T, 7>(a, b, mode, nb, variant, s);
+    case 8: return go_r<T, 8>(a, b, mode, nb, variant, s);
+    case 9: return go_r<T, 9>(a, b, mode, nb, variant, s);
+    case 10: return go_r<T, 10>(a, b, mode, nb, variant, s);
+    case 11: return go_r<T, 11>(a, b, mode, nb, variant, s);
+    case 12: return go_r<T, 12>(a, b, mode, nb, variant, s);
   }
   return hipErrorInvalidValue;
 }

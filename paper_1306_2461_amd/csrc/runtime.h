@@ -24,7 +24,7 @@ struct Geometry {
   size_t off_p2[OF_MAX_LEVELS];
   size_t off_flow[4];               // ping-pong u0, u1, v0, v1 (level-0 size each)
   int nb[OF_MAX_LEVELS];            // iteration tile height per level, in bands of 2R+1 rows
-  bool wide[OF_MAX_LEVELS];         // 10 instead of 5 threads per output column
+  int variant[OF_MAX_LEVELS];       // tile variant of the iteration kernel (TileVariant)
   size_t bytes;
   Elem elem(int l) const;
 };
@@ -108,7 +108,7 @@ hipError_t GraphCache::run(const std::vector<uintptr_t>& key, hipStream_t s, F&&
 
 void set_error(const std::string& s);
 int default_bands(int H, int W, int R);
-bool default_wide(int H, int W);
+int default_tile_variant(long long ntiles);
 bool check_params(int H, int W, int levels, int radius, int iters, unsigned flags);
 Geometry make_geometry(int H, int W, int levels, int radius, int iters, unsigned flags);
 hipError_t enqueue_pair(const Geometry& g, char* ws, const void* I1, const void* I2, float* u,

@@ -40,11 +40,10 @@ int default_bands(int H, int W, int R) {
   return px >= (1 << 22) ? 4 : (px >= (1 << 18) ? 2 : 1);
 }
 
-// Levels of few pixels give few tiles and are latency bound: the wide variant halves the
-// per-thread path of each band.
-// The wide variant (10 waves per workgroup, about 60 VGPRs) keeps about 30 waves per CU
-// resident against 15 for the narrow one; it measured faster at every level size tried.
-bool default_wide(int, int) { return true; }
+// Launches of about one tile per CU are latency bound and take the wide variant (shortest
+// dependent path per band); launches with more tiles take the wide lean variant, whose lower
+// register count lets two workgroups share a CU.
+int default_tile_variant(long long ntiles) { return ntiles >= 384 ? kTileWideLean : kTileWide; }
 
 Geometry make_geometry(int H, int W, int levels, int radius, int iters, unsigned flags) {
   Geometry g{};
@@ -60,7 +59,11 @@ Geometry make_geometry(int H, int W, int levels, int radius, int iters, unsigned
   }
   for (int l = 0; l < levels; ++l) {
     g.nb[l] = default_bands(g.H[l], g.W[l], radius);
-    g.wide[l] = default_wide(g.H[l], g.W[l]);
+    {
+      const long long tx = (g.W[l] + strip_width_for(radius) - 1) / strip_width_for(radius);
+      const long long th = (long long)(2 * radius + 1) * g.nb[l];
+      g.variant[l] = default_tile_variant(tx * ((g.H[l] + th - 1) / th));
+    }
   }
   g.ein = (flags & OF_FLAG_INPUT_F32) ? Elem::F32 : Elem::U8;
   g.e0 = (flags & OF_FLAG_NORMALIZE) ? Elem::F32 : g.ein;
@@ -223,7 +226,7 @@ hipError_t enqueue_pair(const Geometry& g, char* ws, const void* I1, const void*
       a.vout = last ? v : fv[buf];
       hipEvent_t ev;
       hipError_t e = t ? t->begin(s, &ev) : hipSuccess;
-      if (e == hipSuccess) e = launch_iter(g.elem(l), a, g.R, g.nb[l], g.wide[l], s);
+      if (e == hipSuccess) e = launch_iter(g.elem(l), a, g.R, g.nb[l], g.variant[l], s);
       if (e == hipSuccess && t) {
         const double n = (double)a.H * a.W;
         e = t->end(s, ev, OF_KERNEL_ITERATE, n, n * (2.0 * elem_bytes(g.elem(l)) + 16.0));
@@ -349,25 +352,28 @@ void of_plan_destroy(of_plan* p) {
 
 const char* of_last_error(void) { return g_last_error.c_str(); }
 
-of_status of_plan_get_config(const of_plan* p, int* bands, int* wide) {
-  if (!p || !bands || !wide) return set_error("NULL argument"), OF_EINVAL;
+of_status of_plan_get_config(const of_plan* p, int* bands, int* variant) {
+  if (!p || !bands || !variant) return set_error("NULL argument"), OF_EINVAL;
   for (int l = 0; l < p->g.L; ++l) {
     bands[l] = p->g.nb[l];
-    wide[l] = p->g.wide[l] ? 1 : 0;
+    variant[l] = p->g.variant[l];
   }
   return OF_OK;
 }
 
-of_status of_plan_set_config(of_plan* p, const int* bands, const int* wide) {
-  if (!p || !bands || !wide) return set_error("NULL argument"), OF_EINVAL;
-  for (int l = 0; l < p->g.L; ++l)
+of_status of_plan_set_config(of_plan* p, const int* bands, const int* variant) {
+  if (!p || !bands || !variant) return set_error("NULL argument"), OF_EINVAL;
+  for (int l = 0; l < p->g.L; ++l) {
     if (bands[l] < 1 || bands[l] > 64) return set_error("bands out of range"), OF_EINVAL;
+    if (variant[l] < kTileNarrow || variant[l] > kTileWideLean)
+      return set_error("tile variant out of range"), OF_EINVAL;
+  }
   DeviceGuard guard(p->device);
   hipDeviceSynchronize();
   p->graphs.clear();
   for (int l = 0; l < p->g.L; ++l) {
     p->g.nb[l] = bands[l];
-    p->g.wide[l] = wide[l] != 0;
+    p->g.variant[l] = variant[l];
   }
   return OF_OK;
 }
@@ -386,12 +392,12 @@ of_status of_plan_autotune(of_plan* p, const void* I1, const void* I2, float* u,
   for (int l = 0; l < g.L && e == hipSuccess && g.K > 0; ++l) {
     double best = 1e30;
     int bnb = g.nb[l];
-    bool bw = g.wide[l];
+    int bw = g.variant[l];
     for (int nb : kBands) {
       if (nb > 1 && (2 * g.R + 1) * nb > 2 * g.H[l]) continue;
-      for (int w = 0; w < 2; ++w) {
+      for (int w = kTileNarrow; w <= kTileWideLean; ++w) {
         g.nb[l] = nb;
-        g.wide[l] = w != 0;
+        g.variant[l] = w;
         double tl = 1e30;
         for (int r = 0; r <= reps && e == hipSuccess; ++r) {
           e = enqueue_pair(g, p->ws, I1, I2, u, v, s, &p->timer);
@@ -419,12 +425,12 @@ of_status of_plan_autotune(of_plan* p, const void* I1, const void* I2, float* u,
         if (tl < best) {
           best = tl;
           bnb = nb;
-          bw = w != 0;
+          bw = w;
         }
       }
     }
     g.nb[l] = bnb;
-    g.wide[l] = bw;
+    g.variant[l] = bw;
   }
   p->timer.on = was_on;
   hipDeviceSynchronize();
@@ -477,7 +483,7 @@ of_status of_debug_stage(of_plan* p, int stage, int level, const void* const* in
     a.H = g.H[level];
     a.W = g.W[level];
     a.mode = kFlowSame;
-    e = launch_iter(g.elem(level), a, g.R, g.nb[level], g.wide[level], s);
+    e = launch_iter(g.elem(level), a, g.R, g.nb[level], g.variant[level], s);
   } else {
     return set_error("unknown stage"), OF_EINVAL;
   }

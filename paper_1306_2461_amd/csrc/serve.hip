@@ -335,7 +335,7 @@ of_status of_server_push(of_server* s, of_session* const* ss, int n, const void*
       bl.tiles = (const int4*)(s->blk + p.off_tiles[l]);
       bl.ntiles = (int)p.tiles[l].size();
       bl.grid = (bl.ntiles + 7) / 8 * 8;
-      bl.wide = true;
+      bl.variant = default_tile_variant(bl.ntiles);
       const int mode = k > 0 ? kFlowSame : (l == L - 1 ? kFlowZero : kFlowCoarse);
       e = launch_iter_batch(gg.elem(l), bl, R, mode, st);
     }

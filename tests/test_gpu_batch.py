@@ -66,16 +66,16 @@ def test_batch_graph_replays_and_configs(gpu_lib):
             assert np.array_equal(us[i].cpu().numpy(), ref[i][0]), (rep, i)
             assert np.array_equal(vs[i].cpu().numpy(), ref[i][1]), (rep, i)
     # other tile heights / persistent grids give the same bits
-    for bands, grid, wide in [([1, 1, 1], [0, 0, 0], [0, 0, 0]), ([2, 4, 8], [256, 512, 8], [1, 1, 1]),
-                              ([4, 1, 2], [0, 16, 0], [0, 1, -1])]:
-        announce(f"batch config bands={bands} grid={grid} wide={wide}")
-        g.set_config({"bands": bands, "grid": grid, "wide": wide})
-        assert g.config() == {"bands": bands, "grid": grid, "wide": wide}
+    for bands, grid, var in [([1, 1, 1], [0, 0, 0], [0, 0, 0]), ([2, 4, 8], [256, 512, 8], [1, 1, 1]),
+                             ([4, 1, 2], [0, 16, 0], [0, 2, -1]), ([1, 2, 1], [24, 0, 8], [2, 2, 2])]:
+        announce(f"batch config bands={bands} grid={grid} variant={var}")
+        g.set_config({"bands": bands, "grid": grid, "variant": var})
+        assert g.config() == {"bands": bands, "grid": grid, "variant": var}
         g.compute(d1, d2, us, vs)
         torch.cuda.synchronize()
         for i in range(len(SIZES)):
-            assert np.array_equal(us[i].cpu().numpy(), ref[i][0]), (bands, grid, wide, i)
-            assert np.array_equal(vs[i].cpu().numpy(), ref[i][1]), (bands, grid, wide, i)
+            assert np.array_equal(us[i].cpu().numpy(), ref[i][0]), (bands, grid, var, i)
+            assert np.array_equal(vs[i].cpu().numpy(), ref[i][1]), (bands, grid, var, i)
     announce("batch autotune")
     cfg = g.autotune(d1, d2, us, vs, reps=1)
     assert len(cfg["bands"]) == 3
