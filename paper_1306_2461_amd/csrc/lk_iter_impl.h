@@ -135,11 +135,11 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
         read_flow<MODE>(a, gx, gy, cu[k], cv[k]);
       }
     }
+    // Items past the end repeat the last position (clamped index) and store the identical
+    // value to the identical slot, so the stores need no guard: a guard lets the compiler
+    // sink each item's gathers into its own branch and wait for them one item at a time.
 #pragma unroll
-    for (int k = 0; k < C::K1; ++k) {
-      const float z = warp_sample(I2, H, W, wgx[k], wgy[k], wu[k], wv[k]);
-      if (tid + k * NT < nw) w2[wofs[k]] = z;
-    }
+    for (int k = 0; k < C::K1; ++k) w2[wofs[k]] = warp_sample(I2, H, W, wgx[k], wgy[k], wu[k], wv[k]);
     __syncthreads();
     // ---------------------------------------------------------------- P2
     if constexpr (kDefer) {
