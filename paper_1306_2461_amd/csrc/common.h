@@ -56,15 +56,16 @@ __device__ __forceinline__ void st(__half* p, unsigned i, float x) {
 
 // Integer base and fraction of the sample coordinate x + d along one axis of length n,
 // clamped into [0, n-1].  Splitting d = floor(d) + frac keeps the coordinate exact in FP32
-// (x + d itself would round to the spacing of |x|).  Returns base; frac is 0 when clamped.
-__device__ __forceinline__ int split_coord(int x, float d, int n, float& frac) {
-  float fd = floorf(d);
-  frac = d - fd;
-  fd = fminf(fmaxf(fd, -1048576.f), 1048576.f);
-  int b = x + (int)fd;
-  if (b < 0) { b = 0; frac = 0.f; }
-  else if (b >= n - 1) { b = n - 1; frac = 0.f; }
-  return b;
+// (x + d itself would round to the spacing of |x|).  The sample is interior when its base
+// lies in [0, n-2]; otherwise the base is clamped and the fraction is 0.  Returns the base;
+// `step` is 1 for an interior sample (the second tap is the next element) and 0 otherwise.
+__device__ __forceinline__ int split_coord(int x, float d, int n, float& frac, unsigned& step) {
+  const float fd = floorf(d);
+  const int bu = x + (int)fminf(fmaxf(fd, -1048576.f), 1048576.f);
+  const bool inside = (unsigned)bu < (unsigned)(n - 1);
+  frac = inside ? d - fd : 0.f;
+  step = inside ? 1u : 0u;
+  return min(max(bu, 0), n - 1);
 }
 
 // I(x + u, y + v) by bilinear interpolation with clamped coordinates.
@@ -72,13 +73,13 @@ template <typename T>
 __device__ __forceinline__ float warp_sample(const T* __restrict__ I, int H, int W, int x, int y,
                                              float u, float v) {
   float a, b;
-  const int xi = split_coord(x, u, W, a);
-  const int yi = split_coord(y, v, H, b);
-  const unsigned dx = xi < W - 1 ? 1u : 0u;
-  const unsigned dy = yi < H - 1 ? (unsigned)W : 0u;
+  unsigned sx, sy;
+  const int xi = split_coord(x, u, W, a, sx);
+  const int yi = split_coord(y, v, H, b, sy);
   const unsigned o00 = (unsigned)yi * (unsigned)W + (unsigned)xi;
-  const float z00 = ld(I, o00), z01 = ld(I, o00 + dx);
-  const float z10 = ld(I, o00 + dy), z11 = ld(I, o00 + dy + dx);
+  const unsigned dy = sy * (unsigned)W;
+  const float z00 = ld(I, o00), z01 = ld(I, o00 + sx);
+  const float z10 = ld(I, o00 + dy), z11 = ld(I, o00 + dy + sx);
   const float t = fmaf(a, z01 - z00, z00);
   const float s = fmaf(a, z11 - z10, z10);
   return fmaf(b, s - t, t);
