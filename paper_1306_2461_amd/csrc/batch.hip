@@ -277,7 +277,7 @@ size_t of_batch_workspace_bytes(int n, const int* H, const int* W, int levels, i
       Geometry g = make_geometry(H[p], W[p], levels, radius, iters, flags);
       if (l == 0) off += align256(g.bytes);
       tl += (size_t)((g.W[l] + TW - 1) / TW) * ((g.H[l] + N - 1) / N);
-      if (l >= 1) it += 2 * (size_t)((g.W[l] + 63) / 64) * ((g.H[l] + 3) / 4);
+      if (l >= 1) it += 2 * (size_t)reduce_blocks(g.H[l], g.W[l]);
     }
     tiles = std::max(tiles, tl);
     items += align256(it * sizeof(int2));
@@ -333,7 +333,7 @@ of_batch* of_batch_create(int n, const int* H, const int* W, int levels, int rad
   std::vector<std::vector<int2>> items(levels);
   for (int l = 1; l < levels; ++l) {
     for (int p = 0; p < n; ++p) {
-      const int blocks = ((b->g[p].W[l] + 63) / 64) * ((b->g[p].H[l] + 3) / 4);
+      const int blocks = reduce_blocks(b->g[p].H[l], b->g[p].W[l]);
       for (int f = 0; f < 2; ++f)
         for (int k = 0; k < blocks; ++k) items[l].push_back(make_int2(2 * p + f, k));
     }

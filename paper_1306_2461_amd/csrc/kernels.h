@@ -19,7 +19,13 @@ struct ReduceJob {
   int H, W, Ho, Wo;
 };
 
-// Batched pyramid step over (job, 64x4 output block) work items.
+// Output tile of the pyramid reduction kernels (columns x rows of the coarser level).
+constexpr int kReduceTileW = 64, kReduceTileH = 16;
+inline int reduce_blocks(int Ho, int Wo) {
+  return ((Wo + kReduceTileW - 1) / kReduceTileW) * ((Ho + kReduceTileH - 1) / kReduceTileH);
+}
+
+// Batched pyramid step over (job, output tile) work items.
 hipError_t launch_reduce_batch(Elem tin, Elem tout, const ReduceJob* jobs, const int2* items,
                                int nitems, int grid, hipStream_t s);
 

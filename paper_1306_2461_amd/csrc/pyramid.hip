@@ -1,5 +1,6 @@
 // Pyramid reduction: separable binomial [1 4 6 4 1]/16 blur (rows first, then columns),
 // clamp-to-edge, keep even rows and columns (factor 4 in area per level, Sec. 2.4).
+// Each row and column filter is the fused-multiply-add chain over the taps in order.
 #include "kernels.h"
 
 namespace ofmi {
@@ -8,61 +9,116 @@ namespace {
 
 constexpr float kB0 = 1.f / 16.f, kB1 = 4.f / 16.f, kB2 = 6.f / 16.f;
 
+// One output tile (kReduceTileW x kReduceTileH pixels of the coarser level) of one frame.
+// The clamped input window of the tile (2*TW+3 columns, 2*TH+3 rows) is staged in LDS with
+// row-contiguous loads; the row pass then filters the staged rows at the even columns, the
+// column pass filters those results at the even rows.  Input elements are loaded once per
+// tile instead of 25 times per output pixel.
+constexpr int TW = kReduceTileW, TH = kReduceTileH;
+constexpr int IW = 2 * TW + 3, IH = 2 * TH + 3;   // staged input window
+constexpr int IWP = IW + 1;                        // its LDS row pitch
+
+template <typename Tin, typename Tout>
+__device__ __forceinline__ void reduce_tile(const Tin* __restrict__ in, int H, int W,
+                                            Tout* __restrict__ out, int Ho, int Wo, int bx, int by,
+                                            float* win, float* hrow) {
+  const int i0 = by * TH, j0 = bx * TW;             // first output row / column
+  const int r0 = 2 * i0 - 2, c0 = 2 * j0 - 2;       // first input row / column of the window
+  for (int e = threadIdx.x; e < IH * IW; e += 256) {
+    const int ry = e / IW, rx = e - ry * IW;
+    const int y = min(max(r0 + ry, 0), H - 1), x = min(max(c0 + rx, 0), W - 1);
+    win[ry * IWP + rx] = ld(in, (unsigned)y * (unsigned)W + (unsigned)x);
+  }
+  __syncthreads();
+  // Row pass at the even columns 2j of every staged row.
+  for (int e = threadIdx.x; e < IH * TW; e += 256) {
+    const int ry = e / TW, q = e - ry * TW;
+    const float* w = win + ry * IWP + 2 * q;
+    float acc = kB0 * w[0];
+    acc = fmaf(kB1, w[1], acc);
+    acc = fmaf(kB2, w[2], acc);
+    acc = fmaf(kB1, w[3], acc);
+    acc = fmaf(kB0, w[4], acc);
+    hrow[ry * TW + q] = acc;
+  }
+  __syncthreads();
+  // Column pass at the even rows 2i.
+  for (int e = threadIdx.x; e < TH * TW; e += 256) {
+    const int p = e / TW, q = e - p * TW;
+    const int i = i0 + p, j = j0 + q;
+    if (i < Ho && j < Wo) {
+      const float* h = hrow + 2 * p * TW + q;
+      float acc = kB0 * h[0];
+      acc = fmaf(kB1, h[TW], acc);
+      acc = fmaf(kB2, h[2 * TW], acc);
+      acc = fmaf(kB1, h[3 * TW], acc);
+      acc = fmaf(kB0, h[4 * TW], acc);
+      st(out, (unsigned)i * (unsigned)Wo + (unsigned)j, acc);
+    }
+  }
+}
+
 template <typename Tin, typename Tout>
 __global__ __launch_bounds__(256) void reduce_kernel(const Tin* __restrict__ in1,
                                                       const Tin* __restrict__ in2, int H, int W,
                                                       Tout* __restrict__ out1,
                                                       Tout* __restrict__ out2, int Ho, int Wo) {
+  __shared__ float win[IH * IWP];
+  __shared__ float hrow[IH * TW];
+  reduce_tile<Tin, Tout>(blockIdx.z ? in2 : in1, H, W, blockIdx.z ? out2 : out1, Ho, Wo,
+                         blockIdx.x, blockIdx.y, win, hrow);
+}
+
+// Direct form for small planes (latency bound: no staging barriers): one thread per output
+// pixel reads its 5x5 input window itself.  Same arithmetic, in the same order, as
+// reduce_tile, so both give identical bits.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void reduce_direct_kernel(const Tin* __restrict__ in1,
+                                                             const Tin* __restrict__ in2, int H,
+                                                             int W, Tout* __restrict__ out1,
+                                                             Tout* __restrict__ out2, int Ho,
+                                                             int Wo) {
   const int j = blockIdx.x * 64 + (threadIdx.x & 63);
   const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (i >= Ho || j >= Wo) return;
   const Tin* in = blockIdx.z ? in2 : in1;
   Tout* out = blockIdx.z ? out2 : out1;
-  const float k[5] = {kB0, kB1, kB2, kB1, kB0};
-  unsigned rows[5];
+  unsigned cols[5];
 #pragma unroll
-  for (int a = 0; a < 5; ++a) rows[a] = (unsigned)min(max(2 * i + a - 2, 0), H - 1) * (unsigned)W;
-  float acc = 0.f;
+  for (int b = 0; b < 5; ++b) cols[b] = (unsigned)min(max(2 * j + b - 2, 0), W - 1);
+  float h[5];
 #pragma unroll
-  for (int b = 0; b < 5; ++b) {
-    const unsigned xx = (unsigned)min(max(2 * j + b - 2, 0), W - 1);
-    float col = 0.f;
-#pragma unroll
-    for (int a = 0; a < 5; ++a) col = fmaf(k[a], ld(in, rows[a] + xx), col);
-    acc = fmaf(k[b], col, acc);
+  for (int a = 0; a < 5; ++a) {
+    const unsigned row = (unsigned)min(max(2 * i + a - 2, 0), H - 1) * (unsigned)W;
+    float acc = kB0 * ld(in, row + cols[0]);
+    acc = fmaf(kB1, ld(in, row + cols[1]), acc);
+    acc = fmaf(kB2, ld(in, row + cols[2]), acc);
+    acc = fmaf(kB1, ld(in, row + cols[3]), acc);
+    acc = fmaf(kB0, ld(in, row + cols[4]), acc);
+    h[a] = acc;
   }
+  float acc = kB0 * h[0];
+  acc = fmaf(kB1, h[1], acc);
+  acc = fmaf(kB2, h[2], acc);
+  acc = fmaf(kB1, h[3], acc);
+  acc = fmaf(kB0, h[4], acc);
   st(out, (unsigned)i * (unsigned)Wo + (unsigned)j, acc);
 }
 
-// Batched reduction: workgroups stride over a list of (job, block) items; a block is 64x4
-// output pixels of one job's output plane.
+// Batched reduction: workgroups stride over a list of (job, output tile) items.
 template <typename Tin, typename Tout>
 __global__ __launch_bounds__(256) void reduce_batch_kernel(const ReduceJob* __restrict__ jobs,
                                                             const int2* __restrict__ items,
                                                             int nitems) {
-  const float k[5] = {kB0, kB1, kB2, kB1, kB0};
+  __shared__ float win[IH * IWP];
+  __shared__ float hrow[IH * TW];
   for (int t = blockIdx.x; t < nitems; t += gridDim.x) {
     const int2 it = items[t];
     const ReduceJob jb = jobs[it.x];
-    const int bxn = (jb.Wo + 63) / 64;
-    const int j = (it.y % bxn) * 64 + (threadIdx.x & 63);
-    const int i = (it.y / bxn) * 4 + (threadIdx.x >> 6);
-    if (i >= jb.Ho || j >= jb.Wo) continue;
-    const Tin* in = (const Tin*)jb.in;
-    unsigned rows[5];
-#pragma unroll
-    for (int a = 0; a < 5; ++a)
-      rows[a] = (unsigned)min(max(2 * i + a - 2, 0), jb.H - 1) * (unsigned)jb.W;
-    float acc = 0.f;
-#pragma unroll
-    for (int b = 0; b < 5; ++b) {
-      const unsigned xx = (unsigned)min(max(2 * j + b - 2, 0), jb.W - 1);
-      float col = 0.f;
-#pragma unroll
-      for (int a = 0; a < 5; ++a) col = fmaf(k[a], ld(in, rows[a] + xx), col);
-      acc = fmaf(k[b], col, acc);
-    }
-    st((Tout*)jb.out, (unsigned)i * (unsigned)jb.Wo + (unsigned)j, acc);
+    const int bxn = (jb.Wo + TW - 1) / TW;
+    reduce_tile<Tin, Tout>((const Tin*)jb.in, jb.H, jb.W, (Tout*)jb.out, jb.Ho, jb.Wo,
+                           it.y % bxn, it.y / bxn, win, hrow);
+    __syncthreads();
   }
 }
 
@@ -73,12 +129,20 @@ hipError_t go_batch(const ReduceJob* jobs, const int2* items, int nitems, int gr
   return hipGetLastError();
 }
 
+// Planes of up to 2^20 output pixels take the direct form (a single pair's pyramid step is
+// latency bound), larger ones the staged form.
 template <typename Tin, typename Tout>
 hipError_t go(const void* in1, const void* in2, int H, int W, void* out1, void* out2, int Ho,
               int Wo, hipStream_t s) {
-  dim3 grid((Wo + 63) / 64, (Ho + 3) / 4, in2 ? 2 : 1);
-  hipLaunchKernelGGL((reduce_kernel<Tin, Tout>), grid, dim3(256), 0, s, (const Tin*)in1,
-                     (const Tin*)in2, H, W, (Tout*)out1, (Tout*)out2, Ho, Wo);
+  if ((long long)Ho * Wo <= (1ll << 20)) {
+    dim3 grid((Wo + 63) / 64, (Ho + 3) / 4, in2 ? 2 : 1);
+    hipLaunchKernelGGL((reduce_direct_kernel<Tin, Tout>), grid, dim3(256), 0, s, (const Tin*)in1,
+                       (const Tin*)in2, H, W, (Tout*)out1, (Tout*)out2, Ho, Wo);
+  } else {
+    dim3 grid((Wo + TW - 1) / TW, (Ho + TH - 1) / TH, in2 ? 2 : 1);
+    hipLaunchKernelGGL((reduce_kernel<Tin, Tout>), grid, dim3(256), 0, s, (const Tin*)in1,
+                       (const Tin*)in2, H, W, (Tout*)out1, (Tout*)out2, Ho, Wo);
+  }
   return hipGetLastError();
 }
 

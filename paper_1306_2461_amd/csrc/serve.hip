@@ -239,7 +239,7 @@ of_status of_server_push(of_server* s, of_session* const* ss, int n, const void*
       const int job = (int)p.jobs[l - 1].size();
       p.jobs[l - 1].push_back({x->mem + x->slot_off[x->cur][l - 1], x->mem + x->slot_off[x->cur][l],
                                x->g.H[l - 1], x->g.W[l - 1], x->g.H[l], x->g.W[l]});
-      const int blocks = ((x->g.W[l] + 63) / 64) * ((x->g.H[l] + 3) / 4);
+      const int blocks = reduce_blocks(x->g.H[l], x->g.W[l]);
       for (int k = 0; k < blocks; ++k) p.items[l - 1].push_back(make_int2(job, k));
     }
   std::vector<int> flowing;

@@ -18,7 +18,10 @@ TOL16 = 2e-2
 
 # ------------------------------------------------------------------ stages
 
-@pytest.mark.parametrize("shape,L", [((256, 256), 4), ((97, 131), 4), ((2, 7), 2), ((5, 3), 2)])
+# (2100, 2090): the level-1 plane has more than 2^20 pixels, so the plain path takes the
+# LDS-staged reduction kernel instead of the direct one.
+@pytest.mark.parametrize("shape,L", [((256, 256), 4), ((97, 131), 4), ((2, 7), 2), ((5, 3), 2),
+                                     ((2100, 2090), 2)])
 def test_reduce_uint8_exact(gpu_lib, shape, L):
     import torch
     ofmi = gpu_lib
@@ -39,6 +42,22 @@ def test_reduce_uint8_exact(gpu_lib, shape, L):
         else:
             np.testing.assert_allclose(got, P[lev + 1], rtol=1e-6)
         cur = out
+    plan.close()
+
+
+def test_reduce_float_input_staged(gpu_lib):
+    """Float32 frames (rounding matters): the staged kernel against the FP64 reduction."""
+    import torch
+    ofmi = gpu_lib
+    H, W = 2100, 2090
+    F = (np.random.default_rng(4).random((H, W)) * 200.0 - 50.0).astype(np.float32)
+    P = oracle.pyramid(F.astype(np.float64), 2)
+    plan = ofmi.Plan(H, W, 2, 2, 1, input_f32=True, device=dev())
+    out = torch.empty(P[1].shape, dtype=torch.float32, device=dev())
+    announce("reduce float32 2100x2090 (staged)")
+    ofmi.debug_stage(plan, ofmi.OF_STAGE_REDUCE, 0, [to_dev(F)], [out])
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(out.cpu().numpy().astype(np.float64), P[1], rtol=0, atol=2e-5)
     plan.close()
 
 
