@@ -46,6 +46,7 @@
 #define OFMI_H
 
 #include <stddef.h>
+#include <stdint.h>
 
 #ifdef __cplusplus
 extern "C" {
@@ -120,6 +121,23 @@ OF_API of_status of_compute(of_plan* plan, const void* I1, const void* I2, float
 
 /* Releases the plan and the workspace it allocated.  NULL-safe. */
 OF_API void of_plan_destroy(of_plan* plan);
+
+/* Region-of-interest mask, the speed lever of Sec. 3.2 (skip obstacles and side walls):
+ * `mask` is a DEVICE H x W uint8 plane, nonzero = compute.  The plan copies it (on `stream`,
+ * after synchronising the device) and derives one mask per level: a coarser pixel is
+ * unmasked when any of its (up to four) finer pixels is.  Every iteration then writes zero
+ * flow at masked pixels; iteration tiles without an unmasked output pixel are not computed
+ * (zero is written).  Unmasked pixels see the zero flow of masked neighbours, so results near
+ * a mask edge differ from the unmasked computation.  mask == NULL removes the mask.  The first
+ * call allocates the mask pyramid (freed by of_plan_destroy).  Drops captured graphs.
+ * Errors: OF_EINVAL (NULL plan), OF_ENOMEM, OF_EHIP (e.g. `mask` not a device pointer). */
+OF_API of_status of_plan_set_mask(of_plan* plan, const uint8_t* mask, void* stream);
+
+/* Level count from eq. 1: the smallest L >= 1 with dmax / 2^(L-1) < 3 px, capped at the
+ * largest count an H x W frame allows (1 + floor(log2(min(H, W))), at most OF_MAX_LEVELS).
+ * dmax: the largest expected displacement in pixels.  Host only (no device call).  Returns 0
+ * for invalid arguments (H or W < 1, dmax negative or not finite). */
+OF_API int of_levels_for_displacement(float dmax, int H, int W);
 
 /* Per-level launch configuration of a plan: bands[l] = tile height of the iteration kernel
  * in bands of 2r+1 rows (1..64), variant[l] = OF_TILE_* (default: WIDE for levels of under

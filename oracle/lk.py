@@ -163,16 +163,36 @@ def lk_iteration(I1l, I2l, u, v, r, tau=TAU):
     return u + du, v + dv
 
 
-def flow(I1, I2, levels, radius, iters, tau=TAU, dtype=np.float64, return_levels=False):
+def mask_pyramid(M, levels):
+    """Masks of all levels from a level-0 mask (True = computed): a coarser pixel is computed
+    when any of its (up to four) finer pixels is.  Reading of the paper's suggestion to skip
+    computation over obstacles and side walls (Sec. 3.2)."""
+    out = [np.asarray(M, dtype=bool)]
+    for _ in range(levels - 1):
+        m = out[-1]
+        H, W = m.shape
+        ys = np.arange((H + 1) // 2) * 2
+        xs = np.arange((W + 1) // 2) * 2
+        y1 = np.minimum(ys + 1, H - 1)
+        x1 = np.minimum(xs + 1, W - 1)
+        out.append(m[np.ix_(ys, xs)] | m[np.ix_(ys, x1)] | m[np.ix_(y1, xs)] | m[np.ix_(y1, x1)])
+    return out
+
+
+def flow(I1, I2, levels, radius, iters, tau=TAU, dtype=np.float64, return_levels=False,
+         mask=None):
     """Dense displacement (u, v) in level-0 pixels from frame I1 to frame I2.
 
     ``levels`` counts the pyramid levels including full resolution (>= 1), ``radius`` is the
     window radius r >= 0 and ``iters`` the Gauss-Newton iterations per level (>= 0).
+    ``mask`` (optional, level-0 booleans, True = computed): after every iteration the field is
+    set to zero at the pixels the level's mask (``mask_pyramid``) excludes.
     """
     if levels < 1 or radius < 0 or iters < 0:
         raise ValueError("levels >= 1, radius >= 0, iters >= 0 required")
     P1 = pyramid(I1, levels, dtype)
     P2 = pyramid(I2, levels, dtype)
+    M = mask_pyramid(mask, levels) if mask is not None else None
     H, W = P1[-1].shape
     u = np.zeros((H, W), dtype=dtype)
     v = np.zeros((H, W), dtype=dtype)
@@ -184,6 +204,9 @@ def flow(I1, I2, levels, radius, iters, tau=TAU, dtype=np.float64, return_levels
             v = upsample_flow(v, H, W)
         for _ in range(iters):
             u, v = lk_iteration(P1[lev], P2[lev], u, v, radius, tau)
+            if M is not None:
+                u = np.where(M[lev], u, 0.0).astype(dtype)
+                v = np.where(M[lev], v, 0.0).astype(dtype)
         per_level.append((lev, u.copy(), v.copy()))
     if return_levels:
         return u, v, per_level

@@ -10,4 +10,4 @@ from ._binding import (  # noqa: F401
     OF_STAGE_REDUCE, OF_TILE_NARROW, OF_TILE_WIDE, OF_TILE_WIDE_LEAN, OfError,
     last_error, load,
 )
-from .api import Batch, BubbleMonitor, Plan, compute, debug_stage, normalize  # noqa: F401
+from .api import Batch, BubbleMonitor, Plan, compute, debug_stage, levels_for, normalize  # noqa: F401

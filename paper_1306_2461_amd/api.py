@@ -88,6 +88,17 @@ class Plan:
                                           _stream_handle(self.device, stream), reps), "of_plan_autotune")
         return self.config()
 
+    def set_mask(self, mask, stream=None):
+        """Region-of-interest mask (uint8 H x W device tensor, nonzero = compute) or None.
+        Masked pixels get zero flow and tiles without unmasked pixels are skipped."""
+        if mask is None:
+            ptr = None
+        else:
+            _check_frame(mask, self.H, self.W, torch.uint8, self.device, "mask")
+            ptr = mask.data_ptr()
+        B.check(B.load().of_plan_set_mask(self._h, ptr, _stream_handle(self.device, stream)),
+                "of_plan_set_mask")
+
     def set_timing(self, enable: bool):
         """Bracket every kernel launch with hipEvents on its stream (measurement only)."""
         B.check(B.load().of_plan_set_timing(self._h, 1 if enable else 0), "of_plan_set_timing")
@@ -114,6 +125,14 @@ def read_timing(handle, kernel: int):
     B.check(B.load().of_plan_read_timing(handle, kernel, ctypes.byref(ms), ctypes.byref(n),
                                          ctypes.byref(un), ctypes.byref(by)), "of_plan_read_timing")
     return ms.value, n.value, un.value, by.value
+
+
+def levels_for(dmax: float, H: int, W: int) -> int:
+    """Level count from eq. 1 for a largest expected displacement of `dmax` px (host only)."""
+    L = int(B.load().of_levels_for_displacement(float(dmax), int(H), int(W)))
+    if L < 1:
+        raise B.OfError(f"invalid arguments for levels_for: dmax={dmax}, H={H}, W={W}")
+    return L
 
 
 def compute(I1, I2, levels, radius, iters, fp16=False):

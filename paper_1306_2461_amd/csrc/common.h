@@ -24,6 +24,7 @@ struct IterArgs {
   int H, W;            // level size
   int Hc, Wc;          // coarse level size (kFlowCoarse)
   int mode;            // FlowMode
+  const uint8_t* mask; // this level's mask (nonzero = computed) or nullptr (no mask)
 };
 
 // Element access by an unsigned 32-bit element index whose byte offset is formed in 32 bits

@@ -29,6 +29,10 @@ inline int reduce_blocks(int Ho, int Wo) {
 hipError_t launch_reduce_batch(Elem tin, Elem tout, const ReduceJob* jobs, const int2* items,
                                int nitems, int grid, hipStream_t s);
 
+// Mask pyramid step: out(i, j) = 1 if any of in(2i..2i+1, 2j..2j+1) (clamped) is nonzero.
+hipError_t launch_mask_reduce(const uint8_t* in, int H, int W, uint8_t* out, int Ho, int Wo,
+                              hipStream_t s);
+
 // One pyramid reduction of up to two frames of the same geometry (out = reduce(in)).
 hipError_t launch_reduce(Elem tin, Elem tout, const void* in1, const void* in2, int H, int W,
                          void* out1, void* out2, int Ho, int Wo, hipStream_t s);

@@ -266,6 +266,10 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
           solve_update(s[0], s[N * TW], s[2 * N * TW], s[3 * N * TW], s[4 * N * TW], cu[k],
                        cv[k], un, vn);
           const unsigned o = (unsigned)gy * (unsigned)W + (unsigned)gx;
+          if (a.mask && at(a.mask, o) == 0) {   // masked-out pixel: zero flow
+            un = 0.f;
+            vn = 0.f;
+          }
           at(a.uout, o) = un;
           at(a.vout, o) = vn;
         }
@@ -288,6 +292,28 @@ __device__ __forceinline__ bool tile_interior(const IterArgs& a, int TH, int nba
          y0 - R + N * nbands <= a.H - 1;
 }
 
+// Masked plans: false when no output pixel of the tile (TW columns from x0, TH rows from
+// y0) is unmasked; the workgroup then writes zero flow over the tile instead of computing it.
+// Block-uniform result (every thread of the workgroup must call it).
+template <int TW>
+__device__ __forceinline__ bool tile_active_or_zero(const IterArgs& a, int TH, int bx, int by) {
+  const int x0 = bx * TW, y0 = by * TH;
+  const int w = min(TW, a.W - x0), h = min(TH, a.H - y0);
+  int any = 0;
+  for (int i = threadIdx.x; i < w * h; i += blockDim.x) {
+    const int r = i / w, c = i - r * w;
+    any |= at(a.mask, (unsigned)(y0 + r) * (unsigned)a.W + (unsigned)(x0 + c)) != 0;
+  }
+  if (__syncthreads_or(any)) return true;
+  for (int i = threadIdx.x; i < w * h; i += blockDim.x) {
+    const int r = i / w, c = i - r * w;
+    const unsigned o = (unsigned)(y0 + r) * (unsigned)a.W + (unsigned)(x0 + c);
+    at(a.uout, o) = 0.f;
+    at(a.vout, o) = 0.f;
+  }
+  return false;
+}
+
 // Workgroup index -> work index so that the workgroups one XCD runs (hardware dispatch is
 // round-robin over the 8 XCDs) take a contiguous range of tiles, which share halos in L2.
 __device__ __forceinline__ int xcd_order(int b, int nblocks) {
@@ -303,6 +329,7 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_strip(IterArgs a
   const int t = xcd_order(blockIdx.x, gridDim.x);
   if (t >= ntiles) return;
   const int bx = t % tiles_x, by = t / tiles_x;
+  if (a.mask && !tile_active_or_zero<TW>(a, TH, bx, by)) return;
   constexpr bool kDefer = WIDE || R > 8;
   if (R <= 8 && tile_interior<R, TW>(a, TH, nbands, bx, by))
     strip_tile<T, R, TW, MODE, WIDE, kDefer, true, LEAN>(a, TH, nbands, bx, by, sm4);
@@ -323,6 +350,10 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_batch(const Iter
     const int4 w = tiles[t];
     const IterArgs a = args[w.x];
     const int nb = w.w / C::N + 1;
+    if (a.mask && !tile_active_or_zero<TW>(a, w.w, w.y, w.z)) {
+      __syncthreads();
+      continue;
+    }
     if (R <= 8 && tile_interior<R, TW>(a, w.w, nb, w.y, w.z))
       strip_tile<T, R, TW, MODE, WIDE, true, true, LEAN>(a, w.w, nb, w.y, w.z, sm4);
     else

@@ -146,7 +146,30 @@ hipError_t go(const void* in1, const void* in2, int H, int W, void* out1, void* 
   return hipGetLastError();
 }
 
+// Mask pyramid: a coarse pixel is unmasked when any of its (up to) four finer pixels is.
+__global__ __launch_bounds__(256) void mask_reduce_kernel(const uint8_t* __restrict__ in, int H,
+                                                           int W, uint8_t* __restrict__ out,
+                                                           int Ho, int Wo) {
+  const long long n = (long long)Ho * Wo;
+  for (long long e = blockIdx.x * 256ll + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+    const int i = (int)(e / Wo), j = (int)(e - (long long)i * Wo);
+    const unsigned r0 = (unsigned)(2 * i) * (unsigned)W, r1 = (unsigned)min(2 * i + 1, H - 1) * (unsigned)W;
+    const unsigned c0 = (unsigned)(2 * j), c1 = (unsigned)min(2 * j + 1, W - 1);
+    const bool on = at(in, r0 + c0) | at(in, r0 + c1) | at(in, r1 + c0) | at(in, r1 + c1);
+    at(out, (unsigned)e) = on ? 1 : 0;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_mask_reduce(const uint8_t* in, int H, int W, uint8_t* out, int Ho, int Wo,
+                              hipStream_t s) {
+  const long long n = (long long)Ho * Wo;
+  const long long blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(mask_reduce_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)),
+                     dim3(256), 0, s, in, H, W, out, Ho, Wo);
+  return hipGetLastError();
+}
 
 hipError_t launch_reduce_batch(Elem tin, Elem tout, const ReduceJob* jobs, const int2* items,
                                int nitems, int grid, hipStream_t s) {

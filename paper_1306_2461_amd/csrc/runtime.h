@@ -25,6 +25,7 @@ struct Geometry {
   size_t off_flow[4];               // ping-pong u0, u1, v0, v1 (level-0 size each)
   int nb[OF_MAX_LEVELS];            // iteration tile height per level, in bands of 2R+1 rows
   int variant[OF_MAX_LEVELS];       // tile variant of the iteration kernel (TileVariant)
+  const uint8_t* mask[OF_MAX_LEVELS];   // per-level masks (of_plan_set_mask) or nullptr
   size_t bytes;
   Elem elem(int l) const;
 };

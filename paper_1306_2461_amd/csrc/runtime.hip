@@ -221,6 +221,7 @@ hipError_t enqueue_pair(const Geometry& g, char* ws, const void* I1, const void*
       a.Hc = cH;
       a.Wc = cW;
       a.mode = k > 0 ? kFlowSame : (l == g.L - 1 ? kFlowZero : kFlowCoarse);
+      a.mask = g.mask[l];
       const bool last = (l == 0 && k == g.K - 1);
       a.uout = last ? u : fu[buf];
       a.vout = last ? v : fv[buf];
@@ -251,6 +252,7 @@ struct of_plan {
   char* ws;
   bool owns_ws;
   int device;
+  uint8_t* maskbuf = nullptr;   // mask pyramid (of_plan_set_mask), all levels
   KernelTimer timer;
   GraphCache graphs;
 };
@@ -347,10 +349,57 @@ void of_plan_destroy(of_plan* p) {
   hipDeviceSynchronize();
   p->graphs.clear();
   if (p->owns_ws) hipFree(p->ws);
+  if (p->maskbuf) hipFree(p->maskbuf);
   delete p;
 }
 
 const char* of_last_error(void) { return g_last_error.c_str(); }
+
+of_status of_plan_set_mask(of_plan* p, const uint8_t* mask, void* stream) {
+  if (!p) return set_error("NULL plan"), OF_EINVAL;
+  DeviceGuard guard(p->device);
+  hipStream_t s = (hipStream_t)stream;
+  Geometry& g = p->g;
+  hipError_t e = hipStreamSynchronize(s);   // graphs in flight may still read the old masks
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail("set_mask", e);
+  p->graphs.clear();
+  if (!mask) {
+    for (int l = 0; l < g.L; ++l) g.mask[l] = nullptr;
+    return OF_OK;
+  }
+  size_t off[OF_MAX_LEVELS], total = 0;
+  for (int l = 0; l < g.L; ++l) {
+    off[l] = total;
+    total += align256((size_t)g.H[l] * g.W[l]);
+  }
+  if (!p->maskbuf) {
+    e = hipMalloc((void**)&p->maskbuf, total);
+    if (e != hipSuccess) {
+      p->maskbuf = nullptr;
+      set_error(std::string("mask allocation: ") + hipGetErrorString(e));
+      return OF_ENOMEM;
+    }
+  }
+  e = hipMemcpyAsync(p->maskbuf, mask, (size_t)g.H[0] * g.W[0], hipMemcpyDeviceToDevice, s);
+  for (int l = 1; l < g.L && e == hipSuccess; ++l)
+    e = launch_mask_reduce(p->maskbuf + off[l - 1], g.H[l - 1], g.W[l - 1], p->maskbuf + off[l],
+                           g.H[l], g.W[l], s);
+  if (e != hipSuccess) return hip_fail("set_mask", e);
+  for (int l = 0; l < g.L; ++l) g.mask[l] = p->maskbuf + off[l];
+  return OF_OK;
+}
+
+int of_levels_for_displacement(float dmax, int H, int W) {
+  if (H < 1 || W < 1 || !(dmax >= 0.f) || !(dmax < 1e30f)) return 0;
+  int m = H < W ? H : W, maxl = 1;
+  while (m >= 2) { m >>= 1; ++maxl; }
+  if (maxl > OF_MAX_LEVELS) maxl = OF_MAX_LEVELS;
+  int L = 1;
+  // eq. 1: dmax / 2^(L-1) < 3 px, evaluated in double (exact for the powers of two)
+  while (L < maxl && (double)dmax / (double)(1ll << (L - 1)) >= 3.0) ++L;
+  return L;
+}
 
 of_status of_plan_get_config(const of_plan* p, int* bands, int* variant) {
   if (!p || !bands || !variant) return set_error("NULL argument"), OF_EINVAL;
