@@ -26,8 +26,70 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = "c2"
 
 
+# Launch configuration the plan autotuner settles on for this workload (FP32 and FP16): used by
+# the --probe run, which profilers wrap, so that it needs no autotuning launches.
+PROBE_CONFIG = {"bands": [4, 1, 1, 1], "variant": [1, 1, 1, 1]}
+# Sources of the fused iteration kernel: the HBM traffic recorded in the counter summary is
+# used only while they are unchanged.
+KERNEL_SOURCES = ["paper_1306_2461_amd/csrc/lk_iter_impl.h", "paper_1306_2461_amd/csrc/common.h",
+                  "paper_1306_2461_amd/csrc/lk_iter.hip", "paper_1306_2461_amd/csrc/kernels.h"]
+COUNTER_SUMMARY = "profiles/lk_iter_1024_plain_path_counters.md"
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per iteration launch from the committed counter summary (rocprofv3 FETCH_SIZE
+    and WRITE_SIZE runs, copy-calibrated), or None when the kernel sources changed since."""
+    import re
+    try:
+        text = open(os.path.join(ROOT, COUNTER_SUMMARY)).read()
+    except OSError:
+        return None
+    m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.]+)", text)
+    if not m_hash or not m_val or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_val.group(1))
+
+
+def probe(args):
+    """Fixed short run for counter collection: a 256 MiB device copy (calibration of the
+    FETCH_SIZE / WRITE_SIZE counters), then 5 plain FP32 pairs (graphs off, so every launch is
+    a kernel dispatch of its own) at PROBE_CONFIG; no timing, no JSON line."""
+    import synth
+    import torch
+    import paper_1306_2461_amd as ofmi
+    dev = torch.device("cuda", 0)
+    # calibration: a plain copy of 256 MiB (reads and writes 2^28 bytes each)
+    src = torch.ones(1 << 26, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    pairs = [synth.make_pair(WORKLOAD, i)[:2] for i in range(4)]
+    d1 = [torch.from_numpy(p[0]).to(dev) for p in pairs]
+    d2 = [torch.from_numpy(p[1]).to(dev) for p in pairs]
+    wl = synth.workload(WORKLOAD)
+    plan = ofmi.Plan(wl.H, wl.W, wl.levels, wl.radius, wl.iters, device=dev, graph=False)
+    plan.set_config(PROBE_CONFIG)
+    u, v = plan.compute(d1[0], d2[0])
+    for i in range(4):
+        plan.compute(d1[i], d2[i], u, v)
+    torch.cuda.synchronize()
+    log(f"probe: plain path done, kernel sources {kernel_source_hash()}")
+    plan.close()
 
 
 def _gen(i):
@@ -179,6 +241,26 @@ def bench_c4(torch, ofmi, dev, workers, reps):
             "config": cfg}
 
 
+def bench_masked(torch, ofmi, dev, d1, d2, us, vs, wl, cfg, steps, warmup, unmasked_value):
+    """Plain FP32 path with a region-of-interest mask: a step-like obstacle over the lower-left
+    quarter and 64-row side walls top and bottom (the masking lever of Sec. 3.2)."""
+    import numpy as np
+    M = np.ones((wl.H, wl.W), dtype=np.uint8)
+    M[wl.H // 2:, :wl.W // 2] = 0
+    M[:64, :] = 0
+    M[-64:, :] = 0
+    plan = ofmi.Plan(wl.H, wl.W, wl.levels, wl.radius, wl.iters, device=dev)
+    plan.set_config(cfg)
+    plan.set_mask(torch.from_numpy(M).to(dev))
+    el = time_plan(torch, plan, d1, d2, us, vs, steps, warmup)
+    plan.close()
+    value = steps / el
+    log(f"masked: {value:.1f} pairs/s with {M.mean():.3f} of the frame unmasked")
+    return {"value": round(value, 3), "unit": "frame pairs/s", "unmasked_fraction": round(float(M.mean()), 4),
+            "speedup_vs_unmasked": round(value / unmasked_value, 3),
+            "mask": "lower-left quarter (step) and 64-row walls top and bottom excluded"}
+
+
 def bench_serving(torch, ofmi, dev, workers, frames_per_stream):
     """8 streams (sizes from {640x480, 1024^2, 2048^2}), Poisson arrivals at 250 frames/s each."""
     import synth
@@ -230,11 +312,17 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=8)
     ap.add_argument("--no-extra", action="store_true", help="skip the batched, mixed-batch and serving runs")
     ap.add_argument("--serve-frames", type=int, default=24)
+    ap.add_argument("--probe", action="store_true",
+                    help="short fixed run for profilers (4 plain pairs), no timing, no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); pairs are "
               "independent, so a multi-GPU run would deal pairs to GPUs with no exchange", file=sys.stderr)
         sys.exit(2)
+
+    if args.probe:
+        probe(args)
+        return
 
     import numpy as np
     import synth
@@ -296,6 +384,9 @@ def main():
         for name, fn in (("batched_1024_fp32", lambda: bench_batched(torch, ofmi, dev, pairs, wl, False, 20, "fp32")),
                          ("batched_1024_fp16", lambda: bench_batched(torch, ofmi, dev, pairs, wl, True, 20, "fp16")),
                          ("mixed_batch_64", lambda: bench_c4(torch, ofmi, dev, workers, 5)),
+                         ("masked_1024_fp32", lambda: bench_masked(torch, ofmi, dev, d1, d2, us, vs, wl,
+                                                                   results["fp32"]["cfg"], args.steps, args.warmup,
+                                                                   args.steps / results["fp32"]["el"])),
                          ("serving_8_streams", lambda: bench_serving(torch, ofmi, dev, workers, args.serve_frames))):
             try:
                 extra[name] = fn()
@@ -327,7 +418,7 @@ def main():
         "eager_launch_value": round(r32["eager"], 3),
         "max_abs_err_px": r32["err"],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "lk_iter (fused iteration)", "launches": n_it,
                      "avg_launch_us": round(ms_it / max(n_it, 1) * 1e3, 3),
                      "bytes_per_launch": round(bytes_it / max(n_it, 1))},
