@@ -25,6 +25,8 @@ struct IterArgs {
   int Hc, Wc;          // coarse level size (kFlowCoarse)
   int mode;            // FlowMode
   const uint8_t* mask; // this level's mask (nonzero = computed) or nullptr (no mask)
+  const uint8_t* tiles; // with a mask, one flag per iteration tile: 0 = no unmasked output
+                        // pixel, 1 = some masked pixels, 2 = no masked pixel
 };
 
 // Element access by an unsigned 32-bit element index whose byte offset is formed in 32 bits

@@ -55,9 +55,10 @@ struct Cfg {
 // across the band loop: a few more VALU instructions per band for far fewer live registers,
 // i.e. more resident workgroups per CU (launches with many tiles); without it each band's
 // dependent path is shorter (launches with about one tile per CU).
+// pixel_mask: the tile holds masked pixels, whose flow is written as zero.
 template <typename T, int R, int TW, int MODE, bool WIDE, bool DEFER, bool INTERIOR, bool LEAN>
 __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands, int bx, int by,
-                                           float4* sm4) {
+                                           bool pixel_mask, float4* sm4) {
   using C = Cfg<R, TW, WIDE>;
   constexpr int N = C::N, NT = C::NT, PC = C::PC, WC = C::WC, PP = C::PP, WP = C::WP;
   constexpr int RMASK = C::RING - 1;
@@ -266,7 +267,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
           solve_update(s[0], s[N * TW], s[2 * N * TW], s[3 * N * TW], s[4 * N * TW], cu[k],
                        cv[k], un, vn);
           const unsigned o = (unsigned)gy * (unsigned)W + (unsigned)gx;
-          if (a.mask && at(a.mask, o) == 0) {   // masked-out pixel: zero flow
+          if (pixel_mask && at(a.mask, o) == 0) {   // masked-out pixel: zero flow
             un = 0.f;
             vn = 0.f;
           }
@@ -292,26 +293,18 @@ __device__ __forceinline__ bool tile_interior(const IterArgs& a, int TH, int nba
          y0 - R + N * nbands <= a.H - 1;
 }
 
-// Masked plans: false when no output pixel of the tile (TW columns from x0, TH rows from
-// y0) is unmasked; the workgroup then writes zero flow over the tile instead of computing it.
-// Block-uniform result (every thread of the workgroup must call it).
+// Masked plans: a tile without an unmasked output pixel (TW columns from x0, TH rows from
+// y0) is not computed; its workgroup writes zero flow over it.
 template <int TW>
-__device__ __forceinline__ bool tile_active_or_zero(const IterArgs& a, int TH, int bx, int by) {
+__device__ __forceinline__ void zero_tile(const IterArgs& a, int TH, int bx, int by) {
   const int x0 = bx * TW, y0 = by * TH;
   const int w = min(TW, a.W - x0), h = min(TH, a.H - y0);
-  int any = 0;
-  for (int i = threadIdx.x; i < w * h; i += blockDim.x) {
-    const int r = i / w, c = i - r * w;
-    any |= at(a.mask, (unsigned)(y0 + r) * (unsigned)a.W + (unsigned)(x0 + c)) != 0;
-  }
-  if (__syncthreads_or(any)) return true;
   for (int i = threadIdx.x; i < w * h; i += blockDim.x) {
     const int r = i / w, c = i - r * w;
     const unsigned o = (unsigned)(y0 + r) * (unsigned)a.W + (unsigned)(x0 + c);
     at(a.uout, o) = 0.f;
     at(a.vout, o) = 0.f;
   }
-  return false;
 }
 
 // Workgroup index -> work index so that the workgroups one XCD runs (hardware dispatch is
@@ -329,16 +322,25 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_strip(IterArgs a
   const int t = xcd_order(blockIdx.x, gridDim.x);
   if (t >= ntiles) return;
   const int bx = t % tiles_x, by = t / tiles_x;
-  if (a.mask && !tile_active_or_zero<TW>(a, TH, bx, by)) return;
+  bool pixel_mask = false;
+  if (a.mask) {
+    const int f = a.tiles[t];
+    if (f == 0) {
+      zero_tile<TW>(a, TH, bx, by);
+      return;
+    }
+    pixel_mask = f == 1;
+  }
   constexpr bool kDefer = WIDE || R > 8;
   if (R <= 8 && tile_interior<R, TW>(a, TH, nbands, bx, by))
-    strip_tile<T, R, TW, MODE, WIDE, kDefer, true, LEAN>(a, TH, nbands, bx, by, sm4);
+    strip_tile<T, R, TW, MODE, WIDE, kDefer, true, LEAN>(a, TH, nbands, bx, by, pixel_mask, sm4);
   else
-    strip_tile<T, R, TW, MODE, WIDE, kDefer, false, LEAN>(a, TH, nbands, bx, by, sm4);
+    strip_tile<T, R, TW, MODE, WIDE, kDefer, false, LEAN>(a, TH, nbands, bx, by, pixel_mask, sm4);
 }
 
 // Batched form: workgroups stride over a work list of tiles of many pairs at the same
-// (level, iteration) phase.  Work item = (pair, tile x, tile y, tile height).
+// (level, iteration) phase.  Work item = (pair, tile x, tile y, tile height).  Batches carry
+// no masks.
 template <typename T, int R, int TW, int MODE, bool WIDE, bool LEAN>
 __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_batch(const IterArgs* __restrict__ args,
                                                                       const int4* __restrict__ tiles,
@@ -350,14 +352,10 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_batch(const Iter
     const int4 w = tiles[t];
     const IterArgs a = args[w.x];
     const int nb = w.w / C::N + 1;
-    if (a.mask && !tile_active_or_zero<TW>(a, w.w, w.y, w.z)) {
-      __syncthreads();
-      continue;
-    }
     if (R <= 8 && tile_interior<R, TW>(a, w.w, nb, w.y, w.z))
-      strip_tile<T, R, TW, MODE, WIDE, true, true, LEAN>(a, w.w, nb, w.y, w.z, sm4);
+      strip_tile<T, R, TW, MODE, WIDE, true, true, LEAN>(a, w.w, nb, w.y, w.z, false, sm4);
     else
-      strip_tile<T, R, TW, MODE, WIDE, true, false, LEAN>(a, w.w, nb, w.y, w.z, sm4);
+      strip_tile<T, R, TW, MODE, WIDE, true, false, LEAN>(a, w.w, nb, w.y, w.z, false, sm4);
     __syncthreads();
   }
 }

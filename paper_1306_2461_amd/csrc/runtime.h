@@ -26,6 +26,7 @@ struct Geometry {
   int nb[OF_MAX_LEVELS];            // iteration tile height per level, in bands of 2R+1 rows
   int variant[OF_MAX_LEVELS];       // tile variant of the iteration kernel (TileVariant)
   const uint8_t* mask[OF_MAX_LEVELS];   // per-level masks (of_plan_set_mask) or nullptr
+  const uint8_t* tflags[OF_MAX_LEVELS]; // per-level iteration-tile flags (with a mask)
   size_t bytes;
   Elem elem(int l) const;
 };

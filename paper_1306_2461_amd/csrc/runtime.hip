@@ -4,6 +4,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 
 #include "../../include/ofmi.h"
@@ -222,6 +223,7 @@ hipError_t enqueue_pair(const Geometry& g, char* ws, const void* I1, const void*
       a.Wc = cW;
       a.mode = k > 0 ? kFlowSame : (l == g.L - 1 ? kFlowZero : kFlowCoarse);
       a.mask = g.mask[l];
+      a.tiles = g.tflags[l];
       const bool last = (l == 0 && k == g.K - 1);
       a.uout = last ? u : fu[buf];
       a.vout = last ? v : fv[buf];
@@ -253,6 +255,9 @@ struct of_plan {
   bool owns_ws;
   int device;
   uint8_t* maskbuf = nullptr;   // mask pyramid (of_plan_set_mask), all levels
+  uint8_t* tflags = nullptr;    // iteration-tile flags of all levels (capacity: one band per tile)
+  size_t tf_off[OF_MAX_LEVELS] = {};
+  std::vector<uint8_t> hmask[OF_MAX_LEVELS];   // host copy of the mask pyramid
   KernelTimer timer;
   GraphCache graphs;
 };
@@ -350,10 +355,50 @@ void of_plan_destroy(of_plan* p) {
   p->graphs.clear();
   if (p->owns_ws) hipFree(p->ws);
   if (p->maskbuf) hipFree(p->maskbuf);
+  if (p->tflags) hipFree(p->tflags);
   delete p;
 }
 
 const char* of_last_error(void) { return g_last_error.c_str(); }
+
+namespace {
+
+size_t tile_capacity(const Geometry& g, int l) {
+  const size_t tx = (g.W[l] + strip_width_for(g.R) - 1) / strip_width_for(g.R);
+  return tx * ((g.H[l] + 2 * g.R) / (2 * g.R + 1));
+}
+
+// Flags of level l's iteration tiles for its current tile height, from the host mask copy,
+// uploaded to the plan's flag buffer (synchronous copy: outside graph capture only).
+hipError_t upload_tile_flags(of_plan* p, int l) {
+  Geometry& g = p->g;
+  const int TW = strip_width_for(g.R), TH = (2 * g.R + 1) * g.nb[l];
+  const int H = g.H[l], W = g.W[l];
+  const int tx = (W + TW - 1) / TW, ty = (H + TH - 1) / TH;
+  std::vector<uint8_t> f((size_t)tx * ty);
+  const std::vector<uint8_t>& m = p->hmask[l];
+  for (int by = 0; by < ty; ++by)
+    for (int bx = 0; bx < tx; ++bx) {
+      int on = 0, total = 0;
+      for (int y = by * TH; y < std::min(H, (by + 1) * TH); ++y)
+        for (int x = bx * TW; x < std::min(W, (bx + 1) * TW); ++x) {
+          on += m[(size_t)y * W + x] != 0;
+          ++total;
+        }
+      f[(size_t)by * tx + bx] = on == 0 ? 0 : (on == total ? 2 : 1);
+    }
+  g.tflags[l] = p->tflags + p->tf_off[l];
+  return hipMemcpy(p->tflags + p->tf_off[l], f.data(), f.size(), hipMemcpyHostToDevice);
+}
+
+hipError_t upload_all_tile_flags(of_plan* p) {
+  hipError_t e = hipSuccess;
+  if (!p->g.mask[0]) return e;
+  for (int l = 0; l < p->g.L && e == hipSuccess; ++l) e = upload_tile_flags(p, l);
+  return e;
+}
+
+}  // namespace
 
 of_status of_plan_set_mask(of_plan* p, const uint8_t* mask, void* stream) {
   if (!p) return set_error("NULL plan"), OF_EINVAL;
@@ -365,18 +410,23 @@ of_status of_plan_set_mask(of_plan* p, const uint8_t* mask, void* stream) {
   if (e != hipSuccess) return hip_fail("set_mask", e);
   p->graphs.clear();
   if (!mask) {
-    for (int l = 0; l < g.L; ++l) g.mask[l] = nullptr;
+    for (int l = 0; l < g.L; ++l) g.mask[l] = g.tflags[l] = nullptr;
     return OF_OK;
   }
-  size_t off[OF_MAX_LEVELS], total = 0;
+  size_t off[OF_MAX_LEVELS], total = 0, ftotal = 0;
   for (int l = 0; l < g.L; ++l) {
     off[l] = total;
     total += align256((size_t)g.H[l] * g.W[l]);
+    p->tf_off[l] = ftotal;
+    ftotal += align256(tile_capacity(g, l));
   }
   if (!p->maskbuf) {
     e = hipMalloc((void**)&p->maskbuf, total);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->tflags, ftotal);
     if (e != hipSuccess) {
+      if (p->maskbuf) hipFree(p->maskbuf);
       p->maskbuf = nullptr;
+      p->tflags = nullptr;
       set_error(std::string("mask allocation: ") + hipGetErrorString(e));
       return OF_ENOMEM;
     }
@@ -385,8 +435,21 @@ of_status of_plan_set_mask(of_plan* p, const uint8_t* mask, void* stream) {
   for (int l = 1; l < g.L && e == hipSuccess; ++l)
     e = launch_mask_reduce(p->maskbuf + off[l - 1], g.H[l - 1], g.W[l - 1], p->maskbuf + off[l],
                            g.H[l], g.W[l], s);
-  if (e != hipSuccess) return hip_fail("set_mask", e);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  for (int l = 0; l < g.L && e == hipSuccess; ++l) {
+    p->hmask[l].resize((size_t)g.H[l] * g.W[l]);
+    e = hipMemcpy(p->hmask[l].data(), p->maskbuf + off[l], p->hmask[l].size(), hipMemcpyDeviceToHost);
+  }
+  if (e != hipSuccess) {
+    for (int l = 0; l < g.L; ++l) g.mask[l] = g.tflags[l] = nullptr;
+    return hip_fail("set_mask", e);
+  }
   for (int l = 0; l < g.L; ++l) g.mask[l] = p->maskbuf + off[l];
+  e = upload_all_tile_flags(p);
+  if (e != hipSuccess) {
+    for (int l = 0; l < g.L; ++l) g.mask[l] = g.tflags[l] = nullptr;
+    return hip_fail("set_mask tile flags", e);
+  }
   return OF_OK;
 }
 
@@ -424,6 +487,8 @@ of_status of_plan_set_config(of_plan* p, const int* bands, const int* variant) {
     p->g.nb[l] = bands[l];
     p->g.variant[l] = variant[l];
   }
+  hipError_t e = upload_all_tile_flags(p);
+  if (e != hipSuccess) return hip_fail("tile flags", e);
   return OF_OK;
 }
 
@@ -447,6 +512,8 @@ of_status of_plan_autotune(of_plan* p, const void* I1, const void* I2, float* u,
       for (int w = kTileNarrow; w <= kTileWideLean; ++w) {
         g.nb[l] = nb;
         g.variant[l] = w;
+        if (g.mask[l]) e = upload_tile_flags(p, l);
+        if (e != hipSuccess) break;
         double tl = 1e30;
         for (int r = 0; r <= reps && e == hipSuccess; ++r) {
           e = enqueue_pair(g, p->ws, I1, I2, u, v, s, &p->timer);
@@ -480,6 +547,7 @@ of_status of_plan_autotune(of_plan* p, const void* I1, const void* I2, float* u,
     }
     g.nb[l] = bnb;
     g.variant[l] = bw;
+    if (e == hipSuccess && g.mask[l]) e = upload_tile_flags(p, l);
   }
   p->timer.on = was_on;
   hipDeviceSynchronize();
