@@ -243,7 +243,7 @@ def bench_c4(torch, ofmi, dev, workers, reps):
 
 def bench_masked(torch, ofmi, dev, d1, d2, us, vs, wl, steps, warmup, unmasked_value):
     """Plain FP32 path with a region-of-interest mask: a step-like obstacle over the lower-left
-    quarter and 64-row side walls top and bottom (the masking lever of Sec. 3.2)."""
+    quarter and 64-row side walls top and bottom (the masking lever of Sec. 3.3)."""
     import numpy as np
     M = np.ones((wl.H, wl.W), dtype=np.uint8)
     M[wl.H // 2:, :wl.W // 2] = 0

@@ -122,7 +122,7 @@ OF_API of_status of_compute(of_plan* plan, const void* I1, const void* I2, float
 /* Releases the plan and the workspace it allocated.  NULL-safe. */
 OF_API void of_plan_destroy(of_plan* plan);
 
-/* Region-of-interest mask, the speed lever of Sec. 3.2 (skip obstacles and side walls):
+/* Region-of-interest mask, the speed lever of Sec. 3.3 (skip obstacles and side walls):
  * `mask` is a DEVICE H x W uint8 plane, nonzero = compute.  The plan copies it (on `stream`,
  * after synchronising the device) and derives one mask per level: a coarser pixel is
  * unmasked when any of its (up to four) finer pixels is.  Every iteration then writes zero
@@ -283,7 +283,7 @@ OF_API void of_server_destroy(of_server* s);
 
 /* --------------------------------------------------------------------- around the flow
  * Local equalisation of a raw frame (Sec. 2.4, eq. 2; the printed denominator is the root of
- * minus the variance, the text says "divided by the local intensity standard deviation"):
+ * minus the variance, while the text divides by the local standard deviation, as here):
  * out = (in - m) / (sd + eps), m and sd the mean and standard deviation of `in` over the
  * (2r+1)^2 window truncated at the border (in-image pixels only), accumulated in FP64.
  * in: H x W uint8 (float32 with OF_FLAG_INPUT_F32) device plane; out: H x W float32 device

@@ -4,17 +4,17 @@ TEST INFRASTRUCTURE ONLY (same rules as ``oracle.lk``).
 
 * ``local_normalize`` -- the local equalisation applied to raw frames before the flow
   (Sec. 2.4, eq. 2): subtract the local mean and divide by the local standard deviation over a
-  window of radius 5.  eq. 2 as printed takes the root of the mean squared minus the squared
-  mean's *negative*; the text says "divided by the local intensity standard deviation", which
-  is what is computed: sigma = sqrt(mean(I^2) - mean(I)^2), window truncated at the border
-  (means over in-image pixels), result (I - mean) / (sigma + eps).
+  window of radius 5.  eq. 2 as printed takes the root of the *negative* of the variance;
+  the surrounding text divides by the local standard deviation, which is what is computed:
+  sigma = sqrt(mean(I^2) - mean(I)^2), window truncated at the border (means over in-image
+  pixels), result (I - mean) / (sigma + eps).
 * ``levels_for_displacement`` -- the level rule of eq. 1: the smallest n_lev with
   dmax / 2^(n_lev - 1) < 3 px.
 * ``bubble_threshold`` / ``bubble_surface`` -- the recirculation-bubble surface of Sec. 3.2,
   eq. 3: the fraction of vectors whose streamwise component is at or below the threshold
   T_v = (min + max) / 2 of the time-mean streamwise field.  eq. 3's printed denominator is the
-  sum of the components; the text says "relative to the total number of available velocity
-  vectors", which is what is computed.
+  sum of the components; the text describes a ratio to the number of vectors, which is what is
+  computed.
 """
 from __future__ import annotations
 

@@ -166,7 +166,7 @@ def lk_iteration(I1l, I2l, u, v, r, tau=TAU):
 def mask_pyramid(M, levels):
     """Masks of all levels from a level-0 mask (True = computed): a coarser pixel is computed
     when any of its (up to four) finer pixels is.  Reading of the paper's suggestion to skip
-    computation over obstacles and side walls (Sec. 3.2)."""
+    computation over obstacles and side walls (Sec. 3.3)."""
     out = [np.asarray(M, dtype=bool)]
     for _ in range(levels - 1):
         m = out[-1]

@@ -1,4 +1,4 @@
-"""Region-of-interest masks (tile skipping over obstacles and side walls, Sec. 3.2) on the GPU,
+"""Region-of-interest masks (tile skipping over obstacles and side walls, Sec. 3.3) on the GPU,
 against the oracle's masked flow."""
 import numpy as np
 import pytest
