@@ -4,8 +4,8 @@ Only the tests, the smoke check and the benchmark's CPU-baseline leg may import 
 package.  It shares no code with the HIP path.
 """
 from .lk import (  # noqa: F401
-    TAU, bilinear, blur5, box_sum, flow, gradients, lk_iteration, mask_pyramid, pyr_reduce,
-    pyramid, solve, upsample_flow, warp,
+    TAU, bilinear, blur5, box_sum, flow, gaussian_weights, gradients, lk_iteration, mask_pyramid,
+    pyr_reduce, pyramid, solve, upsample_flow, warp, window_sum,
 )
 from .extras import (  # noqa: F401,E402
     bubble_surface, bubble_threshold, levels_for_displacement, local_normalize, running_mean,

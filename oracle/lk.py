@@ -20,7 +20,8 @@ The paper leaves the operators themselves unspecified; this oracle fixes them as
 * prolongation to a finer level: u <- 2 * bilinear(u_coarse, x/2, y/2), same for v;
 * warp: W2(x, y) = bilinear(I2, x + u, y + v), sample coordinates clamped into the image;
 * gradients: central differences of the warped frame W2 with clamped neighbours;
-* window: unweighted (2r+1)^2 box, truncated at the image border;
+* window: unweighted (2r+1)^2 box, truncated at the image border (variant: separable Gaussian
+  taps over the same support, ``gaussian_weights``);
 * Gauss-Newton step: the residual of every window pixel m is linearised around that pixel's
   own current displacement u(m): W2(m) + grad W2(m) . (d - u(m)) - I1(m), with d the displacement
   sought for the window centre x.  With It(m) = W2(m) - I1(m) - grad W2(m) . u(m), A, B, C, sx,
@@ -128,6 +129,37 @@ def box_sum(p, r):
     return out
 
 
+def gaussian_weights(r):
+    """Taps of the Gaussian-weighted window variant: g(d) = exp(-d^2 / (2 sigma^2)) for
+    d = -r..r with sigma = r / 2 (r = 0: a single tap of weight 1).  The paper's window is the
+    unweighted box of radius r; the weighted window is the usual alternative in this family of
+    solvers, with the same support, so that the taps at the window edge weigh exp(-2)."""
+    if r == 0:
+        return np.ones(1)
+    d = np.arange(-r, r + 1, dtype=np.float64)
+    sigma = r / 2.0
+    return np.exp(-d * d / (2.0 * sigma * sigma))
+
+
+def window_sum(p, r, weights=None):
+    """Weighted window sum S(x, y) = sum over the in-image part of the (2r+1)^2 window of
+    g[dy] g[dx] p(y + dy, x + dx) (outside-image terms zero), as the double sum over dy of the
+    sum over dx.  weights=None is the unweighted box (``box_sum``)."""
+    if weights is None:
+        return box_sum(p, r)
+    g = np.asarray(weights, dtype=p.dtype)
+    H, W = p.shape
+    q = np.zeros((H + 2 * r, W + 2 * r), dtype=p.dtype)
+    q[r:r + H, r:r + W] = p
+    rows = np.zeros((H + 2 * r, W), dtype=p.dtype)
+    for dx in range(2 * r + 1):
+        rows = rows + g[dx] * q[:, dx:dx + W]
+    out = np.zeros((H, W), dtype=p.dtype)
+    for dy in range(2 * r + 1):
+        out = out + g[dy] * rows[dy:dy + H, :]
+    return out
+
+
 def solve(A, B, C, bx, by, tau=TAU):
     """Per-pixel Gauss-Newton increment (du, dv) from the five window sums.
 
@@ -151,12 +183,13 @@ def solve(A, B, C, bx, by, tau=TAU):
     return du, dv
 
 
-def lk_iteration(I1l, I2l, u, v, r, tau=TAU):
-    """One Gauss-Newton iteration at one level: warp, gradients, window sums, solve, update."""
+def lk_iteration(I1l, I2l, u, v, r, tau=TAU, weights=None):
+    """One Gauss-Newton iteration at one level: warp, gradients, window sums, solve, update.
+    ``weights``: separable window taps (None = unweighted box)."""
     W2 = warp(I2l, u, v)
     Ix, Iy = gradients(W2)
     It = W2 - I1l - Ix * u - Iy * v
-    A, B, C, sx, sy = (box_sum(p, r) for p in (Ix * Ix, Ix * Iy, Iy * Iy, Ix * It, Iy * It))
+    A, B, C, sx, sy = (window_sum(p, r, weights) for p in (Ix * Ix, Ix * Iy, Iy * Iy, Ix * It, Iy * It))
     bx = sx + A * u + B * v
     by = sy + B * u + C * v
     du, dv = solve(A, B, C, bx, by, tau=tau)
@@ -180,14 +213,18 @@ def mask_pyramid(M, levels):
 
 
 def flow(I1, I2, levels, radius, iters, tau=TAU, dtype=np.float64, return_levels=False,
-         mask=None):
+         mask=None, window="box"):
     """Dense displacement (u, v) in level-0 pixels from frame I1 to frame I2.
 
     ``levels`` counts the pyramid levels including full resolution (>= 1), ``radius`` is the
     window radius r >= 0 and ``iters`` the Gauss-Newton iterations per level (>= 0).
     ``mask`` (optional, level-0 booleans, True = computed): after every iteration the field is
     set to zero at the pixels the level's mask (``mask_pyramid``) excludes.
+    ``window``: "box" (unweighted) or "gauss" (``gaussian_weights``).
     """
+    if window not in ("box", "gauss"):
+        raise ValueError("window must be 'box' or 'gauss'")
+    weights = gaussian_weights(radius) if window == "gauss" else None
     if levels < 1 or radius < 0 or iters < 0:
         raise ValueError("levels >= 1, radius >= 0, iters >= 0 required")
     P1 = pyramid(I1, levels, dtype)
@@ -203,7 +240,7 @@ def flow(I1, I2, levels, radius, iters, tau=TAU, dtype=np.float64, return_levels
             u = upsample_flow(u, H, W)
             v = upsample_flow(v, H, W)
         for _ in range(iters):
-            u, v = lk_iteration(P1[lev], P2[lev], u, v, radius, tau)
+            u, v = lk_iteration(P1[lev], P2[lev], u, v, radius, tau, weights)
             if M is not None:
                 u = np.where(M[lev], u, 0.0).astype(dtype)
                 v = np.where(M[lev], v, 0.0).astype(dtype)

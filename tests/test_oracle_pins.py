@@ -331,3 +331,77 @@ def test_iterations_stop_varying():
     d2 = np.maximum(np.abs(b[0] - c[0]), np.abs(b[1] - c[1]))
     assert d2.max() < 0.6 * d1.max()
     assert np.percentile(d2, 99) < 1e-2
+
+
+# ------------------------------------------------------------------ Gaussian-weighted window
+
+def test_gaussian_weights_closed_form():
+    for r in (1, 4, 8):
+        g = lk.gaussian_weights(r)
+        assert g.shape == (2 * r + 1,) and g[r] == 1.0
+        np.testing.assert_allclose(g, g[::-1], rtol=0, atol=0)
+        np.testing.assert_allclose([g[0], g[-1]], np.exp(-2.0), rtol=1e-15)
+    assert np.array_equal(lk.gaussian_weights(0), [1.0])
+
+
+@pytest.mark.parametrize("shape,r", [((7, 9), 2), ((1, 5), 1), ((12, 4), 3), ((5, 5), 0)])
+def test_weighted_window_sum_brute_force(shape, r):
+    p = RNG.normal(size=shape)
+    g = lk.gaussian_weights(r)
+    H, W = shape
+    ref = np.zeros(shape)
+    for y in range(H):
+        for x in range(W):
+            for dy in range(-r, r + 1):
+                for dx in range(-r, r + 1):
+                    if 0 <= y + dy < H and 0 <= x + dx < W:
+                        ref[y, x] += g[dy + r] * g[dx + r] * p[y + dy, x + dx]
+    np.testing.assert_allclose(lk.window_sum(p, r, g), ref, rtol=1e-12, atol=1e-12)
+    # unit taps are the unweighted box, bitwise
+    assert np.array_equal(lk.window_sum(p, r, np.ones(2 * r + 1)), lk.box_sum(p, r))
+
+
+def test_gaussian_iteration_equals_weighted_least_squares():
+    """Independent formulation: per pixel, lstsq of the linearised window residuals scaled by
+    the square roots of the window weights."""
+    H, W, r = 11, 13, 2
+    I1 = ndi.gaussian_filter(RNG.uniform(0, 255, size=(H, W)), 1.0)
+    I2 = ndi.gaussian_filter(RNG.uniform(0, 255, size=(H, W)), 1.0)
+    u = RNG.uniform(-0.8, 0.8, size=(H, W))
+    v = RNG.uniform(-0.8, 0.8, size=(H, W))
+    g = lk.gaussian_weights(r)
+    un, vn = lk.lk_iteration(I1, I2, u, v, r, weights=g)
+    W2 = lk.warp(I2, u, v)
+    Ix, Iy = lk.gradients(W2)
+    for y in range(H):
+        for x in range(W):
+            rows, rhs = [], []
+            for yy in range(max(0, y - r), min(H, y + r + 1)):
+                for xx in range(max(0, x - r), min(W, x + r + 1)):
+                    s = np.sqrt(g[yy - y + r] * g[xx - x + r])
+                    gr = np.array([Ix[yy, xx], Iy[yy, xx]])
+                    rows.append(s * gr)
+                    rhs.append(s * (I1[yy, xx] - W2[yy, xx] + gr @ np.array([u[yy, xx], v[yy, xx]])))
+            d = np.linalg.lstsq(np.array(rows), np.array(rhs), rcond=None)[0]
+            assert abs(un[y, x] - d[0]) < 1e-8 and abs(vn[y, x] - d[1]) < 1e-8, (y, x)
+
+
+def test_gaussian_window_flow_exact_cases():
+    I = RNG.integers(0, 256, size=(40, 52)).astype(np.uint8)
+    u, v = oracle.flow(I, I, 2, 3, 2, window="gauss")
+    assert np.all(u == 0) and np.all(v == 0)
+    x = np.arange(64, dtype=float)
+    I1 = np.tile(4 * x, (40, 1)).astype(np.uint8)
+    I2 = np.tile(4 * x - 1, (40, 1)).clip(0).astype(np.uint8)
+    u, v = oracle.flow(I1, I2, 1, 3, 2, window="gauss")
+    m = 5 * 2 + 1
+    np.testing.assert_allclose(u[:, m:-m], 0.25, atol=1e-12)
+    np.testing.assert_allclose(v[:, m:-m], 0.0, atol=1e-12)
+    H = W = 64
+    yy, xx = np.mgrid[0:H, 0:W].astype(float)
+    f = lambda X, Y: 50.0 + 2.0 * X + 1.5 * Y + 0.05 * X * Y  # noqa: E731
+    u, v = oracle.flow(f(xx, yy), f(xx - 0.375, yy + 0.25), 2, 4, 10, window="gauss")
+    np.testing.assert_allclose(u[16:-16, 16:-16], 0.375, atol=1e-10)
+    np.testing.assert_allclose(v[16:-16, 16:-16], -0.25, atol=1e-10)
+    with pytest.raises(ValueError):
+        oracle.flow(I, I, 1, 2, 1, window="hann")
