@@ -261,6 +261,18 @@ def bench_masked(torch, ofmi, dev, d1, d2, us, vs, wl, steps, warmup, unmasked_v
             "mask": "lower-left quarter (step) and 64-row walls top and bottom excluded"}
 
 
+def bench_gaussian(torch, ofmi, dev, d1, d2, us, vs, wl, steps, warmup, box_value):
+    """Plain FP32 path with the Gaussian-weighted window (OF_FLAG_GAUSSIAN_WINDOW)."""
+    plan = ofmi.Plan(wl.H, wl.W, wl.levels, wl.radius, wl.iters, gaussian_window=True, device=dev)
+    tuned = plan.autotune(d1[0], d2[0], us[0], vs[0], reps=3)
+    el = time_plan(torch, plan, d1, d2, us, vs, steps, warmup)
+    plan.close()
+    value = steps / el
+    log(f"gaussian window: {value:.1f} pairs/s, config {tuned}")
+    return {"value": round(value, 3), "unit": "frame pairs/s", "vs_box_window": round(value / box_value, 3),
+            "config": tuned}
+
+
 def bench_serving(torch, ofmi, dev, workers, frames_per_stream):
     """8 streams (sizes from {640x480, 1024^2, 2048^2}), Poisson arrivals at 250 frames/s each."""
     import synth
@@ -384,6 +396,9 @@ def main():
         for name, fn in (("batched_1024_fp32", lambda: bench_batched(torch, ofmi, dev, pairs, wl, False, 20, "fp32")),
                          ("batched_1024_fp16", lambda: bench_batched(torch, ofmi, dev, pairs, wl, True, 20, "fp16")),
                          ("mixed_batch_64", lambda: bench_c4(torch, ofmi, dev, workers, 5)),
+                         ("gaussian_window_1024_fp32", lambda: bench_gaussian(torch, ofmi, dev, d1, d2, us, vs, wl,
+                                                                             args.steps, args.warmup,
+                                                                             args.steps / results["fp32"]["el"])),
                          ("masked_1024_fp32", lambda: bench_masked(torch, ofmi, dev, d1, d2, us, vs, wl,
                                                                    args.steps, args.warmup,
                                                                    args.steps / results["fp32"]["el"])),

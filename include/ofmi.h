@@ -70,6 +70,10 @@ typedef enum {
 #define OF_FLAG_NORMALIZE    (1u << 3) /* plans only: equalise both frames locally (see
                                           of_normalize; radius OF_NORMALIZE_RADIUS, eps
                                           OF_NORMALIZE_EPS) before the pyramid */
+#define OF_FLAG_GAUSSIAN_WINDOW (1u << 4) /* plans only: weight the window sums by separable
+                                          Gaussian taps exp(-d^2 / (2 sigma^2)), sigma = r/2,
+                                          over the same (2r+1)^2 support (a variant of the
+                                          unweighted interrogation window of Sec. 2.4) */
 
 /* Tile variants of the fused iteration kernel (launch configuration; results do not depend
  * on them).  NARROW: 5 threads per output column.  WIDE: 10 threads per output column with
@@ -242,7 +246,8 @@ typedef struct of_server of_server;
 typedef struct of_session of_session;
 
 /* Device bytes one session of an H x W stream keeps resident (two frame pyramids including
- * level 0, four level-0 FP32 field planes); 0 on invalid parameters. */
+ * level 0, four level-0 FP32 field planes); 0 on invalid parameters, including the plan-only
+ * flags OF_FLAG_NORMALIZE and OF_FLAG_GAUSSIAN_WINDOW. */
 OF_API size_t of_session_bytes(int H, int W, int levels, int radius, int iters, unsigned flags);
 
 /* Server for streams sharing levels, radius, iters and flags (OF_FLAG_NO_GRAPH ignored).

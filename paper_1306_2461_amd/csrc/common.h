@@ -9,6 +9,7 @@
 namespace ofmi {
 
 constexpr float kTau = 1e-5f;   // relative singularity threshold of the 2x2 solve
+constexpr int kMaxTaps = 25;    // window taps for the largest supported radius (2*12 + 1)
 
 // Field source of an iteration: the previous iteration at the same level, the coarser
 // level's result (prolongation u <- 2 bilinear(u_c, x/2, y/2)), or zero (coarsest level).
@@ -27,6 +28,7 @@ struct IterArgs {
   const uint8_t* mask; // this level's mask (nonzero = computed) or nullptr (no mask)
   const uint8_t* tiles; // with a mask, one flag per iteration tile: 0 = no unmasked output
                         // pixel, 1 = some masked pixels, 2 = no masked pixel
+  float taps[kMaxTaps]; // Gaussian-weighted window: separable taps g[0..2r] (unused for the box)
 };
 
 // Element access by an unsigned 32-bit element index whose byte offset is formed in 32 bits

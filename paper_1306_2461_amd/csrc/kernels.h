@@ -44,6 +44,8 @@ hipError_t launch_reduce(Elem tin, Elem tout, const void* in1, const void* in2, 
 //   wide lean  10 threads per output column, indices recomputed every band (fewer live
 //              registers, so more resident workgroups: launches with many tiles).
 enum TileVariant : int { kTileNarrow = 0, kTileWide = 1, kTileWideLean = 2 };
+// Added to a plain launch's variant: Gaussian-weighted window sums (taps in IterArgs::taps).
+constexpr int kTileGauss = 16;
 
 // Batched iteration launch: `grid` workgroups stride over `ntiles` work items
 // (pair, tile x, tile y, tile height) with per-pair arguments args[pair] (device arrays).

@@ -56,7 +56,11 @@ struct Cfg {
 // i.e. more resident workgroups per CU (launches with many tiles); without it each band's
 // dependent path is shorter (launches with about one tile per CU).
 // pixel_mask: the tile holds masked pixels, whose flow is written as zero.
-template <typename T, int R, int TW, int MODE, bool WIDE, bool DEFER, bool INTERIOR, bool LEAN>
+// GAUSS: window sums weighted by the separable taps a.taps[0..2r] (Gaussian-weighted window)
+// instead of the unweighted box: every horizontal and vertical sum is a direct 2r+1-term
+// weighted sum in a fixed order, so results remain independent of the tiling.
+template <typename T, int R, int TW, int MODE, bool WIDE, bool DEFER, bool INTERIOR, bool LEAN,
+          bool GAUSS = false>
 __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands, int bx, int by,
                                            bool pixel_mask, float4* sm4) {
   using C = Cfg<R, TW, WIDE>;
@@ -205,14 +209,24 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
           vbuf[4 * q + 2] = f.z;
           vbuf[4 * q + 3] = f.w;
         }
-        float s = vbuf[0];
+        if constexpr (GAUSS) {
 #pragma unroll
-        for (int q = 1; q <= 2 * R; ++q) s += vbuf[q];
-        hv[k][0] = s;
+          for (int j = 0; j < 8; ++j) {
+            float s = a.taps[0] * vbuf[j];
 #pragma unroll
-        for (int j = 1; j < 8; ++j) {
-          s = (s - vbuf[j - 1]) + vbuf[j + 2 * R];
-          hv[k][j] = s;
+            for (int q = 1; q <= 2 * R; ++q) s = fmaf(a.taps[q], vbuf[j + q], s);
+            hv[k][j] = s;
+          }
+        } else {
+          float s = vbuf[0];
+#pragma unroll
+          for (int q = 1; q <= 2 * R; ++q) s += vbuf[q];
+          hv[k][0] = s;
+#pragma unroll
+          for (int j = 1; j < 8; ++j) {
+            s = (s - vbuf[j - 1]) + vbuf[j + 2 * R];
+            hv[k][j] = s;
+          }
         }
       }
     }
@@ -229,7 +243,25 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     }
     __syncthreads();
     // ---------------------------------------------------------------- P4
-    if (p4) {
+    if (GAUSS && p4) {
+      // Output row r of the band: previous-band rows r+1..N-1 then current rows 0..r, i.e.
+      // window offsets 0..N-1 from its top row, weighted by the taps in that order.
+      float* col = hs + vk * N * TW + vc;
+      float cur[N];
+#pragma unroll
+      for (int r = 0; r < N; ++r) cur[r] = col[r * TW];
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        float s = 0.f;
+#pragma unroll
+        for (int m = r + 1; m < N; ++m) s = fmaf(a.taps[m - r - 1], prev[m], s);
+#pragma unroll
+        for (int m = 0; m <= r; ++m) s = fmaf(a.taps[N - 1 - r + m], cur[m], s);
+        col[r * TW] = s;
+      }
+#pragma unroll
+      for (int r = 0; r < N; ++r) prev[r] = cur[r];
+    } else if (p4) {
       float* col = hs + vk * N * TW + vc;
       // prev[r] <- prev[r] + ... + prev[N-1] (suffix sums of the previous band, in place)
 #pragma unroll
@@ -315,7 +347,7 @@ __device__ __forceinline__ int xcd_order(int b, int nblocks) {
   return (b % kXcd) * per + b / kXcd;
 }
 
-template <typename T, int R, int TW, int MODE, bool WIDE, bool LEAN>
+template <typename T, int R, int TW, int MODE, bool WIDE, bool LEAN, bool GAUSS>
 __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_strip(IterArgs a, int TH, int nbands,
                                                                       int tiles_x, int ntiles) {
   extern __shared__ float4 sm4[];
@@ -333,9 +365,11 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_strip(IterArgs a
   }
   constexpr bool kDefer = WIDE || R > 8;
   if (R <= 8 && tile_interior<R, TW>(a, TH, nbands, bx, by))
-    strip_tile<T, R, TW, MODE, WIDE, kDefer, true, LEAN>(a, TH, nbands, bx, by, pixel_mask, sm4);
+    strip_tile<T, R, TW, MODE, WIDE, kDefer, true, LEAN, GAUSS>(a, TH, nbands, bx, by, pixel_mask,
+                                                                sm4);
   else
-    strip_tile<T, R, TW, MODE, WIDE, kDefer, false, LEAN>(a, TH, nbands, bx, by, pixel_mask, sm4);
+    strip_tile<T, R, TW, MODE, WIDE, kDefer, false, LEAN, GAUSS>(a, TH, nbands, bx, by, pixel_mask,
+                                                                 sm4);
 }
 
 // Batched form: workgroups stride over a work list of tiles of many pairs at the same
@@ -366,7 +400,7 @@ constexpr int strip_width() {
   return Cfg<R, 64>::LDS_FLOATS * sizeof(float) <= 65536 ? 64 : 32;
 }
 
-template <typename T, int R, int MODE, bool WIDE, bool LEAN>
+template <typename T, int R, int MODE, bool WIDE, bool LEAN, bool GAUSS>
 hipError_t go_plain_v(const IterArgs& a, int nb, hipStream_t s) {
   constexpr int TW = strip_width<R>();
   using C = Cfg<R, TW, WIDE>;
@@ -374,19 +408,26 @@ hipError_t go_plain_v(const IterArgs& a, int nb, hipStream_t s) {
   const int tx = (a.W + TW - 1) / TW, ty = (a.H + TH - 1) / TH;
   const int ntiles = tx * ty;
   const int grid = (ntiles + 7) / 8 * 8;
-  hipLaunchKernelGGL((lk_iter_strip<T, R, TW, MODE, WIDE, LEAN>), dim3(grid), dim3(C::NT),
+  hipLaunchKernelGGL((lk_iter_strip<T, R, TW, MODE, WIDE, LEAN, GAUSS>), dim3(grid), dim3(C::NT),
                      C::LDS_FLOATS * sizeof(float), s, a, TH, nb + 1, tx, ntiles);
   return hipGetLastError();
 }
 
-template <typename T, int R, int MODE>
-hipError_t go_plain(const IterArgs& a, int nb, int variant, hipStream_t s) {
+template <typename T, int R, int MODE, bool GAUSS>
+hipError_t go_plain_g(const IterArgs& a, int nb, int variant, hipStream_t s) {
   switch (variant) {
-    case kTileNarrow: return go_plain_v<T, R, MODE, false, true>(a, nb, s);
-    case kTileWide: return go_plain_v<T, R, MODE, true, false>(a, nb, s);
-    case kTileWideLean: return go_plain_v<T, R, MODE, true, true>(a, nb, s);
+    case kTileNarrow: return go_plain_v<T, R, MODE, false, true, GAUSS>(a, nb, s);
+    case kTileWide: return go_plain_v<T, R, MODE, true, false, GAUSS>(a, nb, s);
+    case kTileWideLean: return go_plain_v<T, R, MODE, true, true, GAUSS>(a, nb, s);
   }
   return hipErrorInvalidValue;
+}
+
+// variant bit kTileGauss selects the Gaussian-weighted window.
+template <typename T, int R, int MODE>
+hipError_t go_plain(const IterArgs& a, int nb, int variant, hipStream_t s) {
+  if (variant & kTileGauss) return go_plain_g<T, R, MODE, true>(a, nb, variant & ~kTileGauss, s);
+  return go_plain_g<T, R, MODE, false>(a, nb, variant, s);
 }
 
 template <typename T, int R, int MODE, bool WIDE, bool LEAN>

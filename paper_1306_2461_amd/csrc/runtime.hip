@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 
 #include "../../include/ofmi.h"
@@ -28,7 +29,8 @@ bool check_params(int H, int W, int levels, int radius, int iters, unsigned flag
   if (levels > maxl) return set_error("levels > 1 + floor(log2(min(H, W)))"), false;
   if (radius < 0 || radius > OF_MAX_RADIUS) return set_error("radius out of range"), false;
   if (iters < 0 || iters > OF_MAX_ITERS) return set_error("iters out of range"), false;
-  if (flags & ~(OF_FLAG_FP16_STORAGE | OF_FLAG_INPUT_F32 | OF_FLAG_NO_GRAPH | OF_FLAG_NORMALIZE))
+  if (flags & ~(OF_FLAG_FP16_STORAGE | OF_FLAG_INPUT_F32 | OF_FLAG_NO_GRAPH | OF_FLAG_NORMALIZE |
+                OF_FLAG_GAUSSIAN_WINDOW))
     return set_error("unknown flags"), false;
   return true;
 }
@@ -169,6 +171,18 @@ KernelTimer::~KernelTimer() {
   for (hipEvent_t e : pool) hipEventDestroy(e);
 }
 
+// Window taps and launch variant of one iteration: the Gaussian-weighted window
+// (OF_FLAG_GAUSSIAN_WINDOW) fills the taps g(d) = exp(-d^2 / (2 sigma^2)), sigma = r/2,
+// d = -r..r, and marks the variant.
+int window_variant(const Geometry& g, int l, IterArgs& a) {
+  if (!(g.flags & OF_FLAG_GAUSSIAN_WINDOW)) return g.variant[l];
+  for (int q = 0; q <= 2 * g.R; ++q) {
+    const double d = q - g.R;
+    a.taps[q] = g.R == 0 ? 1.0f : (float)std::exp(-2.0 * d * d / ((double)g.R * g.R));
+  }
+  return g.variant[l] | kTileGauss;
+}
+
 // Enqueue the whole method for one pair: pyramid then levels x iterations.
 hipError_t enqueue_pair(const Geometry& g, char* ws, const void* I1, const void* I2, float* u,
                         float* v, hipStream_t s, KernelTimer* t) {
@@ -229,7 +243,8 @@ hipError_t enqueue_pair(const Geometry& g, char* ws, const void* I1, const void*
       a.vout = last ? v : fv[buf];
       hipEvent_t ev;
       hipError_t e = t ? t->begin(s, &ev) : hipSuccess;
-      if (e == hipSuccess) e = launch_iter(g.elem(l), a, g.R, g.nb[l], g.variant[l], s);
+      const int variant = window_variant(g, l, a);
+      if (e == hipSuccess) e = launch_iter(g.elem(l), a, g.R, g.nb[l], variant, s);
       if (e == hipSuccess && t) {
         const double n = (double)a.H * a.W;
         e = t->end(s, ev, OF_KERNEL_ITERATE, n, n * (2.0 * elem_bytes(g.elem(l)) + 16.0));
@@ -600,7 +615,8 @@ of_status of_debug_stage(of_plan* p, int stage, int level, const void* const* in
     a.H = g.H[level];
     a.W = g.W[level];
     a.mode = kFlowSame;
-    e = launch_iter(g.elem(level), a, g.R, g.nb[level], g.variant[level], s);
+    const int variant = window_variant(g, level, a);
+    e = launch_iter(g.elem(level), a, g.R, g.nb[level], variant, s);
   } else {
     return set_error("unknown stage"), OF_EINVAL;
   }
