@@ -29,6 +29,8 @@ WORKLOAD = "c2"
 # Launch configuration the plan autotuner settles on for this workload (FP32 and FP16): used by
 # the --probe run, which profilers wrap, so that it needs no autotuning launches.
 PROBE_CONFIG = {"bands": [4, 1, 1, 1], "variant": [1, 1, 1, 1]}
+# One of the configurations the batch autotuner picks for 16 pairs of this workload.
+PROBE_BATCH_CONFIG = {"bands": [8, 8, 4, 1], "grid": [512, 0, 512, 512], "variant": [0, 0, 1, 1]}
 # Sources of the fused iteration kernel: the HBM traffic recorded in the counter summary is
 # used only while they are unchanged.
 KERNEL_SOURCES = ["paper_1306_2461_amd/csrc/lk_iter_impl.h", "paper_1306_2461_amd/csrc/common.h",
@@ -67,7 +69,8 @@ def measured_traffic():
 def probe(args):
     """Fixed short run for counter collection: a 256 MiB device copy (calibration of the
     FETCH_SIZE / WRITE_SIZE counters), then 5 plain FP32 pairs (graphs off, so every launch is
-    a kernel dispatch of its own) at PROBE_CONFIG; no timing, no JSON line."""
+    a kernel dispatch of its own) at PROBE_CONFIG, then one 16-pair batch at
+    PROBE_BATCH_CONFIG; no timing, no JSON line."""
     import synth
     import torch
     import paper_1306_2461_amd as ofmi
@@ -90,6 +93,13 @@ def probe(args):
     torch.cuda.synchronize()
     log(f"probe: plain path done, kernel sources {kernel_source_hash()}")
     plan.close()
+    b = ofmi.Batch([(wl.H, wl.W)] * 16, wl.levels, wl.radius, wl.iters, device=dev, graph=False)
+    b.set_config(PROBE_BATCH_CONFIG)
+    bu, bv = b.outputs()
+    b.compute([d1[i % 4] for i in range(16)], [d2[i % 4] for i in range(16)], bu, bv)
+    torch.cuda.synchronize()
+    log("probe: 16-pair batch done")
+    b.close()
 
 
 def _gen(i):
