@@ -93,9 +93,12 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     if constexpr (LEAN) asm volatile("" : "+v"(tid));
     // ---------------------------------------------------------------- P1
     // Every global load of the band is issued here, branch-free (clamped addresses; results
-    // for items outside the image or the band are discarded), in two rounds: the field at the
-    // warped-frame positions, frame 1 and the field at this thread's P2 items and the centre
-    // field of its P5 items; then the four frame-2 samples of every warped-frame position.
+    // for items outside the image or the band are discarded): the field at the warped-frame
+    // positions, the four frame-2 samples of every warped-frame position, then frame 1 and the
+    // field at this thread's P2 items and the centre field of its P5 items.  In the lean
+    // variants a scheduling barrier keeps the last group after the samples are stored: issued
+    // together the groups are all live at once (the kernel's register peak); the split costs
+    // one more dependent load round per band and buys resident workgroups.
     const int wfirst = b == 0 ? -1 : tb + 1;
     const int nw = (b == 0 ? N + 2 : N) * WC;
     int wofs[C::K1], wgx[C::K1], wgy[C::K1];
@@ -119,25 +122,29 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     // held in flight here.
     constexpr bool kDefer = DEFER && MODE == kFlowCoarse;
     float i1v[C::K2], pu[C::K2], pv[C::K2];
-#pragma unroll
-    for (int k = 0; k < C::K2; ++k) {
-      const int i = min(tid + k * NT, N * PC - 1);
-      int gx = x0 - R + i % PC, gy = y0 - R + tb + i / PC;
-      if constexpr (!INTERIOR) {
-        gx = min(max(gx, 0), W - 1);
-        gy = min(max(gy, 0), H - 1);
-      }
-      i1v[k] = ld(I1, (unsigned)gy * (unsigned)W + (unsigned)gx);
-      if constexpr (!kDefer) read_flow<MODE>(a, gx, gy, pu[k], pv[k]);
-    }
     float cu[C::K5], cv[C::K5];
-    if constexpr (!kDefer) {
+    // (The same loads are written twice, before the samples for the default variants and
+    // after them for the lean ones, so that each keeps its own straight-line schedule.)
+    if constexpr (!LEAN) {
 #pragma unroll
-      for (int k = 0; k < C::K5; ++k) {
-        const int i = min(tid + k * NT, N * TW - 1);
-        const int gx = INTERIOR ? x0 + i % TW : min(x0 + i % TW, W - 1);
-        const int gy = min(max(y0 + tb + i / TW - 2 * R, 0), H - 1);
-        read_flow<MODE>(a, gx, gy, cu[k], cv[k]);
+      for (int k = 0; k < C::K2; ++k) {
+        const int i = min(tid + k * NT, N * PC - 1);
+        int gx = x0 - R + i % PC, gy = y0 - R + tb + i / PC;
+        if constexpr (!INTERIOR) {
+          gx = min(max(gx, 0), W - 1);
+          gy = min(max(gy, 0), H - 1);
+        }
+        i1v[k] = ld(I1, (unsigned)gy * (unsigned)W + (unsigned)gx);
+        if constexpr (!kDefer) read_flow<MODE>(a, gx, gy, pu[k], pv[k]);
+      }
+      if constexpr (!kDefer) {
+#pragma unroll
+        for (int k = 0; k < C::K5; ++k) {
+          const int i = min(tid + k * NT, N * TW - 1);
+          const int gx = INTERIOR ? x0 + i % TW : min(x0 + i % TW, W - 1);
+          const int gy = min(max(y0 + tb + i / TW - 2 * R, 0), H - 1);
+          read_flow<MODE>(a, gx, gy, cu[k], cv[k]);
+        }
       }
     }
     // Items past the end repeat the last position (clamped index) and store the identical
@@ -145,6 +152,29 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     // sink each item's gathers into its own branch and wait for them one item at a time.
 #pragma unroll
     for (int k = 0; k < C::K1; ++k) w2[wofs[k]] = warp_sample(I2, H, W, wgx[k], wgy[k], wu[k], wv[k]);
+    if constexpr (LEAN) {
+      __builtin_amdgcn_sched_barrier(0);   // compiler-only fence
+#pragma unroll
+      for (int k = 0; k < C::K2; ++k) {
+        const int i = min(tid + k * NT, N * PC - 1);
+        int gx = x0 - R + i % PC, gy = y0 - R + tb + i / PC;
+        if constexpr (!INTERIOR) {
+          gx = min(max(gx, 0), W - 1);
+          gy = min(max(gy, 0), H - 1);
+        }
+        i1v[k] = ld(I1, (unsigned)gy * (unsigned)W + (unsigned)gx);
+        if constexpr (!kDefer) read_flow<MODE>(a, gx, gy, pu[k], pv[k]);
+      }
+      if constexpr (!kDefer) {
+#pragma unroll
+        for (int k = 0; k < C::K5; ++k) {
+          const int i = min(tid + k * NT, N * TW - 1);
+          const int gx = INTERIOR ? x0 + i % TW : min(x0 + i % TW, W - 1);
+          const int gy = min(max(y0 + tb + i / TW - 2 * R, 0), H - 1);
+          read_flow<MODE>(a, gx, gy, cu[k], cv[k]);
+        }
+      }
+    }
     __syncthreads();
     // ---------------------------------------------------------------- P2
     if constexpr (kDefer) {
