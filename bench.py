@@ -43,11 +43,17 @@ def log(msg):
 
 
 def kernel_source_hash():
+    """SHA-256 of the iteration kernel's sources with // comments and blank lines removed (a
+    comment edit does not change the kernel the counters measured)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            for line in fh:
+                code = re.sub(r"//.*", "", line).rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()
 
 

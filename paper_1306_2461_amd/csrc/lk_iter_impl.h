@@ -3,7 +3,8 @@
 // gradients of the warped frame, the five window sums, the 2x2 solve and the update.
 //
 // Work decomposition (gfx950, wave64):
-//   * a workgroup of 5*TW threads owns a strip of TW output columns and TH output rows;
+//   * a workgroup of 5*TW threads (narrow) or 10*TW threads (wide) owns a strip of TW output
+//     columns and TH output rows;
 //   * it walks down the strip in bands of N = 2r+1 product rows; per band:
 //       P1  warped frame for the band's new rows into an LDS ring; all global loads of the
 //           band (field, frame 1, centre field of the band's outputs) are issued here;
@@ -11,10 +12,12 @@
 //       P3  horizontal window sums: one thread per (channel, row, 8-column segment), a
 //           direct (2r+1)-term sum re-seeded at every segment, then a running sum over the
 //           segment's 8 outputs (segments sit on multiples of 8 of the level's columns);
+//           the Gaussian-weighted window takes a direct weighted sum per output instead;
 //       P4  vertical window sums: one thread per (channel, column) holds the previous
 //           band's horizontal sums in registers; the window of the band's row i is the
 //           suffix sum of the previous band from row i+1 plus the prefix sum of the current
-//           band up to row i (fixed order; bands sit on a global grid of period N);
+//           band up to row i (fixed order; bands sit on a global grid of period N), or the
+//           direct weighted sum over the same rows for the Gaussian-weighted window;
 //       P5  per-pixel 2x2 solve and update for the band's output rows.
 //   The window sums therefore do not depend on how the image is cut into tiles.
 #pragma once
