@@ -46,9 +46,24 @@ struct Cfg {
   static constexpr int K2 = (N * PC + NT - 1) / NT;             // P2 items per thread
   static constexpr int K3 = (5 * N * NSEG + NT - 1) / NT;       // P3 items per thread
   static constexpr int K5 = (N * TW + NT - 1) / NT;             // P5 items per thread
-  // The window sums [5][N][TW] reuse the product buffer [5][N][PP] once P3 has read it.
+  // The window sums [5][N][TW] reuse the product buffer [5][N][PP] once P3 has read it, or
+  // (SPLIT) have a region of their own after the ring, which saves P3's second barrier.
   static constexpr size_t LDS_FLOATS = 5 * (size_t)N * PP + (size_t)RING * WP;
+  static constexpr size_t HS_FLOATS = 5 * (size_t)N * TW;
+  static constexpr bool SPLIT_FITS = (LDS_FLOATS + HS_FLOATS) * sizeof(float) <= 65536;
 };
+
+// Separate window-sum region for the wide (latency) variant where it fits in 64 KB: that
+// variant runs about one workgroup per CU, so the larger LDS footprint costs no occupancy.
+template <int R, int TW, bool WIDE, bool LEAN>
+constexpr bool split_hs() {
+  return WIDE && !LEAN && Cfg<R, TW, WIDE>::SPLIT_FITS;
+}
+template <int R, int TW, bool WIDE, bool LEAN>
+constexpr size_t lds_bytes() {
+  using C = Cfg<R, TW, WIDE>;
+  return (C::LDS_FLOATS + (split_hs<R, TW, WIDE, LEAN>() ? C::HS_FLOATS : 0)) * sizeof(float);
+}
 
 // One tile: TW output columns from x0 = bx*TW and TH output rows from y0 = by*TH, walked in
 // nbands bands (TH is a multiple of N; nbands = TH/N + 1).  `sm4` is the workgroup's LDS.
@@ -70,9 +85,12 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
   constexpr int N = C::N, NT = C::NT, PC = C::PC, WC = C::WC, PP = C::PP, WP = C::WP;
   constexpr int RMASK = C::RING - 1;
   float* sm = reinterpret_cast<float*>(sm4);
+  constexpr bool kSplit = split_hs<R, TW, WIDE, LEAN>();
   float* pr = sm;                               // [5][N][PP] products (16-byte aligned rows)
-  float* hs = pr;                               // [5][N][TW] horizontal, then window sums
   float* w2 = pr + 5 * N * PP;                  // [RING][WP] warped frame ring
+  // [5][N][TW] horizontal, then window sums (16-byte aligned: RING*WP is a multiple of 4 here
+  // or the region aliases the products)
+  float* hs = kSplit ? w2 + C::RING * WP : pr;
 
   const int tid0 = threadIdx.x;
   const int H = a.H, W = a.W;
@@ -224,8 +242,8 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     }
     __syncthreads();
     // ---------------------------------------------------------------- P3
-    // The window sums overwrite the products they are made from: every thread first reads
-    // and sums its segments, then all write after a barrier.
+    // Where the window sums overwrite the products they are made from, every thread first
+    // reads and sums its segments, then all write after a barrier.
     float hv[C::K3][8];
 #pragma unroll
     for (int k = 0; k < C::K3; ++k) {
@@ -263,7 +281,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
         }
       }
     }
-    __syncthreads();
+    if constexpr (!kSplit) __syncthreads();
 #pragma unroll
     for (int k = 0; k < C::K3; ++k) {
       const int i = tid + k * NT;
@@ -442,7 +460,7 @@ hipError_t go_plain_v(const IterArgs& a, int nb, hipStream_t s) {
   const int ntiles = tx * ty;
   const int grid = (ntiles + 7) / 8 * 8;
   hipLaunchKernelGGL((lk_iter_strip<T, R, TW, MODE, WIDE, LEAN, GAUSS>), dim3(grid), dim3(C::NT),
-                     C::LDS_FLOATS * sizeof(float), s, a, TH, nb + 1, tx, ntiles);
+                     (lds_bytes<R, TW, WIDE, LEAN>()), s, a, TH, nb + 1, tx, ntiles);
   return hipGetLastError();
 }
 
@@ -468,7 +486,7 @@ hipError_t go_batch_v(const BatchLaunch& b, hipStream_t s) {
   constexpr int TW = strip_width<R>();
   using C = Cfg<R, TW, WIDE>;
   hipLaunchKernelGGL((lk_iter_batch<T, R, TW, MODE, WIDE, LEAN>), dim3(b.grid), dim3(C::NT),
-                     C::LDS_FLOATS * sizeof(float), s, b.args, b.tiles, b.ntiles);
+                     (lds_bytes<R, TW, WIDE, LEAN>()), s, b.args, b.tiles, b.ntiles);
   return hipGetLastError();
 }
 
