@@ -84,6 +84,11 @@ typedef enum {
 #define OF_TILE_NARROW 0
 #define OF_TILE_WIDE 1
 #define OF_TILE_WIDE_LEAN 2
+/* Plans with the box window only: the wide variant on strips of 32 or 16 output columns
+ * (instead of 64), for levels with fewer tiles than CUs: more, smaller tiles, each with a
+ * shorter path per band. */
+#define OF_TILE_WIDE32 3
+#define OF_TILE_WIDE16 4
 
 #define OF_MAX_LEVELS 12
 #define OF_MAX_RADIUS 12
@@ -144,16 +149,18 @@ OF_API of_status of_plan_set_mask(of_plan* plan, const uint8_t* mask, void* stre
 OF_API int of_levels_for_displacement(float dmax, int H, int W);
 
 /* Per-level launch configuration of a plan: bands[l] = tile height of the iteration kernel
- * in bands of 2r+1 rows (1..64), variant[l] = OF_TILE_* (default: WIDE for levels of under
- * 384 tiles, else WIDE_LEAN).  Arrays of `levels` entries.  set_config drops the plan's
- * captured graphs; OF_EINVAL for values out of range.  Results do not depend on the
- * configuration. */
+ * in bands of 2r+1 rows (1..64), variant[l] = OF_TILE_* (default: levels of under 384 tiles
+ * of 64 columns take WIDE32, or WIDE with OF_FLAG_GAUSSIAN_WINDOW, larger ones WIDE_LEAN;
+ * WIDE32 and WIDE16 are not available with OF_FLAG_GAUSSIAN_WINDOW).  Arrays of
+ * `levels` entries.  set_config drops the plan's captured graphs; OF_EINVAL for values out
+ * of range.  Results do not depend on the configuration. */
 OF_API of_status of_plan_get_config(const of_plan* plan, int* bands, int* variant);
 OF_API of_status of_plan_set_config(of_plan* plan, const int* bands, const int* variant);
 
 /* Autotuner: for each level in turn, times that level's iteration launches for bands in
- * {1,2,4,8} x the three tile variants on the given buffers (reps timed runs after one
- * warm-up) and keeps the fastest.  Synchronises `stream`; writes u, v. */
+ * {1,2,4,8} x the tile variants (five with the box window, three with the Gaussian window)
+ * on the given buffers (reps timed runs after one warm-up) and keeps the fastest.
+ * Synchronises `stream`; writes u, v. */
 OF_API of_status of_plan_autotune(of_plan* plan, const void* I1, const void* I2, float* u,
                                   float* v, void* stream, int reps);
 
@@ -209,8 +216,8 @@ OF_API of_status of_batch_compute(of_batch* b, const void* const* I1, const void
 
 /* Per-level launch configuration: bands[l] = tile height in bands of 2r+1 rows (1..64),
  * grid[l] = workgroups of the iteration launches (0 = one per tile, else a persistent grid
- * striding over the work list), variant[l] = OF_TILE_* or -1 for the default (WIDE for
- * launches of under 384 tiles, else WIDE_LEAN).  Arrays of `levels` entries; `variant` may
+ * striding over the work list), variant[l] = OF_TILE_NARROW, _WIDE or _WIDE_LEAN, or -1 for
+ * the default (WIDE for launches of under 384 tiles, else WIDE_LEAN).  Arrays of `levels` entries; `variant` may
  * be NULL (get: not returned; set: -1 for every level).  set_config rebuilds the work lists
  * and drops captured graphs. */
 OF_API of_status of_batch_get_config(const of_batch* b, int* bands, int* grid, int* variant);

@@ -25,6 +25,8 @@ OF_KERNEL_REDUCE = 1
 OF_TILE_NARROW = 0
 OF_TILE_WIDE = 1
 OF_TILE_WIDE_LEAN = 2
+OF_TILE_WIDE32 = 3
+OF_TILE_WIDE16 = 4
 
 # exported symbol -> (restype, argtypes)
 _c_int, _c_uint, _c_size, _vp = ctypes.c_int, ctypes.c_uint, ctypes.c_size_t, ctypes.c_void_p

@@ -43,7 +43,11 @@ hipError_t launch_reduce(Elem tin, Elem tout, const void* in1, const void* in2, 
 //              dependent path per band: launches with about one tile per CU);
 //   wide lean  10 threads per output column, indices recomputed every band (fewer live
 //              registers, so more resident workgroups: launches with many tiles).
-enum TileVariant : int { kTileNarrow = 0, kTileWide = 1, kTileWideLean = 2 };
+//   wide 32 /  the wide variant on strips of 32 or 16 output columns (plain launches of the
+//   wide 16    box window): small levels spread over more CUs, fewer waves per SIMD per tile,
+//              hence a shorter path per band where a level has fewer tiles than CUs.
+enum TileVariant : int { kTileNarrow = 0, kTileWide = 1, kTileWideLean = 2, kTileWide32 = 3,
+                         kTileWide16 = 4 };
 // Added to a plain launch's variant: Gaussian-weighted window sums (taps in IterArgs::taps).
 constexpr int kTileGauss = 16;
 
@@ -57,8 +61,12 @@ struct BatchLaunch {
   int variant;   // TileVariant
 };
 
-// Strip width (output columns per tile) and band height of the iteration kernel for radius R.
+// Strip width (output columns per tile) of the iteration kernel for radius R (variants 0-2).
 int strip_width_for(int R);
+// Strip width of a plain launch's tile variant.
+inline int tile_width(int variant, int R) {
+  return variant == kTileWide32 ? 32 : (variant == kTileWide16 ? 16 : strip_width_for(R));
+}
 
 // One fused Gauss-Newton iteration at one level (frames of element type `t`), tiles of height
 // (2R+1)*nb, tile variant `variant` (TileVariant).

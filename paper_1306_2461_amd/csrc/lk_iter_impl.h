@@ -451,9 +451,9 @@ constexpr int strip_width() {
   return Cfg<R, 64>::LDS_FLOATS * sizeof(float) <= 65536 ? 64 : 32;
 }
 
-template <typename T, int R, int MODE, bool WIDE, bool LEAN, bool GAUSS>
+template <typename T, int R, int MODE, bool WIDE, bool LEAN, bool GAUSS, int TWV = 0>
 hipError_t go_plain_v(const IterArgs& a, int nb, hipStream_t s) {
-  constexpr int TW = strip_width<R>();
+  constexpr int TW = TWV ? TWV : strip_width<R>();
   using C = Cfg<R, TW, WIDE>;
   const int TH = C::N * nb;
   const int tx = (a.W + TW - 1) / TW, ty = (a.H + TH - 1) / TH;
@@ -470,6 +470,12 @@ hipError_t go_plain_g(const IterArgs& a, int nb, int variant, hipStream_t s) {
     case kTileNarrow: return go_plain_v<T, R, MODE, false, true, GAUSS>(a, nb, s);
     case kTileWide: return go_plain_v<T, R, MODE, true, false, GAUSS>(a, nb, s);
     case kTileWideLean: return go_plain_v<T, R, MODE, true, true, GAUSS>(a, nb, s);
+  }
+  if constexpr (!GAUSS) {   // narrow strips: box window only
+    switch (variant) {
+      case kTileWide32: return go_plain_v<T, R, MODE, true, false, false, 32>(a, nb, s);
+      case kTileWide16: return go_plain_v<T, R, MODE, true, false, false, 16>(a, nb, s);
+    }
   }
   return hipErrorInvalidValue;
 }

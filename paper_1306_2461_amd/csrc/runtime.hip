@@ -63,9 +63,13 @@ Geometry make_geometry(int H, int W, int levels, int radius, int iters, unsigned
   for (int l = 0; l < levels; ++l) {
     g.nb[l] = default_bands(g.H[l], g.W[l], radius);
     {
+      // Plans: about one tile per CU or fewer on 64-column strips -> the wide variant on
+      // 32-column strips (box window; the fastest measured at 1024^2 and below), else the
+      // batch default.
       const long long tx = (g.W[l] + strip_width_for(radius) - 1) / strip_width_for(radius);
       const long long th = (long long)(2 * radius + 1) * g.nb[l];
-      g.variant[l] = default_tile_variant(tx * ((g.H[l] + th - 1) / th));
+      const int v = default_tile_variant(tx * ((g.H[l] + th - 1) / th));
+      g.variant[l] = (v == kTileWide && !(flags & OF_FLAG_GAUSSIAN_WINDOW)) ? kTileWide32 : v;
     }
   }
   g.ein = (flags & OF_FLAG_INPUT_F32) ? Elem::F32 : Elem::U8;
@@ -378,8 +382,9 @@ const char* of_last_error(void) { return g_last_error.c_str(); }
 
 namespace {
 
+// Tile count of level l at one band per tile on the narrowest strips (16 columns).
 size_t tile_capacity(const Geometry& g, int l) {
-  const size_t tx = (g.W[l] + strip_width_for(g.R) - 1) / strip_width_for(g.R);
+  const size_t tx = (g.W[l] + 15) / 16;
   return tx * ((g.H[l] + 2 * g.R) / (2 * g.R + 1));
 }
 
@@ -387,7 +392,7 @@ size_t tile_capacity(const Geometry& g, int l) {
 // uploaded to the plan's flag buffer (synchronous copy: outside graph capture only).
 hipError_t upload_tile_flags(of_plan* p, int l) {
   Geometry& g = p->g;
-  const int TW = strip_width_for(g.R), TH = (2 * g.R + 1) * g.nb[l];
+  const int TW = tile_width(g.variant[l], g.R), TH = (2 * g.R + 1) * g.nb[l];
   const int H = g.H[l], W = g.W[l];
   const int tx = (W + TW - 1) / TW, ty = (H + TH - 1) / TH;
   std::vector<uint8_t> f((size_t)tx * ty);
@@ -492,8 +497,10 @@ of_status of_plan_set_config(of_plan* p, const int* bands, const int* variant) {
   if (!p || !bands || !variant) return set_error("NULL argument"), OF_EINVAL;
   for (int l = 0; l < p->g.L; ++l) {
     if (bands[l] < 1 || bands[l] > 64) return set_error("bands out of range"), OF_EINVAL;
-    if (variant[l] < kTileNarrow || variant[l] > kTileWideLean)
+    if (variant[l] < kTileNarrow || variant[l] > kTileWide16)
       return set_error("tile variant out of range"), OF_EINVAL;
+    if (variant[l] > kTileWideLean && (p->g.flags & OF_FLAG_GAUSSIAN_WINDOW))
+      return set_error("narrow-strip variants apply to the box window only"), OF_EINVAL;
   }
   DeviceGuard guard(p->device);
   hipDeviceSynchronize();
@@ -524,7 +531,8 @@ of_status of_plan_autotune(of_plan* p, const void* I1, const void* I2, float* u,
     int bw = g.variant[l];
     for (int nb : kBands) {
       if (nb > 1 && (2 * g.R + 1) * nb > 2 * g.H[l]) continue;
-      for (int w = kTileNarrow; w <= kTileWideLean; ++w) {
+      const int last = (g.flags & OF_FLAG_GAUSSIAN_WINDOW) ? kTileWideLean : kTileWide16;
+      for (int w = kTileNarrow; w <= last; ++w) {
         g.nb[l] = nb;
         g.variant[l] = w;
         if (g.mask[l]) e = upload_tile_flags(p, l);

@@ -37,6 +37,12 @@ def test_masked_plan_matches_oracle_and_skips_tiles(gpu_lib):
         ou, ov = oracle.flow(I1, I2, 3, 4, 4, mask=M.astype(bool))
         d = flow_error(gu, gv, ou, ov)
         assert d.max() <= 1e-3, report(d, 1e-3)
+    # other tile widths skip other tiles and give the same bits
+    for cfg in ({"bands": [1, 1, 1], "variant": [4, 4, 3]}, {"bands": [4, 2, 1], "variant": [0, 3, 2]}):
+        plan.set_config(cfg)
+        u, v = plan.compute(to_dev(I1), to_dev(I2))
+        torch.cuda.synchronize()
+        assert np.array_equal(u.cpu().numpy(), gu) and np.array_equal(v.cpu().numpy(), gv), cfg
     # the same plan without the mask again gives the unmasked bits
     plan.set_mask(None)
     u, v = plan.compute(to_dev(I1), to_dev(I2))
@@ -55,7 +61,8 @@ def test_all_ones_mask_keeps_bits_and_configs(gpu_lib):
     torch.cuda.synchronize()
     ref = (u0.cpu().numpy(), v0.cpu().numpy())
     plan.set_mask(to_dev(np.ones((200, 231), np.uint8)))
-    for cfg in ({"bands": [1, 1, 1], "variant": [0, 0, 0]}, {"bands": [2, 1, 1], "variant": [1, 2, 1]}):
+    for cfg in ({"bands": [1, 1, 1], "variant": [0, 0, 0]}, {"bands": [2, 1, 1], "variant": [1, 2, 1]},
+                {"bands": [1, 2, 1], "variant": [4, 3, 4]}):
         announce(f"all-ones mask, config {cfg}")
         plan.set_config(cfg)
         u, v = plan.compute(to_dev(I1), to_dev(I2))

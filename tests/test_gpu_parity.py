@@ -244,13 +244,14 @@ def test_plan_configs_and_autotune_keep_bits(gpu_lib):
     torch.cuda.synchronize()
     ref = (u0.cpu().numpy(), v0.cpu().numpy())
     for cfg in ({"bands": [1, 1, 1], "variant": [0, 0, 0]}, {"bands": [8, 4, 2], "variant": [1, 1, 1]},
-                {"bands": [2, 8, 1], "variant": [0, 1, 2]}, {"bands": [1, 2, 4], "variant": [2, 2, 2]}):
+                {"bands": [2, 8, 1], "variant": [0, 1, 2]}, {"bands": [1, 2, 4], "variant": [2, 2, 2]},
+                {"bands": [1, 1, 1], "variant": [3, 4, 4]}, {"bands": [2, 1, 4], "variant": [4, 3, 3]}):
         announce(f"plan config {cfg}")
         plan.set_config(cfg)
         u, v = plan.compute(d1, d2)
         torch.cuda.synchronize()
         assert np.array_equal(u.cpu().numpy(), ref[0]) and np.array_equal(v.cpu().numpy(), ref[1]), cfg
-    for bad in ({"bands": [1, 1, 1], "variant": [0, 3, 0]}, {"bands": [0, 1, 1], "variant": [0, 0, 0]}):
+    for bad in ({"bands": [1, 1, 1], "variant": [0, 5, 0]}, {"bands": [0, 1, 1], "variant": [0, 0, 0]}):
         with pytest.raises(ofmi.OfError):
             plan.set_config(bad)
     announce("plan autotune")
