@@ -89,6 +89,12 @@ typedef enum {
  * shorter path per band. */
 #define OF_TILE_WIDE32 3
 #define OF_TILE_WIDE16 4
+/* Plans with the box window and r <= 8 only: WIDE32 / WIDE16 with two bands per pass (20
+ * threads per output column): a tile's priming band and first output band (a tile of one
+ * output band is exactly these two) take one dependent path through the kernel instead of
+ * two, for levels of about one tile per CU. */
+#define OF_TILE_WIDE32X2 5
+#define OF_TILE_WIDE16X2 6
 
 #define OF_MAX_LEVELS 12
 #define OF_MAX_RADIUS 12
@@ -149,16 +155,18 @@ OF_API of_status of_plan_set_mask(of_plan* plan, const uint8_t* mask, void* stre
 OF_API int of_levels_for_displacement(float dmax, int H, int W);
 
 /* Per-level launch configuration of a plan: bands[l] = tile height of the iteration kernel
- * in bands of 2r+1 rows (1..64), variant[l] = OF_TILE_* (default: levels of under 384 tiles
- * of 64 columns take WIDE32, or WIDE with OF_FLAG_GAUSSIAN_WINDOW, larger ones WIDE_LEAN;
- * WIDE32 and WIDE16 are not available with OF_FLAG_GAUSSIAN_WINDOW).  Arrays of
- * `levels` entries.  set_config drops the plan's captured graphs; OF_EINVAL for values out
+ * in bands of 2r+1 rows (1..64), variant[l] = OF_TILE_* (default: levels of under 128 tiles
+ * of 64 columns take WIDE16X2 (WIDE32 above r = 8), of under 384 tiles WIDE32, both WIDE with
+ * OF_FLAG_GAUSSIAN_WINDOW, larger ones WIDE_LEAN;
+ * WIDE32, WIDE16, WIDE32X2 and WIDE16X2 are not available with OF_FLAG_GAUSSIAN_WINDOW,
+ * WIDE32X2 and WIDE16X2 not above r = 8).  Arrays of `levels` entries.  set_config drops the plan's captured graphs; OF_EINVAL for values out
  * of range.  Results do not depend on the configuration. */
 OF_API of_status of_plan_get_config(const of_plan* plan, int* bands, int* variant);
 OF_API of_status of_plan_set_config(of_plan* plan, const int* bands, const int* variant);
 
 /* Autotuner: for each level in turn, times that level's iteration launches for bands in
- * {1,2,4,8} x the tile variants (five with the box window, three with the Gaussian window)
+ * {1,2,3,4,8} x the tile variants the plan allows (seven with the box window and r <= 8, five
+ * with the box window above, three with the Gaussian window)
  * on the given buffers (reps timed runs after one warm-up) and keeps the fastest.
  * Synchronises `stream`; writes u, v. */
 OF_API of_status of_plan_autotune(of_plan* plan, const void* I1, const void* I2, float* u,

@@ -46,8 +46,14 @@ hipError_t launch_reduce(Elem tin, Elem tout, const void* in1, const void* in2, 
 //   wide 32 /  the wide variant on strips of 32 or 16 output columns (plain launches of the
 //   wide 16    box window): small levels spread over more CUs, fewer waves per SIMD per tile,
 //              hence a shorter path per band where a level has fewer tiles than CUs.
+//   wide 32x2 / the same strips with two bands per pass and 20 threads per output column
+//   wide 16x2   (plain launches of the box window, r <= kMaxPairRadius): a tile of one output
+//              band runs its priming band and its output band together, one dependent path.
 enum TileVariant : int { kTileNarrow = 0, kTileWide = 1, kTileWideLean = 2, kTileWide32 = 3,
-                         kTileWide16 = 4 };
+                         kTileWide16 = 4, kTileWide32x2 = 5, kTileWide16x2 = 6 };
+constexpr int kTileVariants = 7;
+// Largest window radius of the two-bands-per-pass variants (their LDS stays within 64 KB).
+constexpr int kMaxPairRadius = 8;
 // Added to a plain launch's variant: Gaussian-weighted window sums (taps in IterArgs::taps).
 constexpr int kTileGauss = 16;
 
@@ -65,7 +71,18 @@ struct BatchLaunch {
 int strip_width_for(int R);
 // Strip width of a plain launch's tile variant.
 inline int tile_width(int variant, int R) {
-  return variant == kTileWide32 ? 32 : (variant == kTileWide16 ? 16 : strip_width_for(R));
+  if (variant == kTileWide32 || variant == kTileWide32x2) return 32;
+  if (variant == kTileWide16 || variant == kTileWide16x2) return 16;
+  return strip_width_for(R);
+}
+// Whether a plain launch of radius R (Gaussian-weighted window or not) has tile variant
+// `variant`: narrow strips only with the box window, two bands per pass only up to
+// kMaxPairRadius.
+inline bool tile_variant_valid(int variant, int R, bool gaussian) {
+  if (variant < kTileNarrow || variant >= kTileVariants) return false;
+  if (gaussian && variant > kTileWideLean) return false;
+  if ((variant == kTileWide32x2 || variant == kTileWide16x2) && R > kMaxPairRadius) return false;
+  return true;
 }
 
 // One fused Gauss-Newton iteration at one level (frames of element type `t`), tiles of height

@@ -28,41 +28,45 @@ namespace ofmi {
 
 namespace {
 
-template <int R, int TW_, bool WIDE = false>
+template <int R, int TW_, bool WIDE = false, int BB = 1>
 struct Cfg {
   static constexpr int N = 2 * R + 1;                 // band height = window height
+  static constexpr int NR = BB * N;                   // product rows per pass (BB bands)
   static constexpr int TW = TW_;                      // output columns per strip
-  static constexpr int NT = (WIDE ? 10 : 5) * TW;     // threads per workgroup
+  static constexpr int NT = (WIDE ? 10 : 5) * TW * BB;   // threads per workgroup
   static constexpr int PC = TW + 2 * R;               // product columns
   static constexpr int WC = PC + 2;                   // warped-frame columns
   static constexpr int HL = 8 + 2 * R;                // products read per horizontal segment
   static constexpr int HL4 = (HL + 3) / 4;            // ... in float4 units
   static constexpr int PP = ((TW + 4 * HL4 - 8) + 3) / 4 * 4 + 4;  // product row pitch
   static constexpr int WP = WC + 1;                   // warped-frame row pitch
-  static constexpr int RING = N + 2 <= 16 ? 16 : 32;  // warped-frame ring rows (power of 2)
+  // Warped-frame rows held in LDS: one band per pass keeps a power-of-two ring (the two rows
+  // shared with the next band stay); two bands per pass sample all NR + 2 rows every pass.
+  static constexpr int RING = N + 2 <= 16 ? 16 : 32;
+  static constexpr int WROWS = BB == 1 ? RING : NR + 2;
   static constexpr int NSEG = TW / 8;
-  static constexpr int P1_ROWS_MAX = N + 2;
+  static constexpr int P1_ROWS_MAX = NR + 2;
   static constexpr int K1 = (P1_ROWS_MAX * WC + NT - 1) / NT;   // P1 items per thread
-  static constexpr int K2 = (N * PC + NT - 1) / NT;             // P2 items per thread
-  static constexpr int K3 = (5 * N * NSEG + NT - 1) / NT;       // P3 items per thread
-  static constexpr int K5 = (N * TW + NT - 1) / NT;             // P5 items per thread
-  // The window sums [5][N][TW] reuse the product buffer [5][N][PP] once P3 has read it, or
-  // (SPLIT) have a region of their own after the ring, which saves P3's second barrier.
-  static constexpr size_t LDS_FLOATS = 5 * (size_t)N * PP + (size_t)RING * WP;
-  static constexpr size_t HS_FLOATS = 5 * (size_t)N * TW;
+  static constexpr int K2 = (NR * PC + NT - 1) / NT;            // P2 items per thread
+  static constexpr int K3 = (5 * NR * NSEG + NT - 1) / NT;      // P3 items per thread
+  static constexpr int K5 = (NR * TW + NT - 1) / NT;            // P5 items per thread
+  // The window sums [5][NR][TW] reuse the product buffer [5][NR][PP] once P3 has read it, or
+  // (SPLIT) have a region of their own after the warped rows, which saves P3's second barrier.
+  static constexpr size_t LDS_FLOATS = 5 * (size_t)NR * PP + (size_t)WROWS * WP;
+  static constexpr size_t HS_FLOATS = 5 * (size_t)NR * TW;
   static constexpr bool SPLIT_FITS = (LDS_FLOATS + HS_FLOATS) * sizeof(float) <= 65536;
 };
 
 // Separate window-sum region for the wide (latency) variant where it fits in 64 KB: that
 // variant runs about one workgroup per CU, so the larger LDS footprint costs no occupancy.
-template <int R, int TW, bool WIDE, bool LEAN>
+template <int R, int TW, bool WIDE, bool LEAN, int BB = 1>
 constexpr bool split_hs() {
-  return WIDE && !LEAN && Cfg<R, TW, WIDE>::SPLIT_FITS;
+  return WIDE && !LEAN && Cfg<R, TW, WIDE, BB>::SPLIT_FITS;
 }
-template <int R, int TW, bool WIDE, bool LEAN>
+template <int R, int TW, bool WIDE, bool LEAN, int BB = 1>
 constexpr size_t lds_bytes() {
-  using C = Cfg<R, TW, WIDE>;
-  return (C::LDS_FLOATS + (split_hs<R, TW, WIDE, LEAN>() ? C::HS_FLOATS : 0)) * sizeof(float);
+  using C = Cfg<R, TW, WIDE, BB>;
+  return (C::LDS_FLOATS + (split_hs<R, TW, WIDE, LEAN, BB>() ? C::HS_FLOATS : 0)) * sizeof(float);
 }
 
 // One tile: TW output columns from x0 = bx*TW and TH output rows from y0 = by*TH, walked in
@@ -77,20 +81,25 @@ constexpr size_t lds_bytes() {
 // GAUSS: window sums weighted by the separable taps a.taps[0..2r] (Gaussian-weighted window)
 // instead of the unweighted box: every horizontal and vertical sum is a direct 2r+1-term
 // weighted sum in a fixed order, so results remain independent of the tiling.
+// BB: bands per pass.  With BB = 2 the phases run over two bands' rows at once with twice the
+// threads, so a tile of two bands (one output band and the band that primes the vertical
+// sums) is one pass of the dependent path instead of two; P4 walks the two bands in order,
+// with the same additions as two single-band passes.  nbands is then even.
 template <typename T, int R, int TW, int MODE, bool WIDE, bool DEFER, bool INTERIOR, bool LEAN,
-          bool GAUSS = false>
+          bool GAUSS = false, int BB = 1>
 __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands, int bx, int by,
                                            bool pixel_mask, float4* sm4) {
-  using C = Cfg<R, TW, WIDE>;
-  constexpr int N = C::N, NT = C::NT, PC = C::PC, WC = C::WC, PP = C::PP, WP = C::WP;
+  using C = Cfg<R, TW, WIDE, BB>;
+  constexpr int N = C::N, NR = C::NR, NT = C::NT, PC = C::PC, WC = C::WC, PP = C::PP, WP = C::WP;
   constexpr int RMASK = C::RING - 1;
+  static_assert(BB == 1 || BB == 2, "one or two bands per pass");
   float* sm = reinterpret_cast<float*>(sm4);
-  constexpr bool kSplit = split_hs<R, TW, WIDE, LEAN>();
-  float* pr = sm;                               // [5][N][PP] products (16-byte aligned rows)
-  float* w2 = pr + 5 * N * PP;                  // [RING][WP] warped frame ring
-  // [5][N][TW] horizontal, then window sums (16-byte aligned: RING*WP is a multiple of 4 here
-  // or the region aliases the products)
-  float* hs = kSplit ? w2 + C::RING * WP : pr;
+  constexpr bool kSplit = split_hs<R, TW, WIDE, LEAN, BB>();
+  float* pr = sm;                               // [5][NR][PP] products (16-byte aligned rows)
+  float* w2 = pr + 5 * NR * PP;                 // [WROWS][WP] warped frame
+  // [5][NR][TW] horizontal, then window sums (16-byte aligned: WROWS*WP is a multiple of 4
+  // here or the region aliases the products)
+  float* hs = kSplit ? w2 + C::WROWS * WP : pr;
 
   const int tid0 = threadIdx.x;
   const int H = a.H, W = a.W;
@@ -106,8 +115,8 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
 #pragma unroll
   for (int i = 0; i < N; ++i) prev[i] = 0.f;
 
-  for (int b = 0; b < nbands; ++b) {
-    const int tb = N * b;                        // first product row of the band
+  for (int b = 0; b < nbands; b += BB) {
+    const int tb = N * b;                        // first product row of the pass
     // LEAN: the thread index is re-materialised per band, opaque to the optimiser, so the
     // item indices derived from it are not hoisted out of the loop.
     int tid = tid0;
@@ -120,8 +129,8 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     // variants a scheduling barrier keeps the last group after the samples are stored: issued
     // together the groups are all live at once (the kernel's register peak); the split costs
     // one more dependent load round per band and buys resident workgroups.
-    const int wfirst = b == 0 ? -1 : tb + 1;
-    const int nw = (b == 0 ? N + 2 : N) * WC;
+    const int wfirst = (BB == 2 || b == 0) ? tb - 1 : tb + 1;
+    const int nw = ((BB == 2 || b == 0) ? NR + 2 : N) * WC;
     int wofs[C::K1], wgx[C::K1], wgy[C::K1];
     float wu[C::K1], wv[C::K1];
 #pragma unroll
@@ -135,7 +144,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
         wgx[k] = min(max(x0 - R - 1 + lx, 0), W - 1);
         wgy[k] = min(max(y0 - R + w, 0), H - 1);
       }
-      wofs[k] = (w & RMASK) * WP + lx;
+      wofs[k] = (BB == 1 ? (w & RMASK) : w - (tb - 1)) * WP + lx;
       read_flow<MODE>(a, wgx[k], wgy[k], wu[k], wv[k]);
     }
     // In the coarse-field mode each field value costs eight loads: where registers are tight
@@ -149,7 +158,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     if constexpr (!LEAN) {
 #pragma unroll
       for (int k = 0; k < C::K2; ++k) {
-        const int i = min(tid + k * NT, N * PC - 1);
+        const int i = min(tid + k * NT, NR * PC - 1);
         int gx = x0 - R + i % PC, gy = y0 - R + tb + i / PC;
         if constexpr (!INTERIOR) {
           gx = min(max(gx, 0), W - 1);
@@ -161,7 +170,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
       if constexpr (!kDefer) {
 #pragma unroll
         for (int k = 0; k < C::K5; ++k) {
-          const int i = min(tid + k * NT, N * TW - 1);
+          const int i = min(tid + k * NT, NR * TW - 1);
           const int gx = INTERIOR ? x0 + i % TW : min(x0 + i % TW, W - 1);
           const int gy = min(max(y0 + tb + i / TW - 2 * R, 0), H - 1);
           read_flow<MODE>(a, gx, gy, cu[k], cv[k]);
@@ -177,7 +186,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
       __builtin_amdgcn_sched_barrier(0);   // compiler-only fence
 #pragma unroll
       for (int k = 0; k < C::K2; ++k) {
-        const int i = min(tid + k * NT, N * PC - 1);
+        const int i = min(tid + k * NT, NR * PC - 1);
         int gx = x0 - R + i % PC, gy = y0 - R + tb + i / PC;
         if constexpr (!INTERIOR) {
           gx = min(max(gx, 0), W - 1);
@@ -189,7 +198,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
       if constexpr (!kDefer) {
 #pragma unroll
         for (int k = 0; k < C::K5; ++k) {
-          const int i = min(tid + k * NT, N * TW - 1);
+          const int i = min(tid + k * NT, NR * TW - 1);
           const int gx = INTERIOR ? x0 + i % TW : min(x0 + i % TW, W - 1);
           const int gy = min(max(y0 + tb + i / TW - 2 * R, 0), H - 1);
           read_flow<MODE>(a, gx, gy, cu[k], cv[k]);
@@ -201,7 +210,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     if constexpr (kDefer) {
 #pragma unroll
       for (int k = 0; k < C::K2; ++k) {
-        const int i = min(tid + k * NT, N * PC - 1);
+        const int i = min(tid + k * NT, NR * PC - 1);
         int gx = x0 - R + i % PC, gy = y0 - R + tb + i / PC;
         if constexpr (!INTERIOR) {
           gx = min(max(gx, 0), W - 1);
@@ -213,13 +222,16 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
 #pragma unroll
     for (int k = 0; k < C::K2; ++k) {
       const int i = tid + k * NT;
-      if (i < N * PC) {
+      if (i < NR * PC) {
         const int r = i / PC, c = i % PC;
         const int t = tb + r;
         const int gx = x0 - R + c, gy = y0 - R + t;
         float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f, p4 = 0.f;
         if (INTERIOR || (gx >= 0 && gx < W && gy >= 0 && gy < H)) {
-          const int s0 = t & RMASK, sm1 = (t - 1) & RMASK, sp1 = (t + 1) & RMASK;
+          // warped row t sits in ring slot t & RMASK, or (two bands per pass) in row r + 1
+          const int s0 = BB == 1 ? t & RMASK : r + 1;
+          const int sm1 = BB == 1 ? (t - 1) & RMASK : r;
+          const int sp1 = BB == 1 ? (t + 1) & RMASK : r + 2;
           const float* row = w2 + s0 * WP + c + 1;
           const float ix = 0.5f * (row[1] - row[-1]);
           const float iy = 0.5f * (w2[sp1 * WP + c + 1] - w2[sm1 * WP + c + 1]);
@@ -234,10 +246,10 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
         }
         float* q = pr + r * PP + c;
         q[0] = p0;
-        q[N * PP] = p1;
-        q[2 * N * PP] = p2;
-        q[3 * N * PP] = p3;
-        q[4 * N * PP] = p4;
+        q[NR * PP] = p1;
+        q[2 * NR * PP] = p2;
+        q[3 * NR * PP] = p3;
+        q[4 * NR * PP] = p4;
       }
     }
     __syncthreads();
@@ -248,8 +260,8 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
 #pragma unroll
     for (int k = 0; k < C::K3; ++k) {
       const int i = tid + k * NT;
-      if (i < 5 * N * C::NSEG) {
-        const int seg = i % C::NSEG, rr = i / C::NSEG;   // rr = ch * N + row
+      if (i < 5 * NR * C::NSEG) {
+        const int seg = i % C::NSEG, rr = i / C::NSEG;   // rr = ch * NR + row
         const float4* src = reinterpret_cast<const float4*>(pr + rr * PP + 8 * seg);
         float vbuf[4 * C::HL4];
 #pragma unroll
@@ -285,7 +297,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
 #pragma unroll
     for (int k = 0; k < C::K3; ++k) {
       const int i = tid + k * NT;
-      if (i < 5 * N * C::NSEG) {
+      if (i < 5 * NR * C::NSEG) {
         const int seg = i % C::NSEG, rr = i / C::NSEG;
         float4* dst = reinterpret_cast<float4*>(hs + rr * C::TW + 8 * seg);
         dst[0] = make_float4(hv[k][0], hv[k][1], hv[k][2], hv[k][3]);
@@ -294,6 +306,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     }
     __syncthreads();
     // ---------------------------------------------------------------- P4
+    static_assert(!GAUSS || BB == 1, "Gaussian-weighted window: one band per pass");
     if (GAUSS && p4) {
       // Output row r of the band: previous-band rows r+1..N-1 then current rows 0..r, i.e.
       // window offsets 0..N-1 from its top row, weighted by the taps in that order.
@@ -313,17 +326,20 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
 #pragma unroll
       for (int r = 0; r < N; ++r) prev[r] = cur[r];
     } else if (p4) {
-      float* col = hs + vk * N * TW + vc;
-      // prev[r] <- prev[r] + ... + prev[N-1] (suffix sums of the previous band, in place)
 #pragma unroll
-      for (int r = N - 2; r >= 0; --r) prev[r] += prev[r + 1];
-      float pre = 0.f;
+      for (int bb = 0; bb < BB; ++bb) {
+        float* col = hs + vk * NR * TW + bb * N * TW + vc;
+        // prev[r] <- prev[r] + ... + prev[N-1] (suffix sums of the previous band, in place)
 #pragma unroll
-      for (int r = 0; r < N; ++r) {
-        const float c = col[r * TW];
-        pre = r == 0 ? c : pre + c;
-        col[r * TW] = r + 1 < N ? prev[r + 1] + pre : pre;
-        prev[r] = c;
+        for (int r = N - 2; r >= 0; --r) prev[r] += prev[r + 1];
+        float pre = 0.f;
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+          const float c = col[r * TW];
+          pre = r == 0 ? c : pre + c;
+          col[r * TW] = r + 1 < N ? prev[r + 1] + pre : pre;
+          prev[r] = c;
+        }
       }
     }
     __syncthreads();
@@ -331,7 +347,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     if constexpr (kDefer) {
 #pragma unroll
       for (int k = 0; k < C::K5; ++k) {
-        const int i = min(tid + k * NT, N * TW - 1);
+        const int i = min(tid + k * NT, NR * TW - 1);
         const int gx = INTERIOR ? x0 + i % TW : min(x0 + i % TW, W - 1);
         const int gy = min(max(y0 + tb + i / TW - 2 * R, 0), H - 1);
         read_flow<MODE>(a, gx, gy, cu[k], cv[k]);
@@ -340,14 +356,14 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
 #pragma unroll
     for (int k = 0; k < C::K5; ++k) {
       const int i = tid + k * NT;
-      if (i < N * TW) {
+      if (i < NR * TW) {
         const int r = i / TW, c = i % TW;
         const int j = tb + r - 2 * R;
         const int gx = x0 + c, gy = y0 + j;
         if (j >= 0 && j < TH && (INTERIOR || (gx < W && gy < H))) {
           const float* s = hs + r * TW + c;
           float un, vn;
-          solve_update(s[0], s[N * TW], s[2 * N * TW], s[3 * N * TW], s[4 * N * TW], cu[k],
+          solve_update(s[0], s[NR * TW], s[2 * NR * TW], s[3 * NR * TW], s[4 * NR * TW], cu[k],
                        cv[k], un, vn);
           const unsigned o = (unsigned)gy * (unsigned)W + (unsigned)gx;
           if (pixel_mask && at(a.mask, o) == 0) {   // masked-out pixel: zero flow
@@ -359,9 +375,9 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
         }
       }
     }
-    // The next band's P1 writes only ring rows that this band's P2 finished reading before
+    // The next pass's P1 writes only warped rows that this pass's P2 finished reading before
     // the barriers above; its P2 rewrites the product/window-sum buffer after the P1 barrier,
-    // when every thread has finished this band's P5.
+    // when every thread has finished this pass's P5.
   }
 }
 
@@ -398,9 +414,10 @@ __device__ __forceinline__ int xcd_order(int b, int nblocks) {
   return (b % kXcd) * per + b / kXcd;
 }
 
-template <typename T, int R, int TW, int MODE, bool WIDE, bool LEAN, bool GAUSS>
-__global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_strip(IterArgs a, int TH, int nbands,
-                                                                      int tiles_x, int ntiles) {
+template <typename T, int R, int TW, int MODE, bool WIDE, bool LEAN, bool GAUSS, int BB>
+__global__ __launch_bounds__((WIDE ? 10 : 5) * TW * BB) void lk_iter_strip(IterArgs a, int TH,
+                                                                           int nbands, int tiles_x,
+                                                                           int ntiles) {
   extern __shared__ float4 sm4[];
   const int t = xcd_order(blockIdx.x, gridDim.x);
   if (t >= ntiles) return;
@@ -416,11 +433,11 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_strip(IterArgs a
   }
   constexpr bool kDefer = WIDE || R > 8;
   if (R <= 8 && tile_interior<R, TW>(a, TH, nbands, bx, by))
-    strip_tile<T, R, TW, MODE, WIDE, kDefer, true, LEAN, GAUSS>(a, TH, nbands, bx, by, pixel_mask,
-                                                                sm4);
+    strip_tile<T, R, TW, MODE, WIDE, kDefer, true, LEAN, GAUSS, BB>(a, TH, nbands, bx, by,
+                                                                    pixel_mask, sm4);
   else
-    strip_tile<T, R, TW, MODE, WIDE, kDefer, false, LEAN, GAUSS>(a, TH, nbands, bx, by, pixel_mask,
-                                                                 sm4);
+    strip_tile<T, R, TW, MODE, WIDE, kDefer, false, LEAN, GAUSS, BB>(a, TH, nbands, bx, by,
+                                                                     pixel_mask, sm4);
 }
 
 // Batched form: workgroups stride over a work list of tiles of many pairs at the same
@@ -451,16 +468,21 @@ constexpr int strip_width() {
   return Cfg<R, 64>::LDS_FLOATS * sizeof(float) <= 65536 ? 64 : 32;
 }
 
-template <typename T, int R, int MODE, bool WIDE, bool LEAN, bool GAUSS, int TWV = 0>
+// nb output bands per tile take nb + 1 bands (the first primes the vertical sums), rounded up
+// to whole passes of BB bands (a band past the tile's rows writes nothing).
+template <typename T, int R, int MODE, bool WIDE, bool LEAN, bool GAUSS, int TWV = 0, int BB = 1>
 hipError_t go_plain_v(const IterArgs& a, int nb, hipStream_t s) {
   constexpr int TW = TWV ? TWV : strip_width<R>();
-  using C = Cfg<R, TW, WIDE>;
+  using C = Cfg<R, TW, WIDE, BB>;
+  static_assert(lds_bytes<R, TW, WIDE, LEAN, BB>() <= 65536, "LDS footprint above 64 KB");
   const int TH = C::N * nb;
   const int tx = (a.W + TW - 1) / TW, ty = (a.H + TH - 1) / TH;
   const int ntiles = tx * ty;
   const int grid = (ntiles + 7) / 8 * 8;
-  hipLaunchKernelGGL((lk_iter_strip<T, R, TW, MODE, WIDE, LEAN, GAUSS>), dim3(grid), dim3(C::NT),
-                     (lds_bytes<R, TW, WIDE, LEAN>()), s, a, TH, nb + 1, tx, ntiles);
+  const int nbands = (nb + 1 + BB - 1) / BB * BB;
+  hipLaunchKernelGGL((lk_iter_strip<T, R, TW, MODE, WIDE, LEAN, GAUSS, BB>), dim3(grid),
+                     dim3(C::NT), (lds_bytes<R, TW, WIDE, LEAN, BB>()), s, a, TH, nbands, tx,
+                     ntiles);
   return hipGetLastError();
 }
 
@@ -475,6 +497,12 @@ hipError_t go_plain_g(const IterArgs& a, int nb, int variant, hipStream_t s) {
     switch (variant) {
       case kTileWide32: return go_plain_v<T, R, MODE, true, false, false, 32>(a, nb, s);
       case kTileWide16: return go_plain_v<T, R, MODE, true, false, false, 16>(a, nb, s);
+    }
+    if constexpr (R <= kMaxPairRadius) {   // two bands per pass
+      switch (variant) {
+        case kTileWide32x2: return go_plain_v<T, R, MODE, true, false, false, 32, 2>(a, nb, s);
+        case kTileWide16x2: return go_plain_v<T, R, MODE, true, false, false, 16, 2>(a, nb, s);
+      }
     }
   }
   return hipErrorInvalidValue;

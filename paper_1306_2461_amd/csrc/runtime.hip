@@ -63,13 +63,17 @@ Geometry make_geometry(int H, int W, int levels, int radius, int iters, unsigned
   for (int l = 0; l < levels; ++l) {
     g.nb[l] = default_bands(g.H[l], g.W[l], radius);
     {
-      // Plans: about one tile per CU or fewer on 64-column strips -> the wide variant on
-      // 32-column strips (box window; the fastest measured at 1024^2 and below), else the
-      // batch default.
+      // Plans with the box window (the fastest measured at 1024^2 and below): levels of at
+      // most half a tile per CU on 64-column strips take 16-column strips with two bands per
+      // pass (r <= 8), about one tile per CU the wide variant on 32-column strips; otherwise,
+      // and with the Gaussian-weighted window, the batch default.
       const long long tx = (g.W[l] + strip_width_for(radius) - 1) / strip_width_for(radius);
       const long long th = (long long)(2 * radius + 1) * g.nb[l];
-      const int v = default_tile_variant(tx * ((g.H[l] + th - 1) / th));
-      g.variant[l] = (v == kTileWide && !(flags & OF_FLAG_GAUSSIAN_WINDOW)) ? kTileWide32 : v;
+      const long long nt = tx * ((g.H[l] + th - 1) / th);
+      const int v = default_tile_variant(nt);
+      g.variant[l] = v;
+      if (v == kTileWide && !(flags & OF_FLAG_GAUSSIAN_WINDOW))
+        g.variant[l] = nt < 128 && radius <= kMaxPairRadius ? kTileWide16x2 : kTileWide32;
     }
   }
   g.ein = (flags & OF_FLAG_INPUT_F32) ? Elem::F32 : Elem::U8;
@@ -497,10 +501,12 @@ of_status of_plan_set_config(of_plan* p, const int* bands, const int* variant) {
   if (!p || !bands || !variant) return set_error("NULL argument"), OF_EINVAL;
   for (int l = 0; l < p->g.L; ++l) {
     if (bands[l] < 1 || bands[l] > 64) return set_error("bands out of range"), OF_EINVAL;
-    if (variant[l] < kTileNarrow || variant[l] > kTileWide16)
+    if (variant[l] < kTileNarrow || variant[l] >= kTileVariants)
       return set_error("tile variant out of range"), OF_EINVAL;
     if (variant[l] > kTileWideLean && (p->g.flags & OF_FLAG_GAUSSIAN_WINDOW))
       return set_error("narrow-strip variants apply to the box window only"), OF_EINVAL;
+    if (!tile_variant_valid(variant[l], p->g.R, p->g.flags & OF_FLAG_GAUSSIAN_WINDOW))
+      return set_error("two-bands-per-pass variants take r <= 8"), OF_EINVAL;
   }
   DeviceGuard guard(p->device);
   hipDeviceSynchronize();
@@ -523,7 +529,7 @@ of_status of_plan_autotune(of_plan* p, const void* I1, const void* I2, float* u,
   Geometry& g = p->g;
   const bool was_on = p->timer.on;
   p->timer.on = true;
-  static const int kBands[] = {1, 2, 4, 8};
+  static const int kBands[] = {1, 2, 3, 4, 8};
   hipError_t e = hipSuccess;
   for (int l = 0; l < g.L && e == hipSuccess && g.K > 0; ++l) {
     double best = 1e30;
@@ -531,8 +537,8 @@ of_status of_plan_autotune(of_plan* p, const void* I1, const void* I2, float* u,
     int bw = g.variant[l];
     for (int nb : kBands) {
       if (nb > 1 && (2 * g.R + 1) * nb > 2 * g.H[l]) continue;
-      const int last = (g.flags & OF_FLAG_GAUSSIAN_WINDOW) ? kTileWideLean : kTileWide16;
-      for (int w = kTileNarrow; w <= last; ++w) {
+      for (int w = kTileNarrow; w < kTileVariants; ++w) {
+        if (!tile_variant_valid(w, g.R, g.flags & OF_FLAG_GAUSSIAN_WINDOW)) continue;
         g.nb[l] = nb;
         g.variant[l] = w;
         if (g.mask[l]) e = upload_tile_flags(p, l);

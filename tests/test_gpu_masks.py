@@ -38,7 +38,8 @@ def test_masked_plan_matches_oracle_and_skips_tiles(gpu_lib):
         d = flow_error(gu, gv, ou, ov)
         assert d.max() <= 1e-3, report(d, 1e-3)
     # other tile widths skip other tiles and give the same bits
-    for cfg in ({"bands": [1, 1, 1], "variant": [4, 4, 3]}, {"bands": [4, 2, 1], "variant": [0, 3, 2]}):
+    for cfg in ({"bands": [1, 1, 1], "variant": [4, 4, 3]}, {"bands": [4, 2, 1], "variant": [0, 3, 2]},
+                {"bands": [1, 2, 1], "variant": [5, 6, 5]}):
         plan.set_config(cfg)
         u, v = plan.compute(to_dev(I1), to_dev(I2))
         torch.cuda.synchronize()
@@ -62,7 +63,7 @@ def test_all_ones_mask_keeps_bits_and_configs(gpu_lib):
     ref = (u0.cpu().numpy(), v0.cpu().numpy())
     plan.set_mask(to_dev(np.ones((200, 231), np.uint8)))
     for cfg in ({"bands": [1, 1, 1], "variant": [0, 0, 0]}, {"bands": [2, 1, 1], "variant": [1, 2, 1]},
-                {"bands": [1, 2, 1], "variant": [4, 3, 4]}):
+                {"bands": [1, 2, 1], "variant": [4, 3, 4]}, {"bands": [3, 1, 2], "variant": [6, 5, 5]}):
         announce(f"all-ones mask, config {cfg}")
         plan.set_config(cfg)
         u, v = plan.compute(to_dev(I1), to_dev(I2))

@@ -245,13 +245,16 @@ def test_plan_configs_and_autotune_keep_bits(gpu_lib):
     ref = (u0.cpu().numpy(), v0.cpu().numpy())
     for cfg in ({"bands": [1, 1, 1], "variant": [0, 0, 0]}, {"bands": [8, 4, 2], "variant": [1, 1, 1]},
                 {"bands": [2, 8, 1], "variant": [0, 1, 2]}, {"bands": [1, 2, 4], "variant": [2, 2, 2]},
-                {"bands": [1, 1, 1], "variant": [3, 4, 4]}, {"bands": [2, 1, 4], "variant": [4, 3, 3]}):
+                {"bands": [1, 1, 1], "variant": [3, 4, 4]}, {"bands": [2, 1, 4], "variant": [4, 3, 3]},
+                {"bands": [1, 1, 1], "variant": [5, 6, 5]}, {"bands": [2, 3, 1], "variant": [6, 5, 6]},
+                {"bands": [4, 1, 8], "variant": [5, 5, 6]}):
         announce(f"plan config {cfg}")
         plan.set_config(cfg)
         u, v = plan.compute(d1, d2)
         torch.cuda.synchronize()
         assert np.array_equal(u.cpu().numpy(), ref[0]) and np.array_equal(v.cpu().numpy(), ref[1]), cfg
-    for bad in ({"bands": [1, 1, 1], "variant": [0, 5, 0]}, {"bands": [0, 1, 1], "variant": [0, 0, 0]}):
+    for bad in ({"bands": [1, 1, 1], "variant": [0, 7, 0]}, {"bands": [0, 1, 1], "variant": [0, 0, 0]},
+                {"bands": [1, 1, 1], "variant": [-1, 0, 0]}):
         with pytest.raises(ofmi.OfError):
             plan.set_config(bad)
     announce("plan autotune")
@@ -260,3 +263,36 @@ def test_plan_configs_and_autotune_keep_bits(gpu_lib):
     torch.cuda.synchronize()
     assert np.array_equal(u.cpu().numpy(), ref[0]) and np.array_equal(v.cpu().numpy(), ref[1]), cfg
     plan.close()
+
+
+def test_two_band_variants_at_radius_8(gpu_lib):
+    """Two bands per pass at the largest radius they take, on a ragged frame (partial strips
+    and tiles, odd and even band counts): the same bits as one band per pass and the oracle's
+    flow to 1e-3 px; above r = 8 the plan rejects them."""
+    import torch
+    ofmi = gpu_lib
+    I1, I2, _, _ = synth.make_pair("c1", 12)
+    I1, I2 = I1[:219, :173].copy(), I2[:219, :173].copy()
+    d1, d2 = to_dev(I1), to_dev(I2)
+    plan = ofmi.Plan(219, 173, 2, 8, 3, device=dev())
+    plan.set_config({"bands": [1, 1], "variant": [1, 3]})
+    u0, v0 = plan.compute(d1, d2)
+    torch.cuda.synchronize()
+    ref = (u0.cpu().numpy(), v0.cpu().numpy())
+    ou, ov = oracle.flow(I1, I2, 2, 8, 3)
+    d = flow_error(ref[0], ref[1], ou, ov)
+    assert d.max() <= 1e-3, report(d, 1e-3)
+    for cfg in ({"bands": [1, 1], "variant": [5, 6]}, {"bands": [2, 1], "variant": [6, 5]},
+                {"bands": [3, 4], "variant": [5, 5]}, {"bands": [8, 2], "variant": [6, 6]}):
+        announce(f"two bands per pass, r=8, config {cfg}")
+        plan.set_config(cfg)
+        u, v = plan.compute(d1, d2)
+        torch.cuda.synchronize()
+        assert np.array_equal(u.cpu().numpy(), ref[0]) and np.array_equal(v.cpu().numpy(), ref[1]), cfg
+    plan.close()
+    big = ofmi.Plan(64, 64, 1, 9, 1, device=dev())
+    for w in (5, 6):
+        with pytest.raises(ofmi.OfError):
+            big.set_config({"bands": [1], "variant": [w]})
+    big.set_config({"bands": [1], "variant": [4]})
+    big.close()

@@ -51,8 +51,9 @@ def test_gaussian_window_flow_matches_oracle(gpu_lib, shape, L, r, K):
     bu, _ = oracle.flow(I1, I2, L, r, K)
     assert np.abs(bu - ou).max() > 1e-2
     # the narrow-strip variants are box-window only
-    with pytest.raises(ofmi.OfError):
-        plan.set_config({"bands": [1] * L, "variant": [3] * L})
+    for w in (3, 4, 5, 6):
+        with pytest.raises(ofmi.OfError):
+            plan.set_config({"bands": [1] * L, "variant": [w] * L})
     # tiling and variant independence, bitwise
     for cfg in ({"bands": [1] * L, "variant": [0] * L}, {"bands": [2] * L, "variant": [2] * L}):
         plan.set_config(cfg)
