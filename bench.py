@@ -28,7 +28,7 @@ WORKLOAD = "c2"
 
 # Launch configuration the plan autotuner settles on for this workload (FP32 and FP16): used by
 # the --probe run, which profilers wrap, so that it needs no autotuning launches.
-PROBE_CONFIG = {"bands": [4, 1, 1, 1], "variant": [3, 3, 3, 3]}
+PROBE_CONFIG = {"bands": [4, 1, 1, 1], "variant": [3, 1, 6, 6]}
 # One of the configurations the batch autotuner picks for 16 pairs of this workload.
 PROBE_BATCH_CONFIG = {"bands": [8, 8, 4, 1], "grid": [512, 0, 512, 512], "variant": [0, 0, 1, 1]}
 # Sources of the fused iteration kernel: the HBM traffic recorded in the counter summary is

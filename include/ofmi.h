@@ -179,11 +179,12 @@ OF_API const char* of_last_error(void);
  * Per-kernel timing for measurement: while enabled, every kernel launch of the plan is
  * bracketed by a pair of hipEvents recorded on the launch stream.  of_plan_read_timing
  * waits for the recorded events, returns the totals since the last read and resets them.
- *   kernel: OF_KERNEL_ITERATE (the fused iteration) or OF_KERNEL_REDUCE (pyramid step).
+ *   kernel: OF_KERNEL_ITERATE (the fused iteration) or OF_KERNEL_REDUCE (pyramid: one
+ *   reduction, or one launch building 2 or 3 levels, for levels of up to 2^20 pixels).
  *   total_ms: summed event-to-event time; launches: number of launches; units: pixel-
  *   iterations (ITERATE) or output pixels (REDUCE); bytes: algorithmic HBM bytes of those
  *   launches (ITERATE: per pixel-iteration 2 frame elements + 16 bytes of u,v read and
- *   written; REDUCE: input plane + output plane per frame).  Any out pointer may be NULL.
+ *   written; REDUCE: per frame the input plane once and every output plane once).  Any out pointer may be NULL.
  * Errors: OF_EINVAL on a NULL plan or unknown kernel; OF_EHIP if event creation fails. */
 #define OF_KERNEL_ITERATE 0
 #define OF_KERNEL_REDUCE 1

@@ -33,6 +33,17 @@ hipError_t launch_reduce_batch(Elem tin, Elem tout, const ReduceJob* jobs, const
 hipError_t launch_mask_reduce(const uint8_t* in, int H, int W, uint8_t* out, int Ho, int Wo,
                               hipStream_t s);
 
+// D = 2 or 3 successive pyramid reductions of up to two frames in one launch (levels f+1 ..
+// f+D from level f; in[1] null for one frame): sizes H[0..D], W[0..D] of levels f .. f+D,
+// out[frame][d-1] = level f+d.  Same bits as D launch_reduce calls.
+struct ReduceChain {
+  const void* in[2];
+  void* out[2][3];
+  int H[4], W[4];
+  int D;
+};
+hipError_t launch_reduce_chain(Elem tin, Elem tout, const ReduceChain& c, hipStream_t s);
+
 // One pyramid reduction of up to two frames of the same geometry (out = reduce(in)).
 hipError_t launch_reduce(Elem tin, Elem tout, const void* in1, const void* in2, int H, int W,
                          void* out1, void* out2, int Ho, int Wo, hipStream_t s);

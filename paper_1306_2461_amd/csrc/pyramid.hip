@@ -146,6 +146,122 @@ hipError_t go(const void* in1, const void* in2, int H, int W, void* out1, void* 
   return hipGetLastError();
 }
 
+// Fused reduction chain (one launch for D levels of one pair's pyramid, which is latency
+// bound level by level).  A workgroup owns a T x T tile of the deepest level and rebuilds
+// the tile's clamped footprint at every level of the chain in LDS: S_D = T rows and columns
+// from o_D = (by T, bx T), and S_{d-1} = 2 S_d + 3 from o_{d-1} = 2 o_d - 2 at the level
+// above.  Footprint entry k of a level holds that level's value at the clamped position
+// clamp(o + k), so every value is computed exactly as reduce_tile computes it (row filter at
+// the clamped columns, then column filter at the clamped rows, the same FMA chains), rounded
+// to the storage type before the next level reads it: the chain gives the bits of D single
+// reductions.  Each level's own part of the tile (T 2^(D-d) square, at footprint offset
+// 2^(D-d+1) - 2) is written out.
+constexpr int chain_span(int D, int T, int d) { return d >= D ? T : 2 * chain_span(D, T, d + 1) + 3; }
+
+template <typename T>
+__device__ __forceinline__ float stored(float x);
+template <>
+__device__ __forceinline__ float stored<float>(float x) { return x; }
+template <>
+__device__ __forceinline__ float stored<__half>(float x) { return __half2float(__float2half_rn(x)); }
+
+// Level d of the chain from level d-1's footprint `src` (row pass into `fr`, column pass into
+// `dst`); Hd x Wd is level d's size, (tyD, txD) the tile's origin at the deepest level.
+template <typename Tout, int D, int T, int d>
+__device__ __forceinline__ void chain_level(const float* src, float* dst, float* fr, int Hd, int Wd,
+                                            Tout* out, int tyD, int txD) {
+  constexpr int Sp = chain_span(D, T, d - 1), Sd = chain_span(D, T, d);
+  constexpr int k = D - d;
+  // footprint origin at level d: o_d = 2^(D-d) o_D - 2^(D-d+1) + 2
+  const int oyd = (tyD << k) - (2 << k) + 2, oxd = (txD << k) - (2 << k) + 2;
+  // Row pass: every footprint row of level d-1 at the columns of level d's footprint.
+  for (int e = threadIdx.x; e < Sp * Sd; e += 256) {
+    const int r = e / Sd, q = e - r * Sd;
+    const int cx = min(max(oxd + q, 0), Wd - 1) - oxd;
+    const float* w = src + r * Sp + 2 * cx;
+    float acc = kB0 * w[0];
+    acc = fmaf(kB1, w[1], acc);
+    acc = fmaf(kB2, w[2], acc);
+    acc = fmaf(kB1, w[3], acc);
+    acc = fmaf(kB0, w[4], acc);
+    fr[r * Sd + q] = acc;
+  }
+  __syncthreads();
+  // Column pass at the rows of level d's footprint; the tile's own part goes out.
+  constexpr int own0 = (2 << k) - 2, own = T << k;
+  for (int e = threadIdx.x; e < Sd * Sd; e += 256) {
+    const int p = e / Sd, q = e - p * Sd;
+    const int cy = min(max(oyd + p, 0), Hd - 1) - oyd;
+    const float* h = fr + 2 * cy * Sd + q;
+    float acc = kB0 * h[0];
+    acc = fmaf(kB1, h[Sd], acc);
+    acc = fmaf(kB2, h[2 * Sd], acc);
+    acc = fmaf(kB1, h[3 * Sd], acc);
+    acc = fmaf(kB0, h[4 * Sd], acc);
+    dst[p * Sd + q] = stored<Tout>(acc);
+    const int i = oyd + p, j = oxd + q;
+    if (p >= own0 && p < own0 + own && q >= own0 && q < own0 + own && i < Hd && j < Wd)
+      st(out, (unsigned)i * (unsigned)Wd + (unsigned)j, acc);
+  }
+  __syncthreads();
+}
+
+template <typename Tin, typename Tout, int D, int T>
+__global__ __launch_bounds__(256) void reduce_chain_kernel(ReduceChain a, int tiles_x) {
+  constexpr int S0 = chain_span(D, T, 0), S1 = chain_span(D, T, 1);
+  __shared__ float fa[S0 * S0];   // footprints of levels 0, 2
+  __shared__ float fr[S0 * S1];   // row-pass results
+  __shared__ float fb[S1 * S1];   // footprints of levels 1, 3
+  const bool f2 = blockIdx.z != 0;
+  const int by = blockIdx.x / tiles_x, bx = blockIdx.x - by * tiles_x;
+  const int tyD = by * T, txD = bx * T;
+  {
+    const Tin* in = (const Tin*)(f2 ? a.in[1] : a.in[0]);
+    const int H = a.H[0], W = a.W[0];
+    const int oy0 = (tyD << D) - (2 << D) + 2, ox0 = (txD << D) - (2 << D) + 2;
+    // All loads in flight together: items past the end repeat the last entry (same value to
+    // the same slot), so neither loads nor stores need a guard.
+    constexpr int NL = (S0 * S0 + 255) / 256;
+    float v[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int e = min((int)threadIdx.x + 256 * k, S0 * S0 - 1);
+      const int ry = e / S0, rx = e - ry * S0;
+      const int y = min(max(oy0 + ry, 0), H - 1), x = min(max(ox0 + rx, 0), W - 1);
+      v[k] = ld(in, (unsigned)y * (unsigned)W + (unsigned)x);
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) fa[min((int)threadIdx.x + 256 * k, S0 * S0 - 1)] = v[k];
+  }
+  __syncthreads();
+  chain_level<Tout, D, T, 1>(fa, fb, fr, a.H[1], a.W[1], (Tout*)(f2 ? a.out[1][0] : a.out[0][0]),
+                             tyD, txD);
+  chain_level<Tout, D, T, 2>(fb, fa, fr, a.H[2], a.W[2], (Tout*)(f2 ? a.out[1][1] : a.out[0][1]),
+                             tyD, txD);
+  if constexpr (D == 3)
+    chain_level<Tout, D, T, 3>(fa, fb, fr, a.H[3], a.W[3], (Tout*)(f2 ? a.out[1][2] : a.out[0][2]),
+                               tyD, txD);
+}
+
+template <typename Tin, typename Tout>
+hipError_t go_chain(const ReduceChain& c, hipStream_t s) {
+  const int nf = c.in[1] ? 2 : 1;
+  if (c.D == 2) {
+    constexpr int T = 16;
+    const int tx = (c.W[2] + T - 1) / T, ty = (c.H[2] + T - 1) / T;
+    hipLaunchKernelGGL((reduce_chain_kernel<Tin, Tout, 2, T>), dim3(tx * ty, 1, nf), dim3(256), 0,
+                       s, c, tx);
+  } else if (c.D == 3) {
+    constexpr int T = 8;
+    const int tx = (c.W[3] + T - 1) / T, ty = (c.H[3] + T - 1) / T;
+    hipLaunchKernelGGL((reduce_chain_kernel<Tin, Tout, 3, T>), dim3(tx * ty, 1, nf), dim3(256), 0,
+                       s, c, tx);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // Mask pyramid: a coarse pixel is unmasked when any of its (up to) four finer pixels is.
 __global__ __launch_bounds__(256) void mask_reduce_kernel(const uint8_t* __restrict__ in, int H,
                                                            int W, uint8_t* __restrict__ out,
@@ -181,6 +297,18 @@ hipError_t launch_reduce_batch(Elem tin, Elem tout, const ReduceJob* jobs, const
     if (tin == Elem::U8) return go_batch<uint8_t, __half>(jobs, items, nitems, grid, s);
     if (tin == Elem::F32) return go_batch<float, __half>(jobs, items, nitems, grid, s);
     if (tin == Elem::F16) return go_batch<__half, __half>(jobs, items, nitems, grid, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce_chain(Elem tin, Elem tout, const ReduceChain& c, hipStream_t s) {
+  if (tout == Elem::F32) {
+    if (tin == Elem::U8) return go_chain<uint8_t, float>(c, s);
+    if (tin == Elem::F32) return go_chain<float, float>(c, s);
+  } else if (tout == Elem::F16) {
+    if (tin == Elem::U8) return go_chain<uint8_t, __half>(c, s);
+    if (tin == Elem::F32) return go_chain<float, __half>(c, s);
+    if (tin == Elem::F16) return go_chain<__half, __half>(c, s);
   }
   return hipErrorInvalidValue;
 }

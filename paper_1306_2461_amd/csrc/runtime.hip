@@ -214,18 +214,44 @@ hipError_t enqueue_pair(const Geometry& g, char* ws, const void* I1, const void*
   for (int l = 1; l < g.L; ++l) {
     P1[l] = ws + g.off_p1[l];
     P2[l] = ws + g.off_p2[l];
+  }
+  // Pyramid: runs of 2 or 3 levels whose first output plane has at most 2^20 pixels take one
+  // fused chain launch each, other levels one reduction each (identical bits either way).
+  for (int l = 1; l < g.L;) {
+    const int rest = g.L - l;
+    const int D = (rest >= 2 && (long long)g.H[l] * g.W[l] <= (1ll << 20)) ? (rest >= 3 ? 3 : 2) : 1;
     hipEvent_t ev;
     hipError_t e = t ? t->begin(s, &ev) : hipSuccess;
-    if (e == hipSuccess)
-      e = launch_reduce(g.elem(l - 1), g.ep, P1[l - 1], P2[l - 1], g.H[l - 1], g.W[l - 1],
-                        (void*)P1[l], (void*)P2[l], g.H[l], g.W[l], s);
+    if (e == hipSuccess) {
+      if (D == 1) {
+        e = launch_reduce(g.elem(l - 1), g.ep, P1[l - 1], P2[l - 1], g.H[l - 1], g.W[l - 1],
+                          (void*)P1[l], (void*)P2[l], g.H[l], g.W[l], s);
+      } else {
+        ReduceChain c{};
+        c.in[0] = P1[l - 1];
+        c.in[1] = P2[l - 1];
+        for (int d = 0; d <= D; ++d) {
+          c.H[d] = g.H[l - 1 + d];
+          c.W[d] = g.W[l - 1 + d];
+        }
+        for (int d = 1; d <= D; ++d) {
+          c.out[0][d - 1] = (void*)P1[l - 1 + d];
+          c.out[1][d - 1] = (void*)P2[l - 1 + d];
+        }
+        c.D = D;
+        e = launch_reduce_chain(g.elem(l - 1), g.ep, c, s);
+      }
+    }
     if (e == hipSuccess && t) {
-      const double no = (double)g.H[l] * g.W[l];
+      // algorithmic: each input plane read once, each output plane written once
+      double no = 0;
+      for (int d = 0; d < D; ++d) no += (double)g.H[l + d] * g.W[l + d];
       const double ni = (double)g.H[l - 1] * g.W[l - 1];
       e = t->end(s, ev, OF_KERNEL_REDUCE, 2 * no,
                  2 * (ni * elem_bytes(g.elem(l - 1)) + no * elem_bytes(g.ep)));
     }
     if (e != hipSuccess) return e;
+    l += D;
   }
   float* fu[2] = {(float*)(ws + g.off_flow[0]), (float*)(ws + g.off_flow[1])};
   float* fv[2] = {(float*)(ws + g.off_flow[2]), (float*)(ws + g.off_flow[3])};

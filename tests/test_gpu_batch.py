@@ -107,3 +107,29 @@ def test_batch_fp16_and_zero_iterations(gpu_lib):
     torch.cuda.synchronize()
     assert all(np.all(t.cpu().numpy() == 0) for t in us + vs)
     b0.close()
+
+
+def test_deep_pyramids_plain_equals_batch_bitwise(gpu_lib):
+    """The plain path builds runs of 2 or 3 pyramid levels in one fused launch, the batch one
+    level per launch: every level count from 2 to 6 (chains of 2, 3, 3 + 1, 3 + 2 levels), FP32
+    and FP16 storage, ragged sizes, gives the same bits."""
+    import torch
+    ofmi = gpu_lib
+    sizes = [(257, 190), (96, 130), (75, 203)]
+    pairs = _pairs(sizes)
+    d1 = [to_dev(p[0]) for p in pairs]
+    d2 = [to_dev(p[1]) for p in pairs]
+    for fp16 in (False, True):
+        for L in (2, 3, 4, 5, 6):
+            announce(f"deep pyramid plain vs batch L={L} fp16={fp16}")
+            b = ofmi.Batch(sizes, L, 2, 1, fp16=fp16, device=dev())
+            us, vs = b.compute(d1, d2)
+            torch.cuda.synchronize()
+            for i, (H, W) in enumerate(sizes):
+                plan = ofmi.Plan(H, W, L, 2, 1, fp16=fp16, device=dev())
+                u, v = plan.compute(d1[i], d2[i])
+                torch.cuda.synchronize()
+                assert np.array_equal(us[i].cpu().numpy(), u.cpu().numpy()), (L, fp16, i)
+                assert np.array_equal(vs[i].cpu().numpy(), v.cpu().numpy()), (L, fp16, i)
+                plan.close()
+            b.close()
