@@ -95,6 +95,9 @@ typedef enum {
  * two, for levels of about one tile per CU. */
 #define OF_TILE_WIDE32X2 5
 #define OF_TILE_WIDE16X2 6
+/* WIDE32X2 with the item indices recomputed every pass (as WIDE_LEAN): 60-80 instead of
+ * 96-134 VGPRs, so two or three workgroups share a CU, for levels with more tiles than CUs. */
+#define OF_TILE_LEAN32X2 7
 
 #define OF_MAX_LEVELS 12
 #define OF_MAX_RADIUS 12
@@ -156,16 +159,16 @@ OF_API int of_levels_for_displacement(float dmax, int H, int W);
 
 /* Per-level launch configuration of a plan: bands[l] = tile height of the iteration kernel
  * in bands of 2r+1 rows (1..64), variant[l] = OF_TILE_* (default: levels of under 128 tiles
- * of 64 columns take WIDE16X2 (WIDE32 above r = 8), of under 384 tiles WIDE32, both WIDE with
- * OF_FLAG_GAUSSIAN_WINDOW, larger ones WIDE_LEAN;
- * WIDE32, WIDE16, WIDE32X2 and WIDE16X2 are not available with OF_FLAG_GAUSSIAN_WINDOW,
- * WIDE32X2 and WIDE16X2 not above r = 8).  Arrays of `levels` entries.  set_config drops the plan's captured graphs; OF_EINVAL for values out
+ * of 64 columns take WIDE16X2, of under 384 tiles LEAN32X2 (both WIDE32 above r = 8, WIDE with
+ * OF_FLAG_GAUSSIAN_WINDOW), larger ones WIDE_LEAN;
+ * WIDE32, WIDE16 and the X2 variants are not available with OF_FLAG_GAUSSIAN_WINDOW, the X2
+ * variants not above r = 8).  Arrays of `levels` entries.  set_config drops the plan's captured graphs; OF_EINVAL for values out
  * of range.  Results do not depend on the configuration. */
 OF_API of_status of_plan_get_config(const of_plan* plan, int* bands, int* variant);
 OF_API of_status of_plan_set_config(of_plan* plan, const int* bands, const int* variant);
 
 /* Autotuner: for each level in turn, times that level's iteration launches for bands in
- * {1,2,3,4,8} x the tile variants the plan allows (seven with the box window and r <= 8, five
+ * {1,2,3,4,8} x the tile variants the plan allows (eight with the box window and r <= 8, five
  * with the box window above, three with the Gaussian window)
  * on the given buffers (reps timed runs after one warm-up) and keeps the fastest.
  * Synchronises `stream`; writes u, v. */

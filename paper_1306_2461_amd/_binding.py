@@ -29,6 +29,7 @@ OF_TILE_WIDE32 = 3
 OF_TILE_WIDE16 = 4
 OF_TILE_WIDE32X2 = 5
 OF_TILE_WIDE16X2 = 6
+OF_TILE_LEAN32X2 = 7
 
 # exported symbol -> (restype, argtypes)
 _c_int, _c_uint, _c_size, _vp = ctypes.c_int, ctypes.c_uint, ctypes.c_size_t, ctypes.c_void_p

@@ -60,9 +60,11 @@ hipError_t launch_reduce(Elem tin, Elem tout, const void* in1, const void* in2, 
 //   wide 32x2 / the same strips with two bands per pass and 20 threads per output column
 //   wide 16x2   (plain launches of the box window, r <= kMaxPairRadius): a tile of one output
 //              band runs its priming band and its output band together, one dependent path.
+//   lean 32x2   wide 32x2 with the item indices recomputed every pass (as wide lean): fewer
+//              live registers, so several workgroups share a CU (levels with more tiles).
 enum TileVariant : int { kTileNarrow = 0, kTileWide = 1, kTileWideLean = 2, kTileWide32 = 3,
-                         kTileWide16 = 4, kTileWide32x2 = 5, kTileWide16x2 = 6 };
-constexpr int kTileVariants = 7;
+                         kTileWide16 = 4, kTileWide32x2 = 5, kTileWide16x2 = 6, kTileLean32x2 = 7 };
+constexpr int kTileVariants = 8;
 // Largest window radius of the two-bands-per-pass variants (their LDS stays within 64 KB).
 constexpr int kMaxPairRadius = 8;
 // Added to a plain launch's variant: Gaussian-weighted window sums (taps in IterArgs::taps).
@@ -82,7 +84,7 @@ struct BatchLaunch {
 int strip_width_for(int R);
 // Strip width of a plain launch's tile variant.
 inline int tile_width(int variant, int R) {
-  if (variant == kTileWide32 || variant == kTileWide32x2) return 32;
+  if (variant == kTileWide32 || variant == kTileWide32x2 || variant == kTileLean32x2) return 32;
   if (variant == kTileWide16 || variant == kTileWide16x2) return 16;
   return strip_width_for(R);
 }
@@ -92,7 +94,9 @@ inline int tile_width(int variant, int R) {
 inline bool tile_variant_valid(int variant, int R, bool gaussian) {
   if (variant < kTileNarrow || variant >= kTileVariants) return false;
   if (gaussian && variant > kTileWideLean) return false;
-  if ((variant == kTileWide32x2 || variant == kTileWide16x2) && R > kMaxPairRadius) return false;
+  if ((variant == kTileWide32x2 || variant == kTileWide16x2 || variant == kTileLean32x2) &&
+      R > kMaxPairRadius)
+    return false;
   return true;
 }
 

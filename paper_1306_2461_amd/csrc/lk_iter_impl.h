@@ -502,6 +502,7 @@ hipError_t go_plain_g(const IterArgs& a, int nb, int variant, hipStream_t s) {
       switch (variant) {
         case kTileWide32x2: return go_plain_v<T, R, MODE, true, false, false, 32, 2>(a, nb, s);
         case kTileWide16x2: return go_plain_v<T, R, MODE, true, false, false, 16, 2>(a, nb, s);
+        case kTileLean32x2: return go_plain_v<T, R, MODE, true, true, false, 32, 2>(a, nb, s);
       }
     }
   }

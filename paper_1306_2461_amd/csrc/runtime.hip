@@ -65,15 +65,16 @@ Geometry make_geometry(int H, int W, int levels, int radius, int iters, unsigned
     {
       // Plans with the box window (the fastest measured at 1024^2 and below): levels of at
       // most half a tile per CU on 64-column strips take 16-column strips with two bands per
-      // pass (r <= 8), about one tile per CU the wide variant on 32-column strips; otherwise,
-      // and with the Gaussian-weighted window, the batch default.
+      // pass, about one tile per CU 32-column strips with two bands per pass and indices
+      // recomputed per pass (both r <= 8; else the wide variant on 32-column strips);
+      // otherwise, and with the Gaussian-weighted window, the batch default.
       const long long tx = (g.W[l] + strip_width_for(radius) - 1) / strip_width_for(radius);
       const long long th = (long long)(2 * radius + 1) * g.nb[l];
       const long long nt = tx * ((g.H[l] + th - 1) / th);
       const int v = default_tile_variant(nt);
       g.variant[l] = v;
       if (v == kTileWide && !(flags & OF_FLAG_GAUSSIAN_WINDOW))
-        g.variant[l] = nt < 128 && radius <= kMaxPairRadius ? kTileWide16x2 : kTileWide32;
+        g.variant[l] = radius > kMaxPairRadius ? kTileWide32 : (nt < 128 ? kTileWide16x2 : kTileLean32x2);
     }
   }
   g.ein = (flags & OF_FLAG_INPUT_F32) ? Elem::F32 : Elem::U8;

@@ -133,3 +133,18 @@ def test_deep_pyramids_plain_equals_batch_bitwise(gpu_lib):
                 assert np.array_equal(vs[i].cpu().numpy(), v.cpu().numpy()), (L, fp16, i)
                 plan.close()
             b.close()
+    # a level-1 plane over 2^20 pixels: one staged reduction, then a chain of two from level 1
+    big = [(2100, 2090)]
+    pairs = _pairs(big)
+    d1, d2 = to_dev(pairs[0][0]), to_dev(pairs[0][1])
+    for fp16 in (False, True):
+        announce(f"pyramid 2100x2090 L=4 plain vs batch fp16={fp16}")
+        b = ofmi.Batch(big, 4, 2, 1, fp16=fp16, device=dev())
+        us, vs = b.compute([d1], [d2])
+        plan = ofmi.Plan(2100, 2090, 4, 2, 1, fp16=fp16, device=dev())
+        u, v = plan.compute(d1, d2)
+        torch.cuda.synchronize()
+        assert np.array_equal(us[0].cpu().numpy(), u.cpu().numpy()), fp16
+        assert np.array_equal(vs[0].cpu().numpy(), v.cpu().numpy()), fp16
+        plan.close()
+        b.close()

@@ -39,7 +39,7 @@ def test_masked_plan_matches_oracle_and_skips_tiles(gpu_lib):
         assert d.max() <= 1e-3, report(d, 1e-3)
     # other tile widths skip other tiles and give the same bits
     for cfg in ({"bands": [1, 1, 1], "variant": [4, 4, 3]}, {"bands": [4, 2, 1], "variant": [0, 3, 2]},
-                {"bands": [1, 2, 1], "variant": [5, 6, 5]}):
+                {"bands": [1, 2, 1], "variant": [5, 6, 5]}, {"bands": [3, 1, 1], "variant": [7, 7, 6]}):
         plan.set_config(cfg)
         u, v = plan.compute(to_dev(I1), to_dev(I2))
         torch.cuda.synchronize()

@@ -247,13 +247,13 @@ def test_plan_configs_and_autotune_keep_bits(gpu_lib):
                 {"bands": [2, 8, 1], "variant": [0, 1, 2]}, {"bands": [1, 2, 4], "variant": [2, 2, 2]},
                 {"bands": [1, 1, 1], "variant": [3, 4, 4]}, {"bands": [2, 1, 4], "variant": [4, 3, 3]},
                 {"bands": [1, 1, 1], "variant": [5, 6, 5]}, {"bands": [2, 3, 1], "variant": [6, 5, 6]},
-                {"bands": [4, 1, 8], "variant": [5, 5, 6]}):
+                {"bands": [4, 1, 8], "variant": [5, 5, 6]}, {"bands": [1, 3, 2], "variant": [7, 7, 5]}):
         announce(f"plan config {cfg}")
         plan.set_config(cfg)
         u, v = plan.compute(d1, d2)
         torch.cuda.synchronize()
         assert np.array_equal(u.cpu().numpy(), ref[0]) and np.array_equal(v.cpu().numpy(), ref[1]), cfg
-    for bad in ({"bands": [1, 1, 1], "variant": [0, 7, 0]}, {"bands": [0, 1, 1], "variant": [0, 0, 0]},
+    for bad in ({"bands": [1, 1, 1], "variant": [0, 8, 0]}, {"bands": [0, 1, 1], "variant": [0, 0, 0]},
                 {"bands": [1, 1, 1], "variant": [-1, 0, 0]}):
         with pytest.raises(ofmi.OfError):
             plan.set_config(bad)
@@ -283,7 +283,8 @@ def test_two_band_variants_at_radius_8(gpu_lib):
     d = flow_error(ref[0], ref[1], ou, ov)
     assert d.max() <= 1e-3, report(d, 1e-3)
     for cfg in ({"bands": [1, 1], "variant": [5, 6]}, {"bands": [2, 1], "variant": [6, 5]},
-                {"bands": [3, 4], "variant": [5, 5]}, {"bands": [8, 2], "variant": [6, 6]}):
+                {"bands": [3, 4], "variant": [5, 5]}, {"bands": [8, 2], "variant": [6, 6]},
+                {"bands": [1, 3], "variant": [7, 7]}):
         announce(f"two bands per pass, r=8, config {cfg}")
         plan.set_config(cfg)
         u, v = plan.compute(d1, d2)
@@ -291,7 +292,7 @@ def test_two_band_variants_at_radius_8(gpu_lib):
         assert np.array_equal(u.cpu().numpy(), ref[0]) and np.array_equal(v.cpu().numpy(), ref[1]), cfg
     plan.close()
     big = ofmi.Plan(64, 64, 1, 9, 1, device=dev())
-    for w in (5, 6):
+    for w in (5, 6, 7):
         with pytest.raises(ofmi.OfError):
             big.set_config({"bands": [1], "variant": [w]})
     big.set_config({"bands": [1], "variant": [4]})

@@ -51,7 +51,7 @@ def test_gaussian_window_flow_matches_oracle(gpu_lib, shape, L, r, K):
     bu, _ = oracle.flow(I1, I2, L, r, K)
     assert np.abs(bu - ou).max() > 1e-2
     # the narrow-strip variants are box-window only
-    for w in (3, 4, 5, 6):
+    for w in (3, 4, 5, 6, 7):
         with pytest.raises(ofmi.OfError):
             plan.set_config({"bands": [1] * L, "variant": [w] * L})
     # tiling and variant independence, bitwise
