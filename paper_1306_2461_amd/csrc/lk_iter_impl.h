@@ -54,6 +54,10 @@ struct Cfg {
   // (SPLIT) have a region of their own after the warped rows, which saves P3's second barrier.
   static constexpr size_t LDS_FLOATS = 5 * (size_t)NR * PP + (size_t)WROWS * WP;
   static constexpr size_t HS_FLOATS = 5 * (size_t)NR * TW;
+  // Field ring (coarse-field launches, one band per pass): u and v of the warped-frame
+  // positions, kept for FRING rows so that P2 and P5 read them instead of re-interpolating.
+  static constexpr int FRING = 64;
+  static constexpr size_t FR_FLOATS = 2 * (size_t)FRING * WP;
   static constexpr bool SPLIT_FITS = (LDS_FLOATS + HS_FLOATS) * sizeof(float) <= 65536;
 };
 
@@ -63,10 +67,17 @@ template <int R, int TW, bool WIDE, bool LEAN, int BB = 1>
 constexpr bool split_hs() {
   return WIDE && !LEAN && Cfg<R, TW, WIDE, BB>::SPLIT_FITS;
 }
-template <int R, int TW, bool WIDE, bool LEAN, int BB = 1>
+template <int R, int TW, bool WIDE, bool LEAN, int BB = 1, bool FR = false>
 constexpr size_t lds_bytes() {
   using C = Cfg<R, TW, WIDE, BB>;
-  return (C::LDS_FLOATS + (split_hs<R, TW, WIDE, LEAN, BB>() ? C::HS_FLOATS : 0)) * sizeof(float);
+  return (C::LDS_FLOATS + (split_hs<R, TW, WIDE, LEAN, BB>() ? C::HS_FLOATS : 0) +
+          (FR ? C::FR_FLOATS : 0)) * sizeof(float);
+}
+// Plain coarse-field launches of the wide variants with one band per pass keep the field
+// ring (its 2*64 rows cost LDS that only these latency-bound launches can spare).
+template <int MODE, bool WIDE, bool LEAN, int BB>
+constexpr bool field_ring() {
+  return MODE == kFlowCoarse && WIDE && !LEAN && BB == 1;
 }
 
 // One tile: TW output columns from x0 = bx*TW and TH output rows from y0 = by*TH, walked in
@@ -85,14 +96,21 @@ constexpr size_t lds_bytes() {
 // threads, so a tile of two bands (one output band and the band that primes the vertical
 // sums) is one pass of the dependent path instead of two; P4 walks the two bands in order,
 // with the same additions as two single-band passes.  nbands is then even.
+// FR (coarse field, one band per pass): P1 stores the interpolated field of every warped-frame
+// position in a ring of FRING rows; P2 and P5 read theirs from it (the same value at the same
+// clamped position) instead of eight more loads per value.  The next band's P1 may overwrite
+// ring rows while slower threads are still in P5: it writes rows tb+N+1 .. tb+2N while P5
+// reads rows tb-R .. tb+R, at most 5R+2 < FRING apart, so no slot is shared.
 template <typename T, int R, int TW, int MODE, bool WIDE, bool DEFER, bool INTERIOR, bool LEAN,
-          bool GAUSS = false, int BB = 1>
+          bool GAUSS = false, int BB = 1, bool FR = false>
 __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands, int bx, int by,
                                            bool pixel_mask, float4* sm4) {
   using C = Cfg<R, TW, WIDE, BB>;
   constexpr int N = C::N, NR = C::NR, NT = C::NT, PC = C::PC, WC = C::WC, PP = C::PP, WP = C::WP;
   constexpr int RMASK = C::RING - 1;
   static_assert(BB == 1 || BB == 2, "one or two bands per pass");
+  static_assert(!FR || (MODE == kFlowCoarse && BB == 1 && 5 * R + 2 < C::FRING),
+                "field ring: coarse-field launches with one band per pass");
   float* sm = reinterpret_cast<float*>(sm4);
   constexpr bool kSplit = split_hs<R, TW, WIDE, LEAN, BB>();
   float* pr = sm;                               // [5][NR][PP] products (16-byte aligned rows)
@@ -100,6 +118,9 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
   // [5][NR][TW] horizontal, then window sums (16-byte aligned: WROWS*WP is a multiple of 4
   // here or the region aliases the products)
   float* hs = kSplit ? w2 + C::WROWS * WP : pr;
+  float* fru = kSplit ? hs + C::HS_FLOATS : w2 + C::WROWS * WP;   // [FRING][WP] (FR only)
+  float* frv = fru + C::FRING * WP;
+  constexpr int FMASK = C::FRING - 1;
 
   const int tid0 = threadIdx.x;
   const int H = a.H, W = a.W;
@@ -146,11 +167,16 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
       }
       wofs[k] = (BB == 1 ? (w & RMASK) : w - (tb - 1)) * WP + lx;
       read_flow<MODE>(a, wgx[k], wgy[k], wu[k], wv[k]);
+      if constexpr (FR) {
+        fru[(w & FMASK) * WP + lx] = wu[k];
+        frv[(w & FMASK) * WP + lx] = wv[k];
+      }
     }
     // In the coarse-field mode each field value costs eight loads: where registers are tight
     // (DEFER) the field at this thread's P2 and P5 items is read in those phases rather than
     // held in flight here.
-    constexpr bool kDefer = DEFER && MODE == kFlowCoarse;
+    constexpr bool kDefer = DEFER && MODE == kFlowCoarse && !FR;
+    constexpr bool kLoadField = !kDefer && !FR;   // P2/P5 field loads issued in P1
     float i1v[C::K2], pu[C::K2], pv[C::K2];
     float cu[C::K5], cv[C::K5];
     // (The same loads are written twice, before the samples for the default variants and
@@ -165,9 +191,9 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
           gy = min(max(gy, 0), H - 1);
         }
         i1v[k] = ld(I1, (unsigned)gy * (unsigned)W + (unsigned)gx);
-        if constexpr (!kDefer) read_flow<MODE>(a, gx, gy, pu[k], pv[k]);
+        if constexpr (kLoadField) read_flow<MODE>(a, gx, gy, pu[k], pv[k]);
       }
-      if constexpr (!kDefer) {
+      if constexpr (kLoadField) {
 #pragma unroll
         for (int k = 0; k < C::K5; ++k) {
           const int i = min(tid + k * NT, NR * TW - 1);
@@ -193,9 +219,9 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
           gy = min(max(gy, 0), H - 1);
         }
         i1v[k] = ld(I1, (unsigned)gy * (unsigned)W + (unsigned)gx);
-        if constexpr (!kDefer) read_flow<MODE>(a, gx, gy, pu[k], pv[k]);
+        if constexpr (kLoadField) read_flow<MODE>(a, gx, gy, pu[k], pv[k]);
       }
-      if constexpr (!kDefer) {
+      if constexpr (kLoadField) {
 #pragma unroll
         for (int k = 0; k < C::K5; ++k) {
           const int i = min(tid + k * NT, NR * TW - 1);
@@ -235,9 +261,17 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
           const float* row = w2 + s0 * WP + c + 1;
           const float ix = 0.5f * (row[1] - row[-1]);
           const float iy = 0.5f * (w2[sp1 * WP + c + 1] - w2[sm1 * WP + c + 1]);
+          float fu, fv;   // field at the product position
+          if constexpr (FR) {
+            fu = fru[(t & FMASK) * WP + c + 1];
+            fv = frv[(t & FMASK) * WP + c + 1];
+          } else {
+            fu = pu[k];
+            fv = pv[k];
+          }
           float it = row[0] - i1v[k];
-          it = fmaf(-ix, pu[k], it);
-          it = fmaf(-iy, pv[k], it);
+          it = fmaf(-ix, fu, it);
+          it = fmaf(-iy, fv, it);
           p0 = ix * ix;
           p1 = ix * iy;
           p2 = iy * iy;
@@ -362,9 +396,17 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
         const int gx = x0 + c, gy = y0 + j;
         if (j >= 0 && j < TH && (INTERIOR || (gx < W && gy < H))) {
           const float* s = hs + r * TW + c;
+          float fu, fv;   // field at the output pixel: warped row j + R, column c + R + 1
+          if constexpr (FR) {
+            fu = fru[((j + R) & FMASK) * WP + c + R + 1];
+            fv = frv[((j + R) & FMASK) * WP + c + R + 1];
+          } else {
+            fu = cu[k];
+            fv = cv[k];
+          }
           float un, vn;
-          solve_update(s[0], s[NR * TW], s[2 * NR * TW], s[3 * NR * TW], s[4 * NR * TW], cu[k],
-                       cv[k], un, vn);
+          solve_update(s[0], s[NR * TW], s[2 * NR * TW], s[3 * NR * TW], s[4 * NR * TW], fu, fv,
+                       un, vn);
           const unsigned o = (unsigned)gy * (unsigned)W + (unsigned)gx;
           if (pixel_mask && at(a.mask, o) == 0) {   // masked-out pixel: zero flow
             un = 0.f;
@@ -432,12 +474,13 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW * BB) void lk_iter_strip(IterA
     pixel_mask = f == 1;
   }
   constexpr bool kDefer = WIDE || R > 8;
+  constexpr bool kFR = field_ring<MODE, WIDE, LEAN, BB>();
   if (R <= 8 && tile_interior<R, TW>(a, TH, nbands, bx, by))
-    strip_tile<T, R, TW, MODE, WIDE, kDefer, true, LEAN, GAUSS, BB>(a, TH, nbands, bx, by,
-                                                                    pixel_mask, sm4);
+    strip_tile<T, R, TW, MODE, WIDE, kDefer, true, LEAN, GAUSS, BB, kFR>(a, TH, nbands, bx, by,
+                                                                         pixel_mask, sm4);
   else
-    strip_tile<T, R, TW, MODE, WIDE, kDefer, false, LEAN, GAUSS, BB>(a, TH, nbands, bx, by,
-                                                                     pixel_mask, sm4);
+    strip_tile<T, R, TW, MODE, WIDE, kDefer, false, LEAN, GAUSS, BB, kFR>(a, TH, nbands, bx, by,
+                                                                          pixel_mask, sm4);
 }
 
 // Batched form: workgroups stride over a work list of tiles of many pairs at the same
@@ -474,15 +517,23 @@ template <typename T, int R, int MODE, bool WIDE, bool LEAN, bool GAUSS, int TWV
 hipError_t go_plain_v(const IterArgs& a, int nb, hipStream_t s) {
   constexpr int TW = TWV ? TWV : strip_width<R>();
   using C = Cfg<R, TW, WIDE, BB>;
-  static_assert(lds_bytes<R, TW, WIDE, LEAN, BB>() <= 65536, "LDS footprint above 64 KB");
+  constexpr bool kFR = field_ring<MODE, WIDE, LEAN, BB>();
+  constexpr size_t kLds = lds_bytes<R, TW, WIDE, LEAN, BB, kFR>();
+  static_assert(kLds <= 160 * 1024, "LDS footprint above 160 KB");
   const int TH = C::N * nb;
   const int tx = (a.W + TW - 1) / TW, ty = (a.H + TH - 1) / TH;
   const int ntiles = tx * ty;
   const int grid = (ntiles + 7) / 8 * 8;
   const int nbands = (nb + 1 + BB - 1) / BB * BB;
+  if constexpr (kLds > 65536) {
+    // Opt in to more than 64 KB of dynamic LDS (gfx950 has 160 KB per workgroup), once.
+    static const hipError_t opt = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&lk_iter_strip<T, R, TW, MODE, WIDE, LEAN, GAUSS, BB>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds);
+    if (opt != hipSuccess) return opt;
+  }
   hipLaunchKernelGGL((lk_iter_strip<T, R, TW, MODE, WIDE, LEAN, GAUSS, BB>), dim3(grid),
-                     dim3(C::NT), (lds_bytes<R, TW, WIDE, LEAN, BB>()), s, a, TH, nbands, tx,
-                     ntiles);
+                     dim3(C::NT), kLds, s, a, TH, nbands, tx, ntiles);
   return hipGetLastError();
 }
 
