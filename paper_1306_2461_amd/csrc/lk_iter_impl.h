@@ -20,6 +20,10 @@
 //           direct weighted sum over the same rows for the Gaussian-weighted window;
 //       P5  per-pixel 2x2 solve and update for the band's output rows.
 //   The window sums therefore do not depend on how the image is cut into tiles.
+//   * two-bands-per-pass variants run the five phases once over two bands' rows with twice
+//     the threads (20*TW), so a one-band tile (output band plus priming band) is one trip;
+//   * coarse-field launches of the wide one-band variants keep the interpolated field of the
+//     warped-frame positions in an LDS ring for P2 and P5.
 #pragma once
 
 #include "kernels.h"
