@@ -501,10 +501,13 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_batch(const Iter
     const int4 w = tiles[t];
     const IterArgs a = args[w.x];
     const int nb = w.w / C::N + 1;
+    constexpr bool kFR = MODE == kFlowCoarse;
     if (R <= 8 && tile_interior<R, TW>(a, w.w, nb, w.y, w.z))
-      strip_tile<T, R, TW, MODE, WIDE, true, true, LEAN>(a, w.w, nb, w.y, w.z, false, sm4);
+      strip_tile<T, R, TW, MODE, WIDE, true, true, LEAN, false, 1, kFR>(a, w.w, nb, w.y, w.z, false,
+                                                                        sm4);
     else
-      strip_tile<T, R, TW, MODE, WIDE, true, false, LEAN>(a, w.w, nb, w.y, w.z, false, sm4);
+      strip_tile<T, R, TW, MODE, WIDE, true, false, LEAN, false, 1, kFR>(a, w.w, nb, w.y, w.z,
+                                                                         false, sm4);
     __syncthreads();
   }
 }
@@ -575,8 +578,15 @@ template <typename T, int R, int MODE, bool WIDE, bool LEAN>
 hipError_t go_batch_v(const BatchLaunch& b, hipStream_t s) {
   constexpr int TW = strip_width<R>();
   using C = Cfg<R, TW, WIDE>;
-  hipLaunchKernelGGL((lk_iter_batch<T, R, TW, MODE, WIDE, LEAN>), dim3(b.grid), dim3(C::NT),
-                     (lds_bytes<R, TW, WIDE, LEAN>()), s, b.args, b.tiles, b.ntiles);
+  constexpr size_t kLds = lds_bytes<R, TW, WIDE, LEAN, 1, MODE == kFlowCoarse>();
+  if constexpr (kLds > 65536) {
+    static const hipError_t opt = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&lk_iter_batch<T, R, TW, MODE, WIDE, LEAN>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds);
+    if (opt != hipSuccess) return opt;
+  }
+  hipLaunchKernelGGL((lk_iter_batch<T, R, TW, MODE, WIDE, LEAN>), dim3(b.grid), dim3(C::NT), kLds,
+                     s, b.args, b.tiles, b.ntiles);
   return hipGetLastError();
 }
 
