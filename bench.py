@@ -340,6 +340,8 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=8)
     ap.add_argument("--no-extra", action="store_true", help="skip the batched, mixed-batch and serving runs")
     ap.add_argument("--serve-frames", type=int, default=24)
+    ap.add_argument("--c4-only", action="store_true",
+                    help="only the 64-pair mixed batch (for profilers): autotune, 3 timed replays, no JSON line")
     ap.add_argument("--probe", action="store_true",
                     help="short fixed run for profilers (4 plain pairs), no timing, no JSON line")
     args = ap.parse_args()
@@ -350,6 +352,14 @@ def main():
 
     if args.probe:
         probe(args)
+        return
+    if args.c4_only:
+        import torch
+        import paper_1306_2461_amd as ofmi
+        ofmi.load()
+        dev = torch.device("cuda", 0)
+        torch.cuda.set_device(dev)
+        bench_c4(torch, ofmi, dev, max(1, min(16, len(os.sched_getaffinity(0)))), 3)
         return
 
     import numpy as np
