@@ -24,10 +24,22 @@ __device__ __forceinline__ void reduce_tile(const Tin* __restrict__ in, int H, i
                                             float* win, float* hrow) {
   const int i0 = by * TH, j0 = bx * TW;             // first output row / column
   const int r0 = 2 * i0 - 2, c0 = 2 * j0 - 2;       // first input row / column of the window
-  for (int e = threadIdx.x; e < IH * IW; e += 256) {
+  // All of a thread's window loads in flight together (a load-then-store loop would wait for
+  // each in turn); items past the end repeat the last element, same value to the same slot.
+  constexpr int NL = (IH * IW + 255) / 256;
+  float v[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int e = min((int)threadIdx.x + 256 * k, IH * IW - 1);
     const int ry = e / IW, rx = e - ry * IW;
     const int y = min(max(r0 + ry, 0), H - 1), x = min(max(c0 + rx, 0), W - 1);
-    win[ry * IWP + rx] = ld(in, (unsigned)y * (unsigned)W + (unsigned)x);
+    v[k] = ld(in, (unsigned)y * (unsigned)W + (unsigned)x);
+  }
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int e = min((int)threadIdx.x + 256 * k, IH * IW - 1);
+    const int ry = e / IW;
+    win[ry * IWP + (e - ry * IW)] = v[k];
   }
   __syncthreads();
   // Row pass at the even columns 2j of every staged row.
