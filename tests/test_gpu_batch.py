@@ -148,3 +148,30 @@ def test_deep_pyramids_plain_equals_batch_bitwise(gpu_lib):
         assert np.array_equal(vs[0].cpu().numpy(), v.cpu().numpy()), fp16
         plan.close()
         b.close()
+
+
+def test_thin_frames_plain_equals_batch_bitwise(gpu_lib):
+    """Frames 4 pixels high or wide: the fused pyramid launch reaches planes of one row or
+    column and the default two-band tiles cover levels shorter than a band; the plain path
+    equals the batch bitwise.  (On such frames the method itself runs away to flows of tens to
+    hundreds of pixels, the FP64 oracle too, so a 1e-3 px comparison says nothing there.)"""
+    import torch
+    ofmi = gpu_lib
+    sizes = [(4, 37), (37, 4), (9, 9), (5, 131)]
+    pairs = _pairs(sizes)
+    d1 = [to_dev(p[0]) for p in pairs]
+    d2 = [to_dev(p[1]) for p in pairs]
+    for L in (2, 3):
+        announce(f"thin frames plain vs batch L={L}")
+        b = ofmi.Batch(sizes, L, 2, 2, device=dev())
+        us, vs = b.compute(d1, d2)
+        torch.cuda.synchronize()
+        for i, (H, W) in enumerate(sizes):
+            plan = ofmi.Plan(H, W, L, 2, 2, device=dev())
+            u, v = plan.compute(d1[i], d2[i])
+            torch.cuda.synchronize()
+            assert np.array_equal(us[i].cpu().numpy(), u.cpu().numpy()), (L, i)
+            assert np.array_equal(vs[i].cpu().numpy(), v.cpu().numpy()), (L, i)
+            assert np.isfinite(u.cpu().numpy()).all() and np.isfinite(v.cpu().numpy()).all()
+            plan.close()
+        b.close()
