@@ -15,25 +15,58 @@ namespace {
 
 constexpr int NTW = 64, NTH = 16;    // output tile of the normalisation kernel
 
-// Window sums in FP64 (exact for 8-bit input), separable: row sums of the tile's rows into
-// LDS, then column sums per output pixel.
+// Window sums in FP64 (exact for 8-bit input), separable: the tile's input window is staged
+// in LDS first (every load of a thread in flight together; pixels outside the image held as
+// 0), then row sums of the tile's rows into LDS, then column sums per output pixel.  The sums
+// run over the in-image pixels in ascending order, as a direct sum over the frame would.
+constexpr int kNormRowsMax = NTH + 2 * OF_MAX_NORMALIZE_RADIUS;
+constexpr int kNormColsMax = NTW + 2 * OF_MAX_NORMALIZE_RADIUS;
+
+inline size_t normalize_lds_bytes(int r) {
+  const size_t rows = NTH + 2 * (size_t)r, cols = NTW + 2 * (size_t)r;
+  return 2 * sizeof(double) * rows * NTW + sizeof(float) * rows * cols;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void normalize_kernel(const T* __restrict__ in, float* __restrict__ out,
                                                         int H, int W, int r, float eps) {
-  extern __shared__ double rs[];     // [(NTH + 2r) * NTW] sums, then the same of squares
+  extern __shared__ double rs[];     // [rows * NTW] sums, the same of squares, then the window
   const int x0 = blockIdx.x * NTW, y0 = blockIdx.y * NTH;
-  const int rows = NTH + 2 * r;
+  const int rows = NTH + 2 * r, cols = NTW + 2 * r;
   double* s1 = rs;
   double* s2 = rs + rows * NTW;
+  float* win = reinterpret_cast<float*>(s2 + rows * NTW);   // [rows][cols] from (y0-r, x0-r)
+  {
+    constexpr int NL = (kNormRowsMax * kNormColsMax + 255) / 256;
+    const int n = rows * cols;
+    float v[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      if (256 * k >= n) break;   // uniform across the workgroup
+      const int e = min((int)threadIdx.x + 256 * k, n - 1);
+      const int ly = e / cols, lx = e - ly * cols;
+      const int gy = y0 - r + ly, gx = x0 - r + lx;
+      const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
+      const unsigned o = (unsigned)min(max(gy, 0), H - 1) * (unsigned)W + (unsigned)min(max(gx, 0), W - 1);
+      const float val = ld(in, o);
+      v[k] = inside ? val : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      if (256 * k >= n) break;
+      win[min((int)threadIdx.x + 256 * k, n - 1)] = v[k];
+    }
+  }
+  __syncthreads();
   for (int i = threadIdx.x; i < rows * NTW; i += 256) {
     const int ly = i / NTW, lx = i - ly * NTW;
     const int gy = y0 - r + ly, gx = x0 + lx;
     double a = 0.0, b = 0.0;
     if (gy >= 0 && gy < H && gx < W) {
-      const unsigned base = (unsigned)gy * (unsigned)W;
+      const float* row = win + ly * cols;   // row[x - (x0 - r)] = frame value at column x
       const int xa = max(gx - r, 0), xb = min(gx + r, W - 1);
       for (int x = xa; x <= xb; ++x) {
-        const double v = (double)ld(in, base + (unsigned)x);
+        const double v = (double)row[x - (x0 - r)];
         a += v;
         b += v * v;
       }
@@ -57,7 +90,8 @@ __global__ __launch_bounds__(256) void normalize_kernel(const T* __restrict__ in
     const double m = a / n, m2 = b / n;
     const double sd = sqrt(fmax(m2 - m * m, 0.0));
     const unsigned o = (unsigned)gy * (unsigned)W + (unsigned)gx;
-    at(out, o) = (float)(((double)ld(in, o) - m) / (sd + (double)eps));
+    const double c = (double)win[(ly + r) * cols + lx + r];
+    at(out, o) = (float)((c - m) / (sd + (double)eps));
   }
 }
 
@@ -142,16 +176,27 @@ unsigned grid_for(long long n) {
 
 hipError_t launch_normalize(Elem t, const void* in, float* out, int H, int W, int r, float eps,
                             hipStream_t s) {
+  if (r < 0 || r > OF_MAX_NORMALIZE_RADIUS) return hipErrorInvalidValue;
   dim3 grid((W + NTW - 1) / NTW, (H + NTH - 1) / NTH);
-  const size_t lds = 2 * sizeof(double) * (size_t)(NTH + 2 * r) * NTW;
-  if (t == Elem::U8)
+  const size_t lds = normalize_lds_bytes(r);
+  // Up to 67.5 KB at the largest radius: opt in to more than 64 KB of dynamic LDS, once.
+  static const hipError_t opt8 = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&normalize_kernel<uint8_t>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)normalize_lds_bytes(OF_MAX_NORMALIZE_RADIUS));
+  static const hipError_t opt32 = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&normalize_kernel<float>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)normalize_lds_bytes(OF_MAX_NORMALIZE_RADIUS));
+  if (t == Elem::U8) {
+    if (opt8 != hipSuccess) return opt8;
     hipLaunchKernelGGL(normalize_kernel<uint8_t>, grid, dim3(256), lds, s, (const uint8_t*)in, out,
                        H, W, r, eps);
-  else if (t == Elem::F32)
+  } else if (t == Elem::F32) {
+    if (opt32 != hipSuccess) return opt32;
     hipLaunchKernelGGL(normalize_kernel<float>, grid, dim3(256), lds, s, (const float*)in, out, H,
                        W, r, eps);
-  else
+  } else {
     return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
