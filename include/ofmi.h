@@ -158,9 +158,10 @@ OF_API of_status of_plan_set_mask(of_plan* plan, const uint8_t* mask, void* stre
 OF_API int of_levels_for_displacement(float dmax, int H, int W);
 
 /* Per-level launch configuration of a plan: bands[l] = tile height of the iteration kernel
- * in bands of 2r+1 rows (1..64), variant[l] = OF_TILE_* (default: levels of under 128 tiles
- * of 64 columns take WIDE16X2, of under 384 tiles LEAN32X2 (both WIDE32 above r = 8, WIDE with
- * OF_FLAG_GAUSSIAN_WINDOW), larger ones WIDE_LEAN;
+ * in bands of 2r+1 rows (1..64), variant[l] = OF_TILE_* (defaults: 4 bands for levels of 2^19
+ * pixels and more, else 1; levels of under 384 tiles of 64 columns at that height take WIDE32
+ * with 4 bands, WIDE16X2 (under 128 tiles) or LEAN32X2 with 1 band (WIDE32 above r = 8, WIDE
+ * with OF_FLAG_GAUSSIAN_WINDOW), larger ones WIDE_LEAN;
  * WIDE32, WIDE16 and the X2 variants are not available with OF_FLAG_GAUSSIAN_WINDOW, the X2
  * variants not above r = 8).  Arrays of `levels` entries.  set_config drops the plan's captured graphs; OF_EINVAL for values out
  * of range.  Results do not depend on the configuration. */

@@ -35,12 +35,14 @@ bool check_params(int H, int W, int levels, int radius, int iters, unsigned flag
   return true;
 }
 
-// Tile height (in bands of 2R+1 rows) of the iteration kernel for one image of a level:
-// taller tiles cut the vertical halo, shorter ones give more workgroups to small levels.
+// Tile height (in bands of 2R+1 rows) of a plan's iteration kernel for one level: planes of
+// 2^19 pixels and more take four bands (the vertical halo and the priming band amortised over
+// more rows; fastest measured at 1024^2 and 2048^2), smaller ones one band (more workgroups,
+// and the two-bands-per-pass variants run a one-band tile as a single trip).
 int default_bands(int H, int W, int R) {
   const long long px = (long long)H * W;
   (void)R;
-  return px >= (1 << 22) ? 4 : (px >= (1 << 18) ? 2 : 1);
+  return px >= (1 << 19) ? 4 : 1;
 }
 
 // Launches of about one tile per CU are latency bound and take the wide variant (shortest
@@ -63,18 +65,23 @@ Geometry make_geometry(int H, int W, int levels, int radius, int iters, unsigned
   for (int l = 0; l < levels; ++l) {
     g.nb[l] = default_bands(g.H[l], g.W[l], radius);
     {
-      // Plans with the box window (the fastest measured at 1024^2 and below): levels of at
-      // most half a tile per CU on 64-column strips take 16-column strips with two bands per
-      // pass, about one tile per CU 32-column strips with two bands per pass and indices
-      // recomputed per pass (both r <= 8; else the wide variant on 32-column strips);
-      // otherwise, and with the Gaussian-weighted window, the batch default.
+      // Variant by the level's tile count on 64-column strips at that height.  Levels of many
+      // tiles, and the Gaussian-weighted window, take the batch default (wide lean, or wide
+      // below 384 tiles).  With the box window (fastest measured at 1024^2 and 2048^2) levels
+      // of about one tile per CU take 32-column strips: with one-band tiles two bands per pass
+      // (16-column strips below 128 tiles; indices recomputed per pass otherwise), r <= 8;
+      // with taller tiles, or above r = 8, one band per pass.
       const long long tx = (g.W[l] + strip_width_for(radius) - 1) / strip_width_for(radius);
       const long long th = (long long)(2 * radius + 1) * g.nb[l];
       const long long nt = tx * ((g.H[l] + th - 1) / th);
       const int v = default_tile_variant(nt);
       g.variant[l] = v;
-      if (v == kTileWide && !(flags & OF_FLAG_GAUSSIAN_WINDOW))
-        g.variant[l] = radius > kMaxPairRadius ? kTileWide32 : (nt < 128 ? kTileWide16x2 : kTileLean32x2);
+      if (v == kTileWide && !(flags & OF_FLAG_GAUSSIAN_WINDOW)) {
+        if (g.nb[l] > 1 || radius > kMaxPairRadius)
+          g.variant[l] = kTileWide32;
+        else
+          g.variant[l] = nt < 128 ? kTileWide16x2 : kTileLean32x2;
+      }
     }
   }
   g.ein = (flags & OF_FLAG_INPUT_F32) ? Elem::F32 : Elem::U8;
