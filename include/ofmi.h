@@ -65,8 +65,9 @@ typedef enum {
 /* Flags of the *_ex constructors. */
 #define OF_FLAG_FP16_STORAGE (1u << 0) /* pyramid levels >= 1 stored in FP16; all math FP32 */
 #define OF_FLAG_INPUT_F32    (1u << 1) /* frames are float32 instead of uint8 */
-#define OF_FLAG_NO_GRAPH     (1u << 2) /* launch kernels one by one instead of replaying a
-                                          captured hipGraph of the schedule */
+#define OF_FLAG_NO_GRAPH     (1u << 2) /* batches: launch kernels one by one instead of
+                                          replaying a captured hipGraph of the schedule;
+                                          plans: eager launches even with OF_FLAG_GRAPH */
 #define OF_FLAG_NORMALIZE    (1u << 3) /* plans only: equalise both frames locally (see
                                           of_normalize; radius OF_NORMALIZE_RADIUS, eps
                                           OF_NORMALIZE_EPS) before the pyramid */
@@ -74,6 +75,10 @@ typedef enum {
                                           Gaussian taps exp(-d^2 / (2 sigma^2)), sigma = r/2,
                                           over the same (2r+1)^2 support (a variant of the
                                           unweighted interrogation window of Sec. 2.4) */
+#define OF_FLAG_GRAPH        (1u << 5) /* plans only: capture the schedule into a hipGraph
+                                          per pointer tuple and replay it (batches and
+                                          servers always replay graphs); plans launch kernels
+                                          one by one otherwise */
 
 /* Tile variants of the fused iteration kernel (launch configuration; results do not depend
  * on them).  NARROW: 5 threads per output column.  WIDE: 10 threads per output column with
@@ -128,10 +133,12 @@ OF_API of_plan* of_plan_create_ex(int H, int W, int levels, int radius, int iter
 
 /* Dense flow from frame I1 to frame I2 (both H x W, uint8 or float32 per the plan's flags)
  * into u and v (H x W float32, 4-byte aligned, u != v).  Enqueues the pyramid build and the
- * levels x iters iterations on `stream`.  iters = 0 writes zeros.  Unless OF_FLAG_NO_GRAPH is
- * set (or kernel timing is on), the schedule is captured once per distinct (I1, I2, u, v)
- * into a hipGraph held by the plan (at most 64, least recently used evicted) and replayed on
- * `stream`; the first call for a pointer tuple pays the capture.
+ * levels x iters iterations on `stream`.  iters = 0 writes zeros.  Kernels are launched one
+ * by one (measured as fast as graph replay or faster for one stream of pairs from 256^2 to
+ * 1024^2).  With OF_FLAG_GRAPH (and neither OF_FLAG_NO_GRAPH nor kernel timing) the schedule
+ * is captured once per distinct (I1, I2, u, v) into a hipGraph held by the plan (at most 64,
+ * least recently used evicted) and replayed on `stream`, one call per pair for callers whose
+ * host thread is the bottleneck; the first call for a pointer tuple pays the capture.
  * Errors: OF_EINVAL on a NULL plan or pointer or u == v (nothing enqueued); OF_EHIP if a
  * launch fails. */
 OF_API of_status of_compute(of_plan* plan, const void* I1, const void* I2, float* u, float* v,

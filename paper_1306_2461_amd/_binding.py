@@ -18,6 +18,7 @@ OF_FLAG_INPUT_F32 = 1 << 1
 OF_FLAG_NO_GRAPH = 1 << 2
 OF_FLAG_NORMALIZE = 1 << 3
 OF_FLAG_GAUSSIAN_WINDOW = 1 << 4
+OF_FLAG_GRAPH = 1 << 5
 OF_STAGE_REDUCE = 0
 OF_STAGE_ITERATE = 1
 OF_KERNEL_ITERATE = 0

@@ -27,17 +27,19 @@ class Plan:
     ``levels`` counts pyramid levels including full resolution, ``radius`` is the window
     radius and ``iters`` the iterations per level (Sec. 2.4, eq. 1).  ``fp16`` stores the
     pyramid levels >= 1 in FP16 (all arithmetic FP32); ``input_f32`` takes float32 frames;
+    ``graph`` replays a captured hipGraph per buffer tuple instead of launching kernels one by
+    one (the default, as fast or faster for one stream of pairs);
     ``normalize`` equalises both frames first (eq. 2); ``gaussian_window`` weights the window
     sums by Gaussian taps (sigma = r/2) instead of the unweighted box.
     The workspace is a torch allocation owned by the plan.
     """
 
     def __init__(self, H, W, levels, radius, iters, fp16=False, input_f32=False, device=None,
-                 graph=True, normalize=False, gaussian_window=False):
+                 graph=False, normalize=False, gaussian_window=False):
         lib = B.load()
         self.H, self.W, self.levels, self.radius, self.iters = H, W, levels, radius, iters
         self.flags = ((B.OF_FLAG_FP16_STORAGE if fp16 else 0) | (B.OF_FLAG_INPUT_F32 if input_f32 else 0)
-                      | (0 if graph else B.OF_FLAG_NO_GRAPH) | (B.OF_FLAG_NORMALIZE if normalize else 0)
+                      | (B.OF_FLAG_GRAPH if graph else 0) | (B.OF_FLAG_NORMALIZE if normalize else 0)
                       | (B.OF_FLAG_GAUSSIAN_WINDOW if gaussian_window else 0))
         self.frame_dtype = torch.float32 if input_f32 else torch.uint8
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)

@@ -86,6 +86,7 @@ bool check_batch(int n, const int* H, const int* W, int levels, int radius, int 
   if (flags & OF_FLAG_NORMALIZE) return set_error("OF_FLAG_NORMALIZE applies to plans only"), false;
   if (flags & OF_FLAG_GAUSSIAN_WINDOW)
     return set_error("OF_FLAG_GAUSSIAN_WINDOW applies to plans only"), false;
+  if (flags & OF_FLAG_GRAPH) return set_error("OF_FLAG_GRAPH applies to plans only"), false;
   if (!H || !W) return set_error("NULL size arrays"), false;
   for (int i = 0; i < n; ++i)
     if (!check_params(H[i], W[i], levels, radius, iters, flags)) {

@@ -30,7 +30,7 @@ bool check_params(int H, int W, int levels, int radius, int iters, unsigned flag
   if (radius < 0 || radius > OF_MAX_RADIUS) return set_error("radius out of range"), false;
   if (iters < 0 || iters > OF_MAX_ITERS) return set_error("iters out of range"), false;
   if (flags & ~(OF_FLAG_FP16_STORAGE | OF_FLAG_INPUT_F32 | OF_FLAG_NO_GRAPH | OF_FLAG_NORMALIZE |
-                OF_FLAG_GAUSSIAN_WINDOW))
+                OF_FLAG_GAUSSIAN_WINDOW | OF_FLAG_GRAPH))
     return set_error("unknown flags"), false;
   return true;
 }
@@ -393,7 +393,7 @@ of_status of_compute(of_plan* p, const void* I1, const void* I2, float* u, float
     return set_error("float32 frames must be 4-byte aligned"), OF_EINVAL;
   DeviceGuard guard(p->device);
   hipError_t e;
-  if (p->timer.on || (p->g.flags & OF_FLAG_NO_GRAPH)) {
+  if (p->timer.on || (p->g.flags & OF_FLAG_NO_GRAPH) || !(p->g.flags & OF_FLAG_GRAPH)) {
     e = enqueue_pair(p->g, p->ws, I1, I2, u, v, (hipStream_t)stream, &p->timer);
   } else {
     const std::vector<uintptr_t> key = {(uintptr_t)I1, (uintptr_t)I2, (uintptr_t)u, (uintptr_t)v};

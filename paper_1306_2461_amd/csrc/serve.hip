@@ -133,8 +133,8 @@ extern "C" {
 
 size_t of_session_bytes(int H, int W, int levels, int radius, int iters, unsigned flags) {
   if (!check_params(H, W, levels, radius, iters, flags)) return 0;
-  if (flags & (OF_FLAG_NORMALIZE | OF_FLAG_GAUSSIAN_WINDOW))
-    return set_error("OF_FLAG_NORMALIZE and OF_FLAG_GAUSSIAN_WINDOW apply to plans only"), 0;
+  if (flags & (OF_FLAG_NORMALIZE | OF_FLAG_GAUSSIAN_WINDOW | OF_FLAG_GRAPH))
+    return set_error("OF_FLAG_NORMALIZE, OF_FLAG_GAUSSIAN_WINDOW and OF_FLAG_GRAPH apply to plans only"), 0;
   return session_bytes(H, W, levels, radius, iters, flags, nullptr, nullptr, nullptr);
 }
 
@@ -144,6 +144,7 @@ of_server* of_server_create(int levels, int radius, int iters, unsigned flags,
   if (flags & OF_FLAG_NORMALIZE) return set_error("OF_FLAG_NORMALIZE applies to plans only"), nullptr;
   if (flags & OF_FLAG_GAUSSIAN_WINDOW)
     return set_error("OF_FLAG_GAUSSIAN_WINDOW applies to plans only"), nullptr;
+  if (flags & OF_FLAG_GRAPH) return set_error("OF_FLAG_GRAPH applies to plans only"), nullptr;
   if (!check_params(1 << (levels > 0 ? levels - 1 : 0), 1 << (levels > 0 ? levels - 1 : 0), levels,
                     radius, iters, flags))
     return nullptr;

@@ -51,16 +51,18 @@ def test_workspace_bytes_and_validation(lib):
     expect16 = sum(2 * a(h * w * 2) for h, w in sizes) + 4 * a(H * W * 4)
     assert lib.of_plan_workspace_bytes(H, W, 3, 4, 4, 1) == expect16
     for bad in [(0, 5, 1, 1, 1, 0), (5, 5, 0, 1, 1, 0), (4, 4, 4, 1, 1, 0), (64, 64, 2, -1, 1, 0),
-                (64, 64, 2, 99, 1, 0), (64, 64, 2, 2, -1, 0), (64, 64, 2, 2, 1, 32)]:
+                (64, 64, 2, 99, 1, 0), (64, 64, 2, 2, -1, 0), (64, 64, 2, 2, 1, 64)]:
         assert lib.of_plan_workspace_bytes(*bad) == 0
     # OF_FLAG_NORMALIZE adds two level-0 float32 planes; the Gaussian window needs nothing more
     assert lib.of_plan_workspace_bytes(H, W, 3, 4, 4, 8) == expect + 2 * a(H * W * 4)
     assert lib.of_plan_workspace_bytes(H, W, 3, 4, 4, 16) == expect
-    # both plan-only flags are refused by batches and servers
+    # OF_FLAG_GRAPH changes the launch mode only
+    assert lib.of_plan_workspace_bytes(H, W, 3, 4, 4, 32) == expect
+    # the plan-only flags are refused by batches and servers
     import ctypes
     hs, ws = (ctypes.c_int * 1)(H), (ctypes.c_int * 1)(W)
     assert lib.of_batch_workspace_bytes(1, hs, ws, 3, 4, 4, 0) > 0
-    for f in (8, 16):
+    for f in (8, 16, 32):
         assert lib.of_batch_workspace_bytes(1, hs, ws, 3, 4, 4, f) == 0
         assert lib.of_session_bytes(H, W, 3, 4, 4, f) == 0
     assert lib.of_plan_create(0, 5, 1, 1, 1) is None
