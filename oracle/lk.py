@@ -78,11 +78,18 @@ def pyr_reduce(P):
     return B[0::2, 0::2].copy()
 
 
-def pyramid(F, levels, dtype=np.float64):
-    """Level 0 is the frame itself (converted exactly); level l+1 = pyr_reduce(level l)."""
+def pyramid(F, levels, dtype=np.float64, storage=None):
+    """Level 0 is the frame itself (converted exactly); level l+1 = pyr_reduce(level l).
+
+    ``storage`` (e.g. ``np.float16``): every level >= 1 is rounded to that type as it is
+    produced (and read back exactly), modelling reduced-precision storage of the pyramid for
+    the rounding-floor diagnostic; None keeps ``dtype`` throughout."""
     P = [np.asarray(F).astype(dtype)]
     for _ in range(levels - 1):
-        P.append(pyr_reduce(P[-1]))
+        nxt = pyr_reduce(P[-1])
+        if storage is not None:
+            nxt = nxt.astype(storage).astype(dtype)
+        P.append(nxt)
     return P
 
 
@@ -93,11 +100,43 @@ def upsample_flow(uc, H, W):
     return dt.type(2) * bilinear(uc, x.astype(dt) / dt.type(2), y.astype(dt) / dt.type(2))
 
 
-def warp(I2, u, v):
-    """W2(x, y) = I2 sampled at (x + u, y + v) with clamped coordinates."""
+def bilinear_split(Z, x, y, u, v):
+    """The same sample as ``bilinear(Z, x + u, y + v)`` for integer pixel indices x, y, with
+    the coordinate kept as an integer base x + floor(u) and a fraction u - floor(u) instead of
+    the rounded sum (the sum loses the low bits of u in reduced precision).  A base outside
+    [0, W-2] is clamped into the plane with fraction 0, which is where the clamped coordinate
+    of ``bilinear`` lands; equal to ``bilinear`` in exact arithmetic."""
+    H, W = Z.shape
+    dt = Z.dtype
+    fu, fv = np.floor(u), np.floor(v)
+    bx = x + fu.astype(np.int64)
+    by = y + fv.astype(np.int64)
+    inx = (bx >= 0) & (bx <= W - 2)
+    iny = (by >= 0) & (by <= H - 2)
+    a = np.where(inx, u - fu, dt.type(0)).astype(dt, copy=False)
+    b = np.where(iny, v - fv, dt.type(0)).astype(dt, copy=False)
+    x0 = np.clip(bx, 0, W - 1)
+    y0 = np.clip(by, 0, H - 1)
+    x1 = np.where(inx, x0 + 1, x0)
+    y1 = np.where(iny, y0 + 1, y0)
+    one = dt.type(1)
+    return ((one - a) * (one - b) * Z[y0, x0] + a * (one - b) * Z[y0, x1]
+            + (one - a) * b * Z[y1, x0] + a * b * Z[y1, x1])
+
+
+def warp(I2, u, v, coords="sum"):
+    """W2(x, y) = I2 sampled at (x + u, y + v) with clamped coordinates.
+
+    ``coords``: "sum" forms the sample coordinate x + u (the oracle's definition); "split"
+    keeps integer base and fraction apart (``bilinear_split``), used by the reduced-precision
+    rounding-floor diagnostic; both are the same function in exact arithmetic."""
     H, W = I2.shape
     dt = I2.dtype
     y, x = np.mgrid[0:H, 0:W]
+    if coords == "split":
+        return bilinear_split(I2, x, y, u, v)
+    if coords != "sum":
+        raise ValueError("coords must be 'sum' or 'split'")
     return bilinear(I2, x.astype(dt) + u, y.astype(dt) + v)
 
 
@@ -183,10 +222,10 @@ def solve(A, B, C, bx, by, tau=TAU):
     return du, dv
 
 
-def lk_iteration(I1l, I2l, u, v, r, tau=TAU, weights=None):
+def lk_iteration(I1l, I2l, u, v, r, tau=TAU, weights=None, coords="sum"):
     """One Gauss-Newton iteration at one level: warp, gradients, window sums, solve, update.
-    ``weights``: separable window taps (None = unweighted box)."""
-    W2 = warp(I2l, u, v)
+    ``weights``: separable window taps (None = unweighted box); ``coords``: see ``warp``."""
+    W2 = warp(I2l, u, v, coords)
     Ix, Iy = gradients(W2)
     It = W2 - I1l - Ix * u - Iy * v
     A, B, C, sx, sy = (window_sum(p, r, weights) for p in (Ix * Ix, Ix * Iy, Iy * Iy, Ix * It, Iy * It))
@@ -213,7 +252,7 @@ def mask_pyramid(M, levels):
 
 
 def flow(I1, I2, levels, radius, iters, tau=TAU, dtype=np.float64, return_levels=False,
-         mask=None, window="box"):
+         mask=None, window="box", coords="sum", storage=None):
     """Dense displacement (u, v) in level-0 pixels from frame I1 to frame I2.
 
     ``levels`` counts the pyramid levels including full resolution (>= 1), ``radius`` is the
@@ -221,14 +260,16 @@ def flow(I1, I2, levels, radius, iters, tau=TAU, dtype=np.float64, return_levels
     ``mask`` (optional, level-0 booleans, True = computed): after every iteration the field is
     set to zero at the pixels the level's mask (``mask_pyramid``) excludes.
     ``window``: "box" (unweighted) or "gauss" (``gaussian_weights``).
+    ``coords``: sample coordinates of the warp, "sum" (the definition) or "split" (``warp``).
+    ``storage``: reduced-precision storage of pyramid levels >= 1 (``pyramid``), diagnostic only.
     """
     if window not in ("box", "gauss"):
         raise ValueError("window must be 'box' or 'gauss'")
     weights = gaussian_weights(radius) if window == "gauss" else None
     if levels < 1 or radius < 0 or iters < 0:
         raise ValueError("levels >= 1, radius >= 0, iters >= 0 required")
-    P1 = pyramid(I1, levels, dtype)
-    P2 = pyramid(I2, levels, dtype)
+    P1 = pyramid(I1, levels, dtype, storage)
+    P2 = pyramid(I2, levels, dtype, storage)
     M = mask_pyramid(mask, levels) if mask is not None else None
     H, W = P1[-1].shape
     u = np.zeros((H, W), dtype=dtype)
@@ -240,7 +281,7 @@ def flow(I1, I2, levels, radius, iters, tau=TAU, dtype=np.float64, return_levels
             u = upsample_flow(u, H, W)
             v = upsample_flow(v, H, W)
         for _ in range(iters):
-            u, v = lk_iteration(P1[lev], P2[lev], u, v, radius, tau, weights)
+            u, v = lk_iteration(P1[lev], P2[lev], u, v, radius, tau, weights, coords)
             if M is not None:
                 u = np.where(M[lev], u, 0.0).astype(dtype)
                 v = np.where(M[lev], v, 0.0).astype(dtype)
