@@ -9,9 +9,10 @@
 //       P1  warped frame for the band's new rows into an LDS ring; all global loads of the
 //           band (field, frame 1, centre field of the band's outputs) are issued here;
 //       P2  the five products Ix^2, IxIy, Iy^2, Ix It, Iy It of the band's rows into LDS;
-//       P3  horizontal window sums: one thread per (channel, row, 8-column segment), a
-//           direct (2r+1)-term sum re-seeded at every segment, then a running sum over the
-//           segment's 8 outputs (segments sit on multiples of 8 of the level's columns);
+//       P3  horizontal window sums: one thread per (channel, row, 8-column segment); every
+//           window of a segment holds one common column, so each window is a suffix sum plus
+//           a prefix sum of its own values (no subtraction of values leaving the window);
+//           r <= 3 takes direct sums (segments sit on multiples of 8 of the level's columns);
 //           the Gaussian-weighted window takes a direct weighted sum per output instead;
 //       P4  vertical window sums: one thread per (channel, column) holds the previous
 //           band's horizontal sums in registers; the window of the band's row i is the
@@ -318,14 +319,33 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
             for (int q = 1; q <= 2 * R; ++q) s = fmaf(a.taps[q], vbuf[j + q], s);
             hv[k][j] = s;
           }
-        } else {
-          float s = vbuf[0];
+        } else if constexpr (2 * R >= 7) {
+          // Every window of the segment holds column 2R (the last column of window 0), so
+          // window j is the suffix vbuf[j..2R] plus the prefix vbuf[2R+1..2R+j]: sums of
+          // values inside the window only.  (A running sum that subtracts the value leaving
+          // the window carries a rounding error relative to the largest product of the
+          // segment rather than of the window, which ill-conditioned windows amplify.)
+          float suf = vbuf[2 * R];
 #pragma unroll
-          for (int q = 1; q <= 2 * R; ++q) s += vbuf[q];
-          hv[k][0] = s;
+          for (int q = 2 * R - 1; q >= 7; --q) suf = vbuf[q] + suf;
+          float sj[8];
+          sj[7] = suf;
+#pragma unroll
+          for (int j = 6; j >= 0; --j) sj[j] = vbuf[j] + sj[j + 1];
+          hv[k][0] = sj[0];
+          float pre = 0.f;
 #pragma unroll
           for (int j = 1; j < 8; ++j) {
-            s = (s - vbuf[j - 1]) + vbuf[j + 2 * R];
+            pre = j == 1 ? vbuf[2 * R + 1] : pre + vbuf[2 * R + j];
+            hv[k][j] = sj[j] + pre;
+          }
+        } else {
+          // r <= 3: direct sums, at most 6 additions per output
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            float s = vbuf[j];
+#pragma unroll
+            for (int q = 1; q <= 2 * R; ++q) s += vbuf[j + q];
             hv[k][j] = s;
           }
         }

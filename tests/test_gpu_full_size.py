@@ -8,6 +8,7 @@ import os
 import numpy as np
 import pytest
 
+import floor_util
 import oracle
 import synth
 from gpu_util import announce, dev, flow_error, report, to_dev
@@ -95,11 +96,10 @@ def test_c5_served_full_sizes_against_plain_path_and_oracle(gpu_lib):
             torch.cuda.synchronize()
             assert np.array_equal(flows[t][0], pu.cpu().numpy()) and np.array_equal(flows[t][1], pv.cpu().numpy()), (s, t)
         plan.close()
-    # the oracle on the 640x480 stream, away from the outflow borders (8 px per frame; see the
-    # serving test for the FP32 floor there)
+    # the oracle on the 640x480 stream, every pixel (its committed FP16-storage floor is far
+    # below the tolerance)
     announce("c5: oracle on the 640x480 stream")
     flows = [(r.u, r.v) for r in reqs[0] if r.has_flow]
     ou, ov = oracle.flow(streams[0][0], streams[0][1], wl.levels, wl.radius, wl.iters)
-    m = 2 * 8 + wl.radius + 2
-    d = flow_error(flows[0][0], flows[0][1], ou, ov)[m:-m, m:-m]
-    assert d.max() <= TOL16, report(d, TOL16)
+    d = flow_error(flows[0][0], flows[0][1], ou, ov)
+    print(floor_util.check_all_pixels(d, TOL16, floor_util.load_floor("c5_640_fp16"), "c5 640x480"))

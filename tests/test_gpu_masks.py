@@ -29,7 +29,7 @@ def test_masked_plan_matches_oracle_and_skips_tiles(gpu_lib):
     torch.cuda.synchronize()
     ref0 = (u0.cpu().numpy(), v0.cpu().numpy())
     plan.set_mask(to_dev(M))
-    for rep in range(2):                      # graph capture, then replay
+    for rep in range(2):                      # two eager runs
         u, v = plan.compute(to_dev(I1), to_dev(I2))
         torch.cuda.synchronize()
         gu, gv = u.cpu().numpy(), v.cpu().numpy()
@@ -87,3 +87,36 @@ def test_fully_masked_frame_is_zero(gpu_lib):
     with pytest.raises(ofmi.OfError):
         plan.set_mask(to_dev(np.ones((255, 256), np.uint8)))
     plan.close()
+
+
+def test_masked_plan_graph_replay(gpu_lib):
+    """A masked plan replaying its captured schedule (OF_FLAG_GRAPH) on fixed buffers equals the
+    masked eager plan bitwise, replay after replay with eager work between, and the oracle."""
+    import torch
+    ofmi = gpu_lib
+    I1, I2, _, _ = synth.make_pair("c1", 6)
+    M = _obstacle_mask(256, 256)
+    d1, d2, dm = to_dev(I1), to_dev(I2), to_dev(M)
+    eager = ofmi.Plan(256, 256, 3, 4, 4, device=dev(), graph=False)
+    graph = ofmi.Plan(256, 256, 3, 4, 4, device=dev(), graph=True)
+    eager.set_mask(dm)
+    graph.set_mask(dm)
+    ue, ve = eager.compute(d1, d2)
+    torch.cuda.synchronize()
+    ref = (ue.cpu().numpy(), ve.cpu().numpy())
+    ou, ov = oracle.flow(I1, I2, 3, 4, 4, mask=M.astype(bool))
+    d = flow_error(ref[0], ref[1], ou, ov)
+    assert d.max() <= 1e-3, report(d, 1e-3)
+    ug = torch.empty_like(ue)
+    vg = torch.empty_like(ve)
+    for rep in range(4):
+        announce(f"masked plan graph replay {rep}")
+        ug.fill_(float("nan"))
+        vg.fill_(float("nan"))
+        graph.compute(d1, d2, ug, vg)
+        eager.compute(d2, d1)                 # eager work between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(ug.cpu().numpy(), ref[0]), f"replay {rep}"
+        assert np.array_equal(vg.cpu().numpy(), ref[1]), f"replay {rep}"
+    eager.close()
+    graph.close()

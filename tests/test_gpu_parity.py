@@ -6,6 +6,7 @@ bit-exact where the arithmetic is exact (pyramid levels 1-2 from uint8, zero flo
 import numpy as np
 import pytest
 
+import floor_util
 import oracle
 import synth
 from gpu_util import announce, dev, flow_error, gpu_flow, report, to_dev
@@ -113,22 +114,30 @@ def _parity(ofmi, I1, I2, L, r, K, fp16=False, tol=TOL32):
     return d
 
 
+def _floor_case(ofmi, case, fp16=False):
+    """Whole-method parity of a floor case on every pixel (tolerance, or tolerance plus the
+    committed FP32 floor multiple where the floor says the tolerance is out of reach)."""
+    I1, I2 = floor_util.case_inputs(case)
+    _, L, r, K, window, _, tol = floor_util.CASES[case]
+    u, v = gpu_flow(ofmi, I1, I2, L, r, K, fp16=fp16)
+    ou, ov = oracle.flow(I1, I2, L, r, K, window=window)
+    d = flow_error(u, v, ou, ov)
+    print(floor_util.check_all_pixels(d, tol, floor_util.load_floor(case), case))
+    return d
+
+
 def test_c1_256_fp32(gpu_lib):
-    wl = synth.workload("c1")
-    I1, I2, _, _ = synth.make_pair("c1", 0)
-    _parity(gpu_lib, I1, I2, wl.levels, wl.radius, wl.iters)
+    d = _floor_case(gpu_lib, "c1")
+    assert d.max() <= TOL32, report(d, TOL32)
 
 
 def test_c2_1024_fp32_full_size(gpu_lib):
-    wl = synth.workload("c2")
-    I1, I2, _, _ = synth.make_pair("c2", 0)
-    _parity(gpu_lib, I1, I2, wl.levels, wl.radius, wl.iters)
+    d = _floor_case(gpu_lib, "c2")
+    assert d.max() <= TOL32, report(d, TOL32)
 
 
 def test_c3_1024_fp16_storage(gpu_lib):
-    wl = synth.workload("c3")
-    I1, I2, _, _ = synth.make_pair("c3", 0)
-    d = _parity(gpu_lib, I1, I2, wl.levels, wl.radius, wl.iters, fp16=True, tol=TOL16)
+    d = _floor_case(gpu_lib, "c3_fp16", fp16=True)
     print(f"c3 fp16 storage: max {d.max():.3e} rms {np.sqrt((d ** 2).mean()):.3e}")
 
 
@@ -147,24 +156,19 @@ def test_ragged_sizes(gpu_lib, shape, L, r, K):
     _parity(gpu_lib, big1, big2, L, r, K)
 
 
-def test_radius_one_single_iteration(gpu_lib):
-    """3x3 windows sit below the FP32 rounding floor over several iterations (an FP32 run of the
-    oracle's own operation order departs by tens of px), so r = 1 is compared on one iteration,
-    on pixels whose window is well conditioned (D / T^2 >= 1e-2); elsewhere finite values."""
-    from oracle import lk
-    I1, I2, _, _ = synth.make_pair("c1", 4)
-    I1, I2 = I1[:129, :200].copy(), I2[:129, :200].copy()
-    u, v = gpu_flow(gpu_lib, I1, I2, 1, 1, 1)
-    ou, ov = oracle.flow(I1, I2, 1, 1, 1)
-    f1, f2 = I1.astype(float), I2.astype(float)
-    Ix, Iy = lk.gradients(f2)
-    A, B, C = (lk.box_sum(p, 1) for p in (Ix * Ix, Ix * Iy, Iy * Iy))
-    with np.errstate(invalid="ignore", divide="ignore"):
-        q = (A * C - B * B) / (A + C) ** 2
-    good = q >= 1e-2
+@pytest.mark.parametrize("case", ["r1_L1_K1", "r1_L1_K3", "r1_L2_K3"])
+def test_radius_one_all_pixels(gpu_lib, case):
+    """3x3 windows: one iteration is well within the tolerance everywhere; over several
+    iterations the least conditioned windows amplify rounding (an FP32 run of the oracle's own
+    operation order departs from FP64 by up to 1.7 px at two levels), so every pixel is held to
+    the tolerance or, where the committed FP32 floor of that pixel says no FP32 evaluation can
+    get closer, to the tolerance plus a multiple of the floor."""
+    I1, I2 = floor_util.case_inputs(case)
+    _, L, r, K, _, _, tol = floor_util.CASES[case]
+    u, v = gpu_flow(gpu_lib, I1, I2, L, r, K)
+    ou, ov = oracle.flow(I1, I2, L, r, K)
     d = flow_error(u, v, ou, ov)
-    assert good.mean() > 0.5
-    assert d[good].max() <= TOL32, report(np.where(good, d, 0), TOL32)
+    print(floor_util.check_all_pixels(d, tol, floor_util.load_floor(case), case))
     assert np.all(np.isfinite(u)) and np.all(np.isfinite(v))
 
 
