@@ -147,6 +147,27 @@ OF_API of_status of_compute(of_plan* plan, const void* I1, const void* I2, float
 /* Releases the plan and the workspace it allocated.  NULL-safe. */
 OF_API void of_plan_destroy(of_plan* plan);
 
+/* --------------------------------------------------------------------- allocation-free form
+ * For callers that cannot allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the flow of one pair without a plan object, with
+ * the pyramids and field buffers in a fixed device scratch array inside the library
+ * (OF_NOALLOC_SCRATCH_MIB MiB on each device that calls it, held until the process ends).
+ * Parameters and results as of_plan_create_ex + of_compute in the default launch
+ * configuration (bitwise the same), except: no plan, no masks, no graph flags (OF_FLAG_GRAPH
+ * and OF_FLAG_NO_GRAPH give OF_EINVAL), kernels are launched one by one on `stream`.  No call
+ * allocates or frees memory; the first call on a device looks up that device's copy of the
+ * array.  Every call on one device uses the same array, so calls that may overlap on one
+ * device (different streams, other threads) race and must be ordered by the caller; each
+ * call writes every scratch byte it reads.  Errors: OF_EINVAL on invalid parameters or
+ * pointers (nothing enqueued); OF_ENOMEM when of_plan_workspace_bytes(...) of these
+ * parameters exceeds of_noalloc_scratch_bytes() (e.g. 1024 x 1024 FP32 at 4 levels needs
+ * about 20 MB; 2048 x 2048 does not fit); OF_EHIP on a launch failure. */
+#define OF_NOALLOC_SCRATCH_MIB 32
+OF_API size_t of_noalloc_scratch_bytes(void);
+OF_API of_status of_compute_noalloc(int H, int W, int levels, int radius, int iters,
+                                    unsigned flags, const void* I1, const void* I2, float* u,
+                                    float* v, void* stream);
+
 /* Region-of-interest mask, the speed lever of Sec. 3.3 (skip obstacles and side walls):
  * `mask` is a DEVICE H x W uint8 plane, nonzero = compute.  The plan copies it (on `stream`,
  * after synchronising the device) and derives one mask per level: a coarser pixel is

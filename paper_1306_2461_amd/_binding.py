@@ -42,6 +42,8 @@ SIGNATURES = {
     "of_plan_create_ex": (_vp, [_c_int, _c_int, _c_int, _c_int, _c_int, _c_uint, _vp, _c_size]),
     "of_compute": (_c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "of_plan_destroy": (None, [_vp]),
+    "of_noalloc_scratch_bytes": (_c_size, []),
+    "of_compute_noalloc": (_c_int, [_c_int, _c_int, _c_int, _c_int, _c_int, _c_uint, _vp, _vp, _vp, _vp, _vp]),
     "of_plan_set_mask": (_c_int, [_vp, _vp, _vp]),
     "of_levels_for_displacement": (_c_int, [ctypes.c_float, _c_int, _c_int]),
     "of_last_error": (ctypes.c_char_p, []),

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "../../include/ofmi.h"
@@ -401,6 +402,67 @@ of_status of_compute(of_plan* p, const void* I1, const void* I2, float* u, float
       return enqueue_pair(p->g, p->ws, I1, I2, u, v, cs, nullptr);
     });
   }
+  if (e != hipSuccess) return hip_fail("kernel launch", e);
+  return OF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device scratch of of_compute_noalloc: a file-scope array of fixed size (each device that
+// runs the library holds one until the process ends).  Host code never uses the array's name
+// as an address: the device address of each device's copy comes from hipGetSymbolAddress,
+// taken once per device with that device current.
+constexpr size_t kNoallocScratchBytes = (size_t)OF_NOALLOC_SCRATCH_MIB << 20;
+__device__ __align__(256) char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch (set up on the first call per device).
+hipError_t scratch_for(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (char*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t of_noalloc_scratch_bytes(void) { return kNoallocScratchBytes; }
+
+of_status of_compute_noalloc(int H, int W, int levels, int radius, int iters, unsigned flags,
+                             const void* I1, const void* I2, float* u, float* v, void* stream) {
+  if (flags & (OF_FLAG_GRAPH | OF_FLAG_NO_GRAPH))
+    return set_error("of_compute_noalloc launches eagerly: graph flags are not accepted"), OF_EINVAL;
+  if (!check_params(H, W, levels, radius, iters, flags)) return OF_EINVAL;
+  if (!I1 || !I2 || !u || !v) return set_error("NULL frame or output pointer"), OF_EINVAL;
+  if (u == v) return set_error("u and v must be distinct planes"), OF_EINVAL;
+  if (((uintptr_t)u | (uintptr_t)v) & 3) return set_error("u, v must be 4-byte aligned"), OF_EINVAL;
+  if ((flags & OF_FLAG_INPUT_F32) && (((uintptr_t)I1 | (uintptr_t)I2) & 3))
+    return set_error("float32 frames must be 4-byte aligned"), OF_EINVAL;
+  const Geometry g = make_geometry(H, W, levels, radius, iters, flags);
+  if (g.bytes > kNoallocScratchBytes)
+    return set_error("of_compute_noalloc: this frame size needs " + std::to_string(g.bytes) +
+                     " bytes of scratch, more than the library's " +
+                     std::to_string(kNoallocScratchBytes)),
+           OF_ENOMEM;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  char* ws = nullptr;
+  if (e == hipSuccess) e = scratch_for(dev, &ws);
+  if (e != hipSuccess) return hip_fail("noalloc scratch", e);
+  e = enqueue_pair(g, ws, I1, I2, u, v, (hipStream_t)stream, nullptr);
   if (e != hipSuccess) return hip_fail("kernel launch", e);
   return OF_OK;
 }
