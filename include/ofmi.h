@@ -76,9 +76,10 @@ typedef enum {
                                           over the same (2r+1)^2 support (a variant of the
                                           unweighted interrogation window of Sec. 2.4) */
 #define OF_FLAG_GRAPH        (1u << 5) /* plans only: capture the schedule into a hipGraph
-                                          per pointer tuple and replay it (batches and
-                                          servers always replay graphs); plans launch kernels
-                                          one by one otherwise */
+                                          per pointer tuple and replay it; plans launch kernels
+                                          one by one otherwise (batches replay graphs unless
+                                          OF_FLAG_NO_GRAPH; servers and sessions launch
+                                          kernels one by one) */
 
 /* Tile variants of the fused iteration kernel (launch configuration; results do not depend
  * on them).  NARROW: 5 threads per output column.  WIDE: 10 threads per output column with
@@ -208,18 +209,28 @@ OF_API of_status of_plan_autotune(of_plan* plan, const void* I1, const void* I2,
 OF_API const char* of_last_error(void);
 
 /* --------------------------------------------------------------------- kernel timing
- * Per-kernel timing for measurement: while enabled, every kernel launch of the plan is
- * bracketed by a pair of hipEvents recorded on the launch stream.  of_plan_read_timing
- * waits for the recorded events, returns the totals since the last read and resets them.
- *   kernel: OF_KERNEL_ITERATE (the fused iteration) or OF_KERNEL_REDUCE (pyramid: one
- *   reduction, or one launch building 2 or 3 levels, for levels of up to 2^20 pixels).
- *   total_ms: summed event-to-event time; launches: number of launches; units: pixel-
- *   iterations (ITERATE) or output pixels (REDUCE); bytes: algorithmic HBM bytes of those
- *   launches (ITERATE: per pixel-iteration 2 frame elements + 16 bytes of u,v read and
- *   written; REDUCE: per frame the input plane once and every output plane once).  Any out pointer may be NULL.
- * Errors: OF_EINVAL on a NULL plan or unknown kernel; OF_EHIP if event creation fails. */
+ * Event timing for measurement, on the launch stream.  enable = OF_TIMING_LAUNCH: every
+ * kernel launch of the plan is bracketed by a pair of hipEvents (kernel ids OF_KERNEL_ITERATE,
+ * OF_KERNEL_REDUCE).  enable = OF_TIMING_LEVEL: one event pair around all pyramid launches of
+ * a pair (OF_KERNEL_REDUCE) and one around the K iteration launches of each level l
+ * (OF_KERNEL_LEVEL(l)), with no events between the launches of a span, so a span's time per
+ * launch is the kernels' back-to-back duration.  0 switches timing off.
+ * of_plan_read_timing waits for the recorded events of `kernel`, returns the totals since
+ * the last read and resets them.
+ *   kernel: OF_KERNEL_ITERATE (the fused iteration), OF_KERNEL_REDUCE (pyramid: one
+ *   reduction, or one launch building 2 or 3 levels, for levels of up to 2^20 pixels), or
+ *   OF_KERNEL_LEVEL(l) (level l's iteration launches, OF_TIMING_LEVEL only).
+ *   total_ms: summed event-to-event time; launches: number of kernel launches timed; units:
+ *   pixel-iterations (ITERATE, LEVEL) or output pixels (REDUCE); bytes: algorithmic HBM bytes
+ *   of those launches (ITERATE, LEVEL: per pixel-iteration 2 frame elements + 16 bytes of u,v
+ *   read and written; REDUCE: per frame the input plane once and every output plane once).
+ *   Any out pointer may be NULL.
+ * Errors: OF_EINVAL on a NULL plan, unknown mode or kernel; OF_EHIP if event creation fails. */
 #define OF_KERNEL_ITERATE 0
 #define OF_KERNEL_REDUCE 1
+#define OF_KERNEL_LEVEL(l) (16 + (l))
+#define OF_TIMING_LAUNCH 1
+#define OF_TIMING_LEVEL 2
 OF_API of_status of_plan_set_timing(of_plan* plan, int enable);
 OF_API of_status of_plan_read_timing(of_plan* plan, int kernel, double* total_ms,
                                      long long* launches, double* units, double* bytes);
@@ -232,12 +243,19 @@ OF_API of_status of_plan_read_timing(of_plan* plan, int kernel, double* total_ms
  * batch exploits that independence on one device. */
 typedef struct of_batch of_batch;
 
+/* Argument blocks of a batch, held in its workspace: one per cached graph (OF_BATCH_GRAPHS
+ * pointer sets) and a ring of OF_BATCH_EAGER_SLOTS for eager runs. */
+#define OF_BATCH_GRAPHS 8
+#define OF_BATCH_EAGER_SLOTS 4
+
 /* Workspace bytes of a batch of n pairs of sizes H[i] x W[i] (host arrays), 0 on invalid
- * parameters (each pair as of_plan_create_ex; 1 <= n <= 65536). */
+ * parameters (each pair as of_plan_create_ex; 1 <= n <= 65536): every pair's pyramids and
+ * field buffers, the tile work lists and the argument blocks. */
 OF_API size_t of_batch_workspace_bytes(int n, const int* H, const int* W, int levels, int radius,
                                        int iters, unsigned flags);
 
 /* Batch object.  H, W: host arrays of n sizes (copied).  workspace as in of_plan_create_ex.
+ * Set-up call: uploads the work lists and allocates pinned staging for the argument blocks.
  * Returns NULL on invalid parameters or allocation failure. */
 OF_API of_batch* of_batch_create(int n, const int* H, const int* W, int levels, int radius,
                                  int iters, unsigned flags, void* workspace,
@@ -246,12 +264,16 @@ OF_API of_batch* of_batch_create(int n, const int* H, const int* W, int levels, 
 /* Flow of every pair i: frames I1[i] -> I2[i] into u[i], v[i].  I1, I2, u, v are HOST arrays
  * of n DEVICE pointers, each plane laid out as for of_compute with pair i's size.  The whole
  * schedule is one hipGraph replay per call, captured on the first call with a given set of
- * pointers (at most 64 sets kept; each holds a small device argument block).  With
- * OF_FLAG_NO_GRAPH or timing on, launches are eager and the arguments are uploaded through a
- * pinned staging buffer.  Results are bitwise identical to of_compute on the same pair with
- * the same tile configuration (the window sums do not depend on the tiling).
- * Errors: OF_EINVAL for a NULL batch, array or buffer or u[i] == v[i]; OF_EHIP on launch
- * failure. */
+ * pointers; its arguments are uploaded on `stream` (pinned staging, asynchronous) into one of
+ * the OF_BATCH_GRAPHS argument blocks.  A ninth pointer set takes the block of the least
+ * recently used graph, which is dropped once its last replay has completed (the call waits
+ * for that replay).  Otherwise the call allocates nothing and does not wait.  With
+ * OF_FLAG_NO_GRAPH or timing on, launches are eager and the arguments go through a ring of
+ * OF_BATCH_EAGER_SLOTS blocks; when the next one is still read by an earlier run the call
+ * returns OF_ESTATE and enqueues nothing.  Results are bitwise identical to of_compute on the
+ * same pair with the same tile configuration (the window sums do not depend on the tiling).
+ * Errors: OF_EINVAL for a NULL batch, array or buffer or u[i] == v[i]; OF_ESTATE (eager ring
+ * busy); OF_EHIP on launch failure. */
 OF_API of_status of_batch_compute(of_batch* b, const void* const* I1, const void* const* I2,
                                   float* const* u, float* const* v, void* stream);
 
@@ -284,18 +306,27 @@ OF_API void of_batch_destroy(of_batch* b);
 /* --------------------------------------------------------------------- serving form
  * Frame streams (e.g. a camera sequence) processed pair by pair: each stream is a session that
  * keeps its previous frame's pyramid resident on the device, so a new frame costs one new
- * pyramid plus the iterations (the paper's first computing scheme, Sec. 2.4: "each field
- * computation requires only one image to be processed").  A server holds the sessions of one
- * parameter set, admits new streams against an HBM budget, and pushes the new frames of many
- * streams together (one launch per pyramid step and per (level, iteration) phase over all of
- * their tiles).  Pushes of one server must be ordered on one stream; the server is internally
- * locked, so concurrent calls from several threads serialise. */
+ * pyramid plus the iterations (the paper's first computing scheme, Sec. 2.4, in which each
+ * field needs only one newly acquired image to be processed).  Sessions of one parameter set
+ * belong to a server, which admits new streams against an HBM budget and pushes the new
+ * frames of many sessions together (one launch per pyramid step and per (level, iteration)
+ * phase over all of their tiles; kernels are launched one by one).
+ *
+ * Push arguments travel through a ring of OF_SERVER_RING staging slots (pinned host and
+ * device memory of the server), sized when a session opens for a push of every open session.
+ * A push never allocates and never waits: when the slot it needs is still held by one of the
+ * last OF_SERVER_RING pushes in flight, it returns OF_ESTATE and enqueues nothing (retry once
+ * an earlier push has completed).  Pushes of one server must be ordered on one stream; the
+ * server is internally locked, so concurrent calls from several threads serialise. */
 typedef struct of_server of_server;
 typedef struct of_session of_session;
 
+#define OF_SERVER_RING 8
+
 /* Device bytes one session of an H x W stream keeps resident (two frame pyramids including
- * level 0, four level-0 FP32 field planes); 0 on invalid parameters, including the plan-only
- * flags OF_FLAG_NORMALIZE and OF_FLAG_GAUSSIAN_WINDOW. */
+ * level 0, four level-0 FP32 field planes); also the workspace size of of_session_create and
+ * of_server_open_ex.  0 on invalid parameters, including the plan-only flags
+ * OF_FLAG_NORMALIZE, OF_FLAG_GAUSSIAN_WINDOW and OF_FLAG_GRAPH. */
 OF_API size_t of_session_bytes(int H, int W, int levels, int radius, int iters, unsigned flags);
 
 /* Server for streams sharing levels, radius, iters and flags (OF_FLAG_NO_GRAPH ignored).
@@ -305,8 +336,15 @@ OF_API of_server* of_server_create(int levels, int radius, int iters, unsigned f
 
 /* Opens a session for an H x W stream.  Returns NULL (of_last_error says why) when the
  * parameters are invalid, when admitting it would exceed the HBM budget, or on allocation
- * failure.  The session memory is allocated here (hipMalloc). */
+ * failure.  Set-up call: it may grow the server's staging ring (after waiting for the device)
+ * and allocates the session memory (hipMalloc). */
 OF_API of_session* of_server_open(of_server* s, int H, int W);
+
+/* As of_server_open with caller-owned session memory: `workspace` is a device buffer of at
+ * least of_session_bytes(...) bytes, 256-byte aligned, kept alive until the session is closed
+ * (NULL = the library allocates it). */
+OF_API of_session* of_server_open_ex(of_server* s, int H, int W, void* workspace,
+                                     size_t workspace_bytes);
 
 /* Pushes the next frame of each of n distinct sessions of server s (host arrays of n
  * entries; frames[i] a device plane of session i's size and the server's frame type).  For a
@@ -314,24 +352,44 @@ OF_API of_session* of_server_open(of_server* s, int H, int W);
  * from its previous frame to frames[i] and has_flow[i] = 1; for a session's first frame only
  * its pyramid is built, u[i], v[i] are not touched (may be NULL) and has_flow[i] = 0.
  * frames[i] may be reused by the caller once the push's work on `stream` has completed.
- * Errors: OF_EINVAL (nothing enqueued) for NULL arguments, a session of another server or a
- * session listed twice; OF_EHIP on launch failure. */
+ * Errors (nothing enqueued): OF_EINVAL for NULL arguments, a session of another server or a
+ * session listed twice; OF_ESTATE when every staging slot is held by a push still in flight;
+ * OF_EHIP on launch failure. */
 OF_API of_status of_server_push(of_server* s, of_session* const* sessions, int n,
                                 const void* const* frames, float* const* u, float* const* v,
                                 int* has_flow, void* stream);
+
+/* Sessions without an explicit server (the hot-path boundary's session entry points): the
+ * session joins a library-held server of its parameter set on the current device (no budget;
+ * retired with its last session).  workspace as in of_server_open_ex (NULL = the library
+ * allocates).  Returns NULL on invalid parameters or allocation failure. */
+OF_API of_session* of_session_create(int H, int W, int levels, int radius, int iters,
+                                     unsigned flags, void* workspace, size_t workspace_bytes);
 
 /* of_server_push for one session. */
 OF_API of_status of_session_push(of_session* session, const void* frame, float* u, float* v,
                                  void* stream, int* has_flow);
 
+/* Continuous batching over sessions: of_server_push of n sessions, which must all belong to
+ * one server (the one of sessions[0]; sessions from of_session_create with equal parameters
+ * on one device share one). */
+OF_API of_status of_session_push_many(of_session* const* sessions, int n,
+                                      const void* const* frames, float* const* u,
+                                      float* const* v, int* has_flow, void* stream);
+
 /* Resident bytes of one session / of all open sessions of a server. */
 OF_API size_t of_session_resident_bytes(const of_session* session);
 OF_API size_t of_server_resident_bytes(const of_server* s);
 
-/* Closes one session (synchronises the device, frees its memory, returns its budget). */
+/* Closes one session of server s (synchronises the device, frees library-allocated session
+ * memory, returns its budget). */
 OF_API of_status of_server_close(of_server* s, of_session* session);
 
-/* Destroys the server and every session still open.  NULL-safe. */
+/* Closes a session (of either kind; as of_server_close).  NULL-safe. */
+OF_API void of_session_destroy(of_session* session);
+
+/* Destroys the server and every session still open.  NULL-safe; a no-op for the
+ * library-held servers of of_session_create. */
 OF_API void of_server_destroy(of_server* s);
 
 /* --------------------------------------------------------------------- around the flow
@@ -359,6 +417,27 @@ OF_API of_status of_field_minmax(const float* x, long long n, float* out2, void*
                                  void* stream);
 OF_API of_status of_count_at_most(const float* x, long long n, float threshold,
                                   unsigned long long* count, void* stream);
+
+/* The bubble surface of a sequence of fields on the device, with no host read (Sec. 3.2,
+ * eq. 3, for the real-time loop that feeds S_bubble to flow control).  The mean field is the
+ * running time-mean of the fields so far; field t is thresholded with T_v = (min + max) / 2
+ * of the mean of the fields before it (field 0 with its own).
+ *   of_plan_set_bubble: device pointers to the threshold T_v (float) and a count (uint64);
+ *     while set, every of_compute clears *count and its final iteration adds the number of
+ *     level-0 u values <= *threshold it writes (a wave sum and one atomic per wave: no pass of
+ *     its own).  NULL, NULL removes it.  Drops the plan's captured graphs.
+ *   of_bubble_step, after field t of H x W = n vectors has been computed into u: *surface =
+ *     S_bubble(t) (for t >= 1 from *count; for t = 0 counted here against field 0's own
+ *     threshold), then mean <- mean + (u - mean) / (t + 1) (t = 0: mean <- u) and *threshold
+ *     <- (min + max) / 2 of the new mean, ready for field t + 1.  work: device scratch of 2
+ *     unsigned ints (caller-owned, reset by every call).  All pointers are device pointers;
+ *     nothing is read back to the host.
+ * Errors: OF_EINVAL on NULL or misaligned pointers, n < 1 or t < 0. */
+OF_API of_status of_plan_set_bubble(of_plan* plan, const float* threshold,
+                                    unsigned long long* count);
+OF_API of_status of_bubble_step(float* mean, const float* u, long long n, int t,
+                                unsigned long long* count, float* threshold, float* surface,
+                                void* work, void* stream);
 
 /* --------------------------------------------------------------------- stage entry points
  * One step of the method on caller buffers, for stage-by-stage checking.

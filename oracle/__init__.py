@@ -8,5 +8,5 @@ from .lk import (  # noqa: F401
     pyr_reduce, pyramid, solve, upsample_flow, warp, window_sum,
 )
 from .extras import (  # noqa: F401,E402
-    bubble_surface, bubble_threshold, levels_for_displacement, local_normalize, running_mean,
+    bubble_series, bubble_surface, bubble_threshold, levels_for_displacement, local_normalize, running_mean,
 )

@@ -15,6 +15,10 @@ TEST INFRASTRUCTURE ONLY (same rules as ``oracle.lk``).
   T_v = (min + max) / 2 of the time-mean streamwise field.  eq. 3's printed denominator is the
   sum of the components; the text describes a ratio to the number of vectors, which is what is
   computed.
+* ``bubble_series`` -- eq. 3 over a sequence of fields as a real-time system can evaluate it
+  (Sec. 3.2 feeds S_bubble to flow control as fields arrive): the mean field is the running
+  time-mean of the fields received so far, and field t is thresholded with T_v of the mean of
+  the fields before it (the first field, which has no predecessor, with its own T_v).
 """
 from __future__ import annotations
 
@@ -54,6 +58,24 @@ def bubble_threshold(mean_u) -> float:
 def bubble_surface(u, threshold: float) -> float:
     u = np.asarray(u)
     return float(np.count_nonzero(u <= threshold)) / u.size
+
+
+def bubble_series(fields):
+    """[S_bubble(t)] of a sequence of streamwise fields: S(0) = bubble_surface(u_0, T_v(u_0));
+    S(t) = bubble_surface(u_t, T_v(mean of u_0 .. u_{t-1})) for t >= 1."""
+    out = []
+    mean = None
+    thr = None
+    for t, u in enumerate(fields):
+        if t == 0:
+            mean = running_mean(np.zeros(np.shape(u)), u, 0)
+            thr = bubble_threshold(mean)
+            out.append(bubble_surface(u, thr))
+        else:
+            out.append(bubble_surface(u, thr))
+            mean = running_mean(mean, u, t)
+            thr = bubble_threshold(mean)
+    return out
 
 
 def _check():  # pragma: no cover - documentation of the closed forms used by the pins

@@ -23,6 +23,12 @@ OF_STAGE_REDUCE = 0
 OF_STAGE_ITERATE = 1
 OF_KERNEL_ITERATE = 0
 OF_KERNEL_REDUCE = 1
+OF_TIMING_LAUNCH = 1
+OF_TIMING_LEVEL = 2
+
+
+def OF_KERNEL_LEVEL(level: int) -> int:
+    return 16 + level
 OF_TILE_NARROW = 0
 OF_TILE_WIDE = 1
 OF_TILE_WIDE_LEAN = 2
@@ -62,6 +68,10 @@ SIGNATURES = {
     "of_session_bytes": (_c_size, [_c_int, _c_int, _c_int, _c_int, _c_int, _c_uint]),
     "of_server_create": (_vp, [_c_int, _c_int, _c_int, _c_uint, _c_size]),
     "of_server_open": (_vp, [_vp, _c_int, _c_int]),
+    "of_server_open_ex": (_vp, [_vp, _c_int, _c_int, _vp, _c_size]),
+    "of_session_create": (_vp, [_c_int, _c_int, _c_int, _c_int, _c_int, _c_uint, _vp, _c_size]),
+    "of_session_push_many": (_c_int, [_VPP, _c_int, _VPP, _VPP, _VPP, _INTP, _vp]),
+    "of_session_destroy": (None, [_vp]),
     "of_server_push": (_c_int, [_vp, _VPP, _c_int, _VPP, _VPP, _VPP, _INTP, _vp]),
     "of_session_push": (_c_int, [_vp, _vp, _vp, _vp, _vp, _INTP]),
     "of_session_resident_bytes": (_c_size, [_vp]),
@@ -72,6 +82,8 @@ SIGNATURES = {
     "of_field_mean_update": (_c_int, [_vp, _vp, ctypes.c_longlong, _c_int, _vp]),
     "of_field_minmax": (_c_int, [_vp, ctypes.c_longlong, _vp, _vp, _vp]),
     "of_count_at_most": (_c_int, [_vp, ctypes.c_longlong, ctypes.c_float, _vp, _vp]),
+    "of_plan_set_bubble": (_c_int, [_vp, _vp, _vp]),
+    "of_bubble_step": (_c_int, [_vp, _vp, ctypes.c_longlong, _c_int, _vp, _vp, _vp, _vp, _vp]),
     "of_plan_get_config": (_c_int, [_vp, _INTP, _INTP]),
     "of_plan_set_config": (_c_int, [_vp, _INTP, _INTP]),
     "of_plan_autotune": (_c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _c_int]),

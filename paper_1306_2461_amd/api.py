@@ -104,9 +104,18 @@ class Plan:
         B.check(B.load().of_plan_set_mask(self._h, ptr, _stream_handle(self.device, stream)),
                 "of_plan_set_mask")
 
-    def set_timing(self, enable: bool):
-        """Bracket every kernel launch with hipEvents on its stream (measurement only)."""
-        B.check(B.load().of_plan_set_timing(self._h, 1 if enable else 0), "of_plan_set_timing")
+    def set_bubble(self, threshold=None, count=None):
+        """eq. 3 count in the final iteration against the device scalar ``threshold`` into the
+        device uint64 ``count`` (see BubbleMonitor); None removes it."""
+        B.check(B.load().of_plan_set_bubble(self._h, None if threshold is None else threshold.data_ptr(),
+                                            None if count is None else count.data_ptr()), "of_plan_set_bubble")
+
+    def set_timing(self, enable):
+        """Event timing on the launch stream (measurement only): True / OF_TIMING_LAUNCH
+        brackets every launch, OF_TIMING_LEVEL each level's iteration launches and the pyramid
+        launches as spans; False switches it off."""
+        mode = B.OF_TIMING_LAUNCH if enable is True else int(enable)
+        B.check(B.load().of_plan_set_timing(self._h, mode), "of_plan_set_timing")
 
     def read_timing(self, kernel: int):
         """(total_ms, launches, units, algorithmic bytes) since the last read; waits on events."""
@@ -243,8 +252,10 @@ class Batch:
         variant = (ctypes.c_int * self.levels)(*cfg.get("variant", [-1] * self.levels))
         B.check(B.load().of_batch_set_config(self._h, bands, grid, variant), "of_batch_set_config")
 
-    def set_timing(self, enable: bool):
-        B.check(B.load().of_batch_set_timing(self._h, 1 if enable else 0), "of_batch_set_timing")
+    def set_timing(self, enable):
+        """As Plan.set_timing."""
+        mode = B.OF_TIMING_LAUNCH if enable is True else int(enable)
+        B.check(B.load().of_batch_set_timing(self._h, mode), "of_batch_set_timing")
 
     def read_timing(self, kernel: int):
         import ctypes
@@ -280,34 +291,40 @@ def normalize(I, radius: int = 5, eps: float = 1.0, out=None, stream=None):
 
 
 class BubbleMonitor:
-    """Recirculation-bubble surface of a sequence of fields (Sec. 3.2, eq. 3): keeps the running
-    mean of the streamwise component on the device; ``update(u)`` folds in a field and returns
-    the fraction of its vectors at or below T_v = (min + max) / 2 of the mean field."""
+    """Recirculation-bubble surface of a sequence of fields (Sec. 3.2, eq. 3), on the device.
+
+    Keeps the running time-mean of the streamwise component, the threshold T_v = (min + max)/2
+    of the mean of the fields seen so far, the count of vectors at or below it and S_bubble,
+    all as device tensors.  ``attach(plan)`` makes the plan's final iteration count the vectors
+    at or below the current threshold as it writes them; ``step(u)`` after each field then
+    finishes S_bubble for that field and moves the mean and threshold on (``of_bubble_step``).
+    Nothing is read back to the host: ``surface`` holds S_bubble of the last field once the
+    work on the stream passed to ``step`` has completed."""
 
     def __init__(self, H, W, device=None):
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.n = H * W
         self.mean = torch.zeros((H, W), dtype=torch.float32, device=self.device)
-        self.t = 0
-        self._mm = torch.empty(2, dtype=torch.float32, device=self.device)
+        self.threshold = torch.zeros(1, dtype=torch.float32, device=self.device)
+        self.count = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self.surface = torch.zeros(1, dtype=torch.float32, device=self.device)
         self._work = torch.empty(2, dtype=torch.int32, device=self.device)
-        self._count = torch.empty(1, dtype=torch.int64, device=self.device)
+        self.t = 0
 
-    def threshold(self, stream=None):
-        lib = B.load()
-        n = self.mean.numel()
-        B.check(lib.of_field_minmax(self.mean.data_ptr(), n, self._mm.data_ptr(), self._work.data_ptr(),
-                                    _stream_handle(self.device, stream)), "of_field_minmax")
-        lo, hi = self._mm.tolist()
-        return 0.5 * (lo + hi)
+    def attach(self, plan):
+        """Count at or below the threshold inside ``plan``'s final iteration."""
+        B.check(B.load().of_plan_set_bubble(plan._h, self.threshold.data_ptr(), self.count.data_ptr()),
+                "of_plan_set_bubble")
 
-    def update(self, u, stream=None):
-        lib = B.load()
-        n = u.numel()
-        st = _stream_handle(self.device, stream)
-        B.check(lib.of_field_mean_update(self.mean.data_ptr(), u.data_ptr(), n, self.t, st),
-                "of_field_mean_update")
+    def detach(self, plan):
+        B.check(B.load().of_plan_set_bubble(plan._h, None, None), "of_plan_set_bubble")
+
+    def step(self, u, stream=None):
+        """Finish S_bubble of field u (computed by the attached plan, or any field for t = 0)
+        and fold u into the mean; returns the device tensor ``surface``."""
+        B.check(B.load().of_bubble_step(self.mean.data_ptr(), u.data_ptr(), self.n, self.t,
+                                        self.count.data_ptr(), self.threshold.data_ptr(),
+                                        self.surface.data_ptr(), self._work.data_ptr(),
+                                        _stream_handle(self.device, stream)), "of_bubble_step")
         self.t += 1
-        thr = self.threshold(stream)
-        B.check(lib.of_count_at_most(u.data_ptr(), n, float(thr), self._count.data_ptr(), st),
-                "of_count_at_most")
-        return int(self._count.item()) / n
+        return self.surface

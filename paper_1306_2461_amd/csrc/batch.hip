@@ -29,6 +29,12 @@ struct LevelCfg {
   int variant;   // TileVariant, or -1: by tile count
 };
 
+// Argument blocks of a batch: one per cached graph (OF_BATCH_GRAPHS pointer sets) and a ring
+// of OF_BATCH_EAGER_SLOTS for eager runs.
+constexpr int kGraphSlots = OF_BATCH_GRAPHS;
+constexpr int kEagerSlots = OF_BATCH_EAGER_SLOTS;
+constexpr int kArgSlots = kGraphSlots + kEagerSlots;
+
 }  // namespace
 
 struct of_batch {
@@ -46,13 +52,16 @@ struct of_batch {
   std::vector<int> ntiles, nitems;
   std::vector<size_t> items_at;
   LevelCfg cfg[OF_MAX_LEVELS];
-  std::vector<char> staging_host;   // argument block being built
-  char* pinned = nullptr;           // pinned staging for eager uploads
-  hipEvent_t staged = nullptr;      // last eager upload consumed the staging buffer
-  bool staged_pending = false;
+  // Argument slots (arg_bytes each, device slots in the workspace from off_args, pinned host
+  // copies in `pinned`): kGraphSlots for captured graphs, then kEagerSlots as a ring for eager
+  // runs.  slot_done[i] is recorded after the last launch that reads slot i.
+  char* pinned = nullptr;
+  hipEvent_t slot_done[kArgSlots] = {};
+  bool slot_used[kArgSlots] = {};
+  int eager_next = 0;
+  std::vector<std::pair<std::vector<uintptr_t>, int>> graph_slot;   // pointer set -> slot
   KernelTimer timer;
   GraphCache graphs;
-  std::vector<void*> graph_args;    // device argument blocks of cached graphs
 };
 
 namespace {
@@ -197,9 +206,15 @@ hipError_t enqueue_batch(of_batch* b, char* blk, float* const* u, float* const* 
   const ReduceJob* jobs = (const ReduceJob*)blk;
   const IterArgs* args =
       (const IterArgs*)(blk + align256(sizeof(ReduceJob) * 2 * (size_t)n * (L > 1 ? L - 1 : 0)));
+  hipEvent_t span = nullptr;
+  double span_units = 0, span_bytes = 0;
+  if (t && t->per_level() && L > 1) {
+    hipError_t e = t->begin(s, &span);
+    if (e != hipSuccess) return e;
+  }
   for (int l = 1; l < L; ++l) {
     hipEvent_t ev = nullptr;
-    hipError_t e = t ? t->begin(s, &ev) : hipSuccess;
+    hipError_t e = t && t->per_launch() ? t->begin(s, &ev) : hipSuccess;
     const int ni = b->nitems[l];
     if (e == hipSuccess)
       e = launch_reduce_batch(g0.elem(l - 1), g0.ep, jobs + (size_t)(l - 1) * 2 * n,
@@ -212,14 +227,25 @@ hipError_t enqueue_batch(of_batch* b, char* blk, float* const* u, float* const* 
         no += 2 * o;
         bytes += 2 * (i * elem_bytes(g0.elem(l - 1)) + o * elem_bytes(g0.ep));
       }
-      e = t->end(s, ev, OF_KERNEL_REDUCE, no, bytes);
+      if (t->per_launch()) e = t->end(s, ev, OF_KERNEL_REDUCE, no, bytes);
+      span_units += no;
+      span_bytes += bytes;
     }
+    if (e != hipSuccess) return e;
+  }
+  if (span) {
+    hipError_t e = t->end(s, span, OF_KERNEL_REDUCE, span_units, span_bytes, L - 1);
     if (e != hipSuccess) return e;
   }
   int phase = 0;
   for (int l = L - 1; l >= 0; --l) {
     double px = 0;
     for (int p = 0; p < n; ++p) px += (double)b->g[p].H[l] * b->g[p].W[l];
+    hipEvent_t lspan = nullptr;
+    if (t && t->per_level()) {
+      hipError_t e = t->begin(s, &lspan);
+      if (e != hipSuccess) return e;
+    }
     for (int k = 0; k < K; ++k, ++phase) {
       BatchLaunch bl;
       bl.args = args + (size_t)phase * n;
@@ -230,39 +256,51 @@ hipError_t enqueue_batch(of_batch* b, char* blk, float* const* u, float* const* 
       bl.variant = b->cfg[l].variant >= 0 ? b->cfg[l].variant : default_tile_variant(bl.ntiles);
       const int mode = k > 0 ? kFlowSame : (l == L - 1 ? kFlowZero : kFlowCoarse);
       hipEvent_t ev = nullptr;
-      hipError_t e = t ? t->begin(s, &ev) : hipSuccess;
+      hipError_t e = t && t->per_launch() ? t->begin(s, &ev) : hipSuccess;
       if (e == hipSuccess) e = launch_iter_batch(g0.elem(l), bl, b->R, mode, s);
-      if (e == hipSuccess && t)
+      if (e == hipSuccess && t && t->per_launch())
         e = t->end(s, ev, OF_KERNEL_ITERATE, px, px * (2.0 * elem_bytes(g0.elem(l)) + 16.0));
+      if (e != hipSuccess) return e;
+    }
+    if (lspan) {
+      hipError_t e = t->end(s, lspan, OF_KERNEL_LEVEL(l), px * K,
+                            px * K * (2.0 * elem_bytes(g0.elem(l)) + 16.0), K);
       if (e != hipSuccess) return e;
     }
   }
   return hipSuccess;
 }
 
-// Eager path: stage the argument block through pinned memory into the workspace copy.
+char* dev_slot(const of_batch* b, int i) { return b->ws + b->off_args + (size_t)i * b->arg_bytes; }
+char* host_slot(const of_batch* b, int i) { return b->pinned + (size_t)i * b->arg_bytes; }
+
+// Is slot i free for new arguments (no launch in flight reads it)?  hipErrorNotReady if busy.
+hipError_t slot_free(of_batch* b, int i) {
+  if (!b->slot_used[i]) return hipSuccess;
+  return hipEventQuery(b->slot_done[i]);
+}
+
+// Eager path: the arguments go through the next pinned slot of the eager ring into its device
+// slot; a slot still read by an earlier run makes the call return busy (hipErrorNotReady).
 hipError_t run_eager(of_batch* b, const void* const* I1, const void* const* I2, float* const* u,
                      float* const* v, hipStream_t s, KernelTimer* t) {
-  hipError_t e;
-  if (b->staged_pending) {
-    e = hipEventSynchronize(b->staged);
-    if (e != hipSuccess) return e;
-  }
-  fill_args(b, b->pinned, I1, I2, u, v);
-  char* blk = b->ws + b->off_args;
-  e = hipMemcpyAsync(blk, b->pinned, b->arg_bytes, hipMemcpyHostToDevice, s);
+  const int slot = kGraphSlots + b->eager_next;
+  hipError_t e = slot_free(b, slot);
   if (e != hipSuccess) return e;
-  e = hipEventRecord(b->staged, s);
+  fill_args(b, host_slot(b, slot), I1, I2, u, v);
+  e = hipMemcpyAsync(dev_slot(b, slot), host_slot(b, slot), b->arg_bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = enqueue_batch(b, dev_slot(b, slot), u, v, s, t);
+  if (e == hipSuccess) e = hipEventRecord(b->slot_done[slot], s);
   if (e != hipSuccess) return e;
-  b->staged_pending = true;
-  return enqueue_batch(b, blk, u, v, s, t);
+  b->slot_used[slot] = true;
+  b->eager_next = (b->eager_next + 1) % kEagerSlots;
+  return hipSuccess;
 }
 
 void drop_graphs(of_batch* b) {
   hipDeviceSynchronize();
   b->graphs.clear();
-  for (void* p : b->graph_args) hipFree(p);
-  b->graph_args.clear();
+  b->graph_slot.clear();
 }
 
 }  // namespace
@@ -285,7 +323,7 @@ size_t of_batch_workspace_bytes(int n, const int* H, const int* W, int levels, i
     tiles = std::max(tiles, tl);
     items += align256(it * sizeof(int2));
   }
-  return off + align256(tiles * sizeof(int4)) * levels + items + args_bytes(n, levels, iters);
+  return off + align256(tiles * sizeof(int4)) * levels + items + kArgSlots * args_bytes(n, levels, iters);
 }
 
 of_batch* of_batch_create(int n, const int* H, const int* W, int levels, int radius, int iters,
@@ -346,7 +384,7 @@ of_batch* of_batch_create(int n, const int* H, const int* W, int levels, int rad
   }
   b->off_args = off;
   b->arg_bytes = args_bytes(n, levels, iters);
-  off += b->arg_bytes;
+  off += kArgSlots * b->arg_bytes;
   if (off != need) {
     set_error("internal: workspace layout mismatch");
     delete b;
@@ -368,8 +406,10 @@ of_batch* of_batch_create(int n, const int* H, const int* W, int levels, int rad
   for (int l = 1; l < levels && e == hipSuccess; ++l)
     e = hipMemcpy(b->ws + b->items_at[l], items[l].data(), items[l].size() * sizeof(int2),
                   hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&b->pinned, b->arg_bytes, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&b->pinned, kArgSlots * b->arg_bytes, hipHostMallocDefault);
+  for (int i = 0; i < kArgSlots && e == hipSuccess; ++i)
+    e = hipEventCreateWithFlags(&b->slot_done[i], hipEventDisableTiming);
   if (e != hipSuccess) {
     hip_fail("batch set-up", e);
     of_batch_destroy(b);
@@ -402,22 +442,50 @@ of_status of_batch_compute(of_batch* b, const void* const* I1, const void* const
       key.push_back((uintptr_t)u[p]);
       key.push_back((uintptr_t)v[p]);
     }
-    char* blk = nullptr;
+    int slot = -1;
+    for (const auto& gs : b->graph_slot)
+      if (gs.first == key) slot = gs.second;
+    const bool fresh = slot < 0;
     e = hipSuccess;
-    if (!b->graphs.contains(key)) {
-      // A new pointer set: the graph gets its own argument block, uploaded before capture.
-      if (b->graphs.entries.size() >= b->graphs.max_entries) drop_graphs(b);
-      e = hipMalloc((void**)&blk, b->arg_bytes);
+    if (fresh) {
+      // A new pointer set: a free graph slot, else the least recently used graph's slot once
+      // its last replay has completed (the only wait of this call).
+      bool taken[kGraphSlots] = {};
+      for (const auto& gs : b->graph_slot) taken[gs.second] = true;
+      for (int i = 0; i < kGraphSlots && slot < 0; ++i)
+        if (!taken[i]) slot = i;
+      if (slot < 0 && b->graphs.entries.empty()) {   // only after failed captures
+        b->graph_slot.clear();
+        slot = 0;
+        e = hipEventSynchronize(b->slot_done[slot]);
+      }
+      if (slot < 0) {
+        const size_t lru = b->graphs.lru();
+        const std::vector<uintptr_t> old = b->graphs.entries[lru].key;
+        for (size_t i = 0; i < b->graph_slot.size(); ++i)
+          if (b->graph_slot[i].first == old) {
+            slot = b->graph_slot[i].second;
+            b->graph_slot.erase(b->graph_slot.begin() + i);
+            break;
+          }
+        e = hipEventSynchronize(b->slot_done[slot]);
+        if (e == hipSuccess) b->graphs.erase(lru);
+      }
       if (e == hipSuccess) {
-        b->graph_args.push_back(blk);
-        b->staging_host.resize(b->arg_bytes);
-        fill_args(b, b->staging_host.data(), I1, I2, u, v);
-        e = hipMemcpy(blk, b->staging_host.data(), b->arg_bytes, hipMemcpyHostToDevice);
+        fill_args(b, host_slot(b, slot), I1, I2, u, v);
+        e = hipMemcpyAsync(dev_slot(b, slot), host_slot(b, slot), b->arg_bytes,
+                           hipMemcpyHostToDevice, s);
       }
     }
+    char* blk = dev_slot(b, slot);
     if (e == hipSuccess)
       e = b->graphs.run(key, s, [&](hipStream_t cs) { return enqueue_batch(b, blk, u, v, cs, nullptr); });
+    if (e == hipSuccess && fresh) b->graph_slot.push_back({key, slot});
+    if (e == hipSuccess) e = hipEventRecord(b->slot_done[slot], s);
+    if (e == hipSuccess) b->slot_used[slot] = true;
   }
+  if (e == hipErrorNotReady)
+    return set_error("busy: every eager argument slot is read by a run still in flight"), OF_ESTATE;
   if (e != hipSuccess) return hip_fail("batch launch", e), OF_EHIP;
   return OF_OK;
 }
@@ -427,7 +495,8 @@ void of_batch_destroy(of_batch* b) {
   DeviceGuard guard(b->device);
   hipDeviceSynchronize();
   drop_graphs(b);
-  if (b->staged) hipEventDestroy(b->staged);
+  for (int i = 0; i < kArgSlots; ++i)
+    if (b->slot_done[i]) hipEventDestroy(b->slot_done[i]);
   if (b->pinned) hipHostFree(b->pinned);
   if (b->owns_ws) hipFree(b->ws);
   delete b;
@@ -435,14 +504,17 @@ void of_batch_destroy(of_batch* b) {
 
 of_status of_batch_set_timing(of_batch* b, int enable) {
   if (!b) return set_error("NULL batch"), OF_EINVAL;
+  if (enable < 0 || enable > OF_TIMING_LEVEL) return set_error("unknown timing mode"), OF_EINVAL;
   b->timer.on = enable != 0;
+  if (enable) b->timer.mode = enable;
   return OF_OK;
 }
 
 of_status of_batch_read_timing(of_batch* b, int kernel, double* total_ms, long long* launches,
                                double* units, double* bytes) {
   if (!b) return set_error("NULL batch"), OF_EINVAL;
-  if (kernel != OF_KERNEL_ITERATE && kernel != OF_KERNEL_REDUCE)
+  if (kernel != OF_KERNEL_ITERATE && kernel != OF_KERNEL_REDUCE &&
+      !(kernel >= OF_KERNEL_LEVEL(0) && kernel < OF_KERNEL_LEVEL(OF_MAX_LEVELS)))
     return set_error("unknown kernel id"), OF_EINVAL;
   DeviceGuard guard(b->device);
   hipError_t e = b->timer.read(kernel, total_ms, launches, units, bytes);
@@ -481,7 +553,9 @@ of_status of_batch_autotune(of_batch* b, const void* const* I1, const void* cons
   DeviceGuard guard(b->device);
   hipStream_t s = (hipStream_t)stream;
   const bool was_on = b->timer.on;
+  const int was_mode = b->timer.mode;
   b->timer.on = true;
+  b->timer.mode = OF_TIMING_LAUNCH;
   static const int kBands[] = {1, 2, 4, 8};
   static const int kGrid[] = {0, 256, 512, 1024, 2048};
   static const int kVariant[] = {kTileNarrow, kTileWide, kTileWideLean};
@@ -535,6 +609,7 @@ of_status of_batch_autotune(of_batch* b, const void* const* I1, const void* cons
     if (e == hipSuccess) e = upload_tiles(b);
   }
   b->timer.on = was_on;
+  b->timer.mode = was_mode;
   drop_graphs(b);
   if (e != hipSuccess) return hip_fail("autotune", e);
   return OF_OK;

@@ -29,6 +29,10 @@ struct IterArgs {
   const uint8_t* tiles; // with a mask, one flag per iteration tile: 0 = no unmasked output
                         // pixel, 1 = some masked pixels, 2 = no masked pixel
   float taps[kMaxTaps]; // Gaussian-weighted window: separable taps g[0..2r] (unused for the box)
+  // Recirculation-bubble count (eq. 3), final iteration of a plan only: when bcount is set,
+  // the launch adds to *bcount the number of written u values <= *bthr.
+  const float* bthr;
+  unsigned long long* bcount;
 };
 
 // Element access by an unsigned 32-bit element index whose byte offset is formed in 32 bits

@@ -167,12 +167,68 @@ __global__ __launch_bounds__(256) void count_kernel(const float* __restrict__ x,
   if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
 }
 
+__global__ __launch_bounds__(256) void count_dev_kernel(const float* __restrict__ x, long long n,
+                                                        const float* __restrict__ thr,
+                                                        unsigned long long* cnt) {
+  const float t = *thr;
+  unsigned long long c = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    c += x[i] <= t ? 1ull : 0ull;
+  c = wave_sum(c);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
+}
+
+// eq. 3 step, device side only.  mean <- mean + (u - mean) / (t + 1) (t = 0: mean <- u) with
+// the extremes of the new mean reduced into mm (ordered uints).
+__global__ __launch_bounds__(256) void mean_minmax_kernel(float* __restrict__ mean,
+                                                          const float* __restrict__ u, long long n,
+                                                          float inv, int first, unsigned* mm) {
+  float lo = INFINITY, hi = -INFINITY;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float m = first ? u[i] : fmaf(u[i] - mean[i], inv, mean[i]);
+    mean[i] = m;
+    lo = fminf(lo, m);
+    hi = fmaxf(hi, m);
+  }
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&mm[0], ordered(lo));
+    atomicMax(&mm[1], ordered(hi));
+  }
+}
+
+// surface <- count / n (when `surface_first` is 0: before the threshold moves), threshold <-
+// (min + max) / 2 of the new mean; the min/max work cells are reset for the next call.
+__global__ void bubble_finish_kernel(unsigned* mm, float* thr, const unsigned long long* cnt,
+                                     long long n, float* surface) {
+  if (threadIdx.x == 0) {
+    if (surface && cnt) *surface = (float)((double)*cnt / (double)n);
+    *thr = 0.5f * (unordered(mm[0]) + unordered(mm[1]));
+    mm[0] = 0xffffffffu;
+    mm[1] = 0u;
+  }
+}
+
+__global__ void bubble_surface_kernel(const unsigned long long* cnt, long long n, float* surface) {
+  if (threadIdx.x == 0) *surface = (float)((double)*cnt / (double)n);
+}
+
 unsigned grid_for(long long n) {
   const long long b = (n + 255) / 256;
   return (unsigned)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
 }
 
 }  // namespace
+
+hipError_t launch_count_at_most(const float* x, long long n, const float* thr,
+                                unsigned long long* c, hipStream_t s) {
+  hipLaunchKernelGGL(stats_init_kernel, dim3(1), dim3(64), 0, s, (unsigned*)nullptr, c);
+  hipLaunchKernelGGL(count_dev_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, thr, c);
+  return hipGetLastError();
+}
 
 hipError_t launch_normalize(Elem t, const void* in, float* out, int H, int W, int r, float eps,
                             hipStream_t s) {
@@ -237,6 +293,31 @@ of_status of_field_minmax(const float* x, long long n, float* out2, void* work, 
   hipLaunchKernelGGL(minmax_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, mm);
   hipLaunchKernelGGL(minmax_finish_kernel, dim3(1), dim3(64), 0, s, mm, out2);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(hipGetErrorString(e)), OF_EHIP;
+  return OF_OK;
+}
+
+of_status of_bubble_step(float* mean, const float* u, long long n, int t,
+                         unsigned long long* count, float* threshold, float* surface, void* work,
+                         void* stream) {
+  if (!mean || !u || !count || !threshold || !surface || !work || n < 1 || t < 0)
+    return set_error("bad argument"), OF_EINVAL;
+  if (((uintptr_t)work & 3) || ((uintptr_t)count & 7)) return set_error("misaligned work or count"), OF_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned* mm = (unsigned*)work;
+  hipLaunchKernelGGL(stats_init_kernel, dim3(1), dim3(64), 0, s, mm, (unsigned long long*)nullptr);
+  if (t > 0)   // count holds u <= the threshold in force while u was computed
+    hipLaunchKernelGGL(bubble_surface_kernel, dim3(1), dim3(64), 0, s, count, n, surface);
+  hipLaunchKernelGGL(mean_minmax_kernel, dim3(grid_for(n)), dim3(256), 0, s, mean, u, n,
+                     1.0f / (float)(t + 1), t == 0 ? 1 : 0, mm);
+  hipLaunchKernelGGL(bubble_finish_kernel, dim3(1), dim3(64), 0, s, mm, threshold,
+                     (const unsigned long long*)nullptr, n, (float*)nullptr);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && t == 0) {   // the first field against its own threshold
+    e = launch_count_at_most(u, n, threshold, count, s);
+    if (e == hipSuccess) hipLaunchKernelGGL(bubble_surface_kernel, dim3(1), dim3(64), 0, s, count, n, surface);
+    if (e == hipSuccess) e = hipGetLastError();
+  }
   if (e != hipSuccess) return set_error(hipGetErrorString(e)), OF_EHIP;
   return OF_OK;
 }

@@ -114,4 +114,11 @@ hipError_t launch_normalize(Elem t, const void* in, float* out, int H, int W, in
 // u = v = 0 over n elements (a fill kernel, safe under stream capture).
 hipError_t launch_zero(float* u, float* v, size_t n, hipStream_t s);
 
+// *c = 0 (a one-thread kernel, safe under stream capture).
+hipError_t launch_zero_count(unsigned long long* c, hipStream_t s);
+
+// *c = number of x[i] <= *thr over n elements (the threshold read on the device).
+hipError_t launch_count_at_most(const float* x, long long n, const float* thr,
+                                unsigned long long* c, hipStream_t s);
+
 }  // namespace ofmi

@@ -48,6 +48,17 @@ hipError_t launch_iter_batch(Elem t, const BatchLaunch& b, int R, int mode, hipS
   return hipErrorInvalidValue;
 }
 
+namespace {
+__global__ void zero_count_kernel(unsigned long long* c) {
+  if (threadIdx.x == 0) *c = 0ull;
+}
+}  // namespace
+
+hipError_t launch_zero_count(unsigned long long* c, hipStream_t s) {
+  hipLaunchKernelGGL(zero_count_kernel, dim3(1), dim3(64), 0, s, c);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(float* u, float* v, size_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const size_t blocks = (n + 255) / 256;

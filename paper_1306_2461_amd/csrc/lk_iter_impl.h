@@ -33,6 +33,13 @@ namespace ofmi {
 
 namespace {
 
+// Adds every lane's count to *dst: a wave sum, then one atomic per wave.
+__device__ __forceinline__ void add_count(unsigned long long* dst, unsigned c) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(dst, (unsigned long long)c);
+}
+
 template <int R, int TW_, bool WIDE = false, int BB = 1>
 struct Cfg {
   static constexpr int N = 2 * R + 1;                 // band height = window height
@@ -97,6 +104,7 @@ constexpr bool field_ring() {
 // GAUSS: window sums weighted by the separable taps a.taps[0..2r] (Gaussian-weighted window)
 // instead of the unweighted box: every horizontal and vertical sum is a direct 2r+1-term
 // weighted sum in a fixed order, so results remain independent of the tiling.
+// BUB: the launch may carry the eq. 3 count (plain launches; checked at run time there).
 // BB: bands per pass.  With BB = 2 the phases run over two bands' rows at once with twice the
 // threads, so a tile of two bands (one output band and the band that primes the vertical
 // sums) is one pass of the dependent path instead of two; P4 walks the two bands in order,
@@ -107,7 +115,7 @@ constexpr bool field_ring() {
 // ring rows while slower threads are still in P5: it writes rows tb+N+1 .. tb+2N while P5
 // reads rows tb-R .. tb+R, at most 5R+2 < FRING apart, so no slot is shared.
 template <typename T, int R, int TW, int MODE, bool WIDE, bool DEFER, bool INTERIOR, bool LEAN,
-          bool GAUSS = false, int BB = 1, bool FR = false>
+          bool GAUSS = false, int BB = 1, bool FR = false, bool BUB = false>
 __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands, int bx, int by,
                                            bool pixel_mask, float4* sm4) {
   using C = Cfg<R, TW, WIDE, BB>;
@@ -141,6 +149,11 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
 #pragma unroll
   for (int i = 0; i < N; ++i) prev[i] = 0.f;
 
+  // eq. 3 count of the final iteration: u values at or below the threshold written by this
+  // thread (one atomic per wave at the end)
+  const bool bub = BUB && a.bcount != nullptr;
+  const float bthr = bub ? at(a.bthr, 0u) : 0.f;
+  unsigned bcnt = 0;
   for (int b = 0; b < nbands; b += BB) {
     const int tb = N * b;                        // first product row of the pass
     // LEAN: the thread index is re-materialised per band, opaque to the optimiser, so the
@@ -301,11 +314,16 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
       const int i = tid + k * NT;
       if (i < 5 * NR * C::NSEG) {
         const int seg = i % C::NSEG, rr = i / C::NSEG;   // rr = ch * NR + row
-        const float4* src = reinterpret_cast<const float4*>(pr + rr * PP + 8 * seg);
+        typedef float f4v __attribute__((ext_vector_type(4)));
+        const f4v* src = reinterpret_cast<const f4v*>(pr + rr * PP + 8 * seg);
         float vbuf[4 * C::HL4];
 #pragma unroll
         for (int q = 0; q < C::HL4; ++q) {
-          const float4 f = src[q];
+          // The empty asm takes the four values as one 128-bit register operand, so each read
+          // stays one 128-bit LDS load (the sums below use the values out of order, and the
+          // loads were otherwise split into 32-bit pairs).
+          f4v f = src[q];
+          asm volatile("" : "+v"(f));
           vbuf[4 * q] = f.x;
           vbuf[4 * q + 1] = f.y;
           vbuf[4 * q + 2] = f.z;
@@ -325,9 +343,9 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
           // values inside the window only.  (A running sum that subtracts the value leaving
           // the window carries a rounding error relative to the largest product of the
           // segment rather than of the window, which ill-conditioned windows amplify.)
-          float suf = vbuf[2 * R];
+          float suf = vbuf[7];   // vbuf[7..2R], in load order
 #pragma unroll
-          for (int q = 2 * R - 1; q >= 7; --q) suf = vbuf[q] + suf;
+          for (int q = 8; q <= 2 * R; ++q) suf += vbuf[q];
           float sj[8];
           sj[7] = suf;
 #pragma unroll
@@ -438,12 +456,18 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
           }
           at(a.uout, o) = un;
           at(a.vout, o) = vn;
+          if constexpr (BUB) {
+            if (bub) bcnt += un <= bthr ? 1u : 0u;
+          }
         }
       }
     }
     // The next pass's P1 writes only warped rows that this pass's P2 finished reading before
     // the barriers above; its P2 rewrites the product/window-sum buffer after the P1 barrier,
     // when every thread has finished this pass's P5.
+  }
+  if constexpr (BUB) {
+    if (bub) add_count(a.bcount, bcnt);
   }
 }
 
@@ -459,7 +483,8 @@ __device__ __forceinline__ bool tile_interior(const IterArgs& a, int TH, int nba
 }
 
 // Masked plans: a tile without an unmasked output pixel (TW columns from x0, TH rows from
-// y0) is not computed; its workgroup writes zero flow over it.
+// y0) is not computed; its workgroup writes zero flow over it (and counts those zeros for the
+// eq. 3 count when the threshold is not negative).
 template <int TW>
 __device__ __forceinline__ void zero_tile(const IterArgs& a, int TH, int bx, int by) {
   const int x0 = bx * TW, y0 = by * TH;
@@ -470,6 +495,8 @@ __device__ __forceinline__ void zero_tile(const IterArgs& a, int TH, int bx, int
     at(a.uout, o) = 0.f;
     at(a.vout, o) = 0.f;
   }
+  if (a.bcount != nullptr && threadIdx.x == 0 && 0.f <= at(a.bthr, 0u))
+    atomicAdd(a.bcount, (unsigned long long)w * (unsigned long long)h);
 }
 
 // Workgroup index -> work index so that the workgroups one XCD runs (hardware dispatch is
@@ -500,11 +527,11 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW * BB) void lk_iter_strip(IterA
   constexpr bool kDefer = WIDE || R > 8;
   constexpr bool kFR = field_ring<MODE, WIDE, LEAN, BB>();
   if (R <= 8 && tile_interior<R, TW>(a, TH, nbands, bx, by))
-    strip_tile<T, R, TW, MODE, WIDE, kDefer, true, LEAN, GAUSS, BB, kFR>(a, TH, nbands, bx, by,
-                                                                         pixel_mask, sm4);
+    strip_tile<T, R, TW, MODE, WIDE, kDefer, true, LEAN, GAUSS, BB, kFR, true>(a, TH, nbands, bx,
+                                                                               by, pixel_mask, sm4);
   else
-    strip_tile<T, R, TW, MODE, WIDE, kDefer, false, LEAN, GAUSS, BB, kFR>(a, TH, nbands, bx, by,
-                                                                          pixel_mask, sm4);
+    strip_tile<T, R, TW, MODE, WIDE, kDefer, false, LEAN, GAUSS, BB, kFR, true>(a, TH, nbands, bx,
+                                                                                by, pixel_mask, sm4);
 }
 
 // Batched form: workgroups stride over a work list of tiles of many pairs at the same

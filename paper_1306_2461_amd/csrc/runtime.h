@@ -27,22 +27,31 @@ struct Geometry {
   int variant[OF_MAX_LEVELS];       // tile variant of the iteration kernel (TileVariant)
   const uint8_t* mask[OF_MAX_LEVELS];   // per-level masks (of_plan_set_mask) or nullptr
   const uint8_t* tflags[OF_MAX_LEVELS]; // per-level iteration-tile flags (with a mask)
+  const float* bthr;                // eq. 3 count of the final field (of_plan_set_bubble)
+  unsigned long long* bcount;
   size_t bytes;
   Elem elem(int l) const;
 };
 
-// Optional per-launch event timing (of_plan_set_timing / of_plan_read_timing).
+// Optional event timing (of_plan_set_timing / of_plan_read_timing): one event pair around
+// every launch (mode OF_TIMING_LAUNCH), or around the pyramid launches and around each level's
+// iteration launches (OF_TIMING_LEVEL: no events between the launches of a span).
 struct KernelTimer {
   struct Rec {
     int kernel;
     hipEvent_t a, b;
     double units, bytes;
+    long long launches;
   };
   bool on = false;
+  int mode = OF_TIMING_LAUNCH;
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
+  bool per_launch() const { return on && mode == OF_TIMING_LAUNCH; }
+  bool per_level() const { return on && mode == OF_TIMING_LEVEL; }
   hipError_t begin(hipStream_t s, hipEvent_t* a);
-  hipError_t end(hipStream_t s, hipEvent_t a, int kernel, double units, double bytes);
+  hipError_t end(hipStream_t s, hipEvent_t a, int kernel, double units, double bytes,
+                 long long launches = 1);
   hipError_t read(int kernel, double* ms, long long* n, double* units, double* bytes);
   ~KernelTimer();
 };
@@ -65,6 +74,18 @@ struct GraphCache {
     for (const Entry& e : entries)
       if (e.key == key) return true;
     return false;
+  }
+  // Index of the least recently used entry (entries must not be empty).
+  size_t lru() const {
+    size_t i = 0;
+    for (size_t j = 1; j < entries.size(); ++j)
+      if (entries[j].used < entries[i].used) i = j;
+    return i;
+  }
+  // Drops entry i (the caller has made sure no replay of it is still in flight).
+  void erase(size_t i) {
+    hipGraphExecDestroy(entries[i].exec);
+    entries.erase(entries.begin() + i);
   }
   void clear();
   ~GraphCache();

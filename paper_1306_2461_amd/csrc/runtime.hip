@@ -127,7 +127,8 @@ hipError_t KernelTimer::begin(hipStream_t s, hipEvent_t* a) {
   return hipEventRecord(*a, s);
 }
 
-hipError_t KernelTimer::end(hipStream_t s, hipEvent_t a, int kernel, double units, double bytes) {
+hipError_t KernelTimer::end(hipStream_t s, hipEvent_t a, int kernel, double units, double bytes,
+                            long long launches) {
   if (!on || !a) return hipSuccess;
   hipEvent_t b;
   if (pool.empty()) {
@@ -137,7 +138,7 @@ hipError_t KernelTimer::end(hipStream_t s, hipEvent_t a, int kernel, double unit
     b = pool.back();
     pool.pop_back();
   }
-  recs.push_back({kernel, a, b, units, bytes});
+  recs.push_back({kernel, a, b, units, bytes, launches});
   return hipEventRecord(b, s);
 }
 
@@ -158,7 +159,7 @@ hipError_t KernelTimer::read(int kernel, double* ms, long long* n, double* units
     tms += f;
     tu += r.units;
     tb += r.bytes;
-    ++cnt;
+    cnt += r.launches;
     pool.push_back(r.a);
     pool.push_back(r.b);
   }
@@ -204,7 +205,15 @@ int window_variant(const Geometry& g, int l, IterArgs& a) {
 hipError_t enqueue_pair(const Geometry& g, char* ws, const void* I1, const void* I2, float* u,
                         float* v, hipStream_t s, KernelTimer* t) {
   const size_t n0 = (size_t)g.H[0] * g.W[0];
-  if (g.K == 0) return launch_zero(u, v, n0, s);
+  if (g.bcount) {
+    hipError_t e = launch_zero_count(g.bcount, s);
+    if (e != hipSuccess) return e;
+  }
+  if (g.K == 0) {
+    hipError_t e = launch_zero(u, v, n0, s);
+    if (e == hipSuccess && g.bcount) e = launch_count_at_most(u, (long long)n0, g.bthr, g.bcount, s);
+    return e;
+  }
   const void* P1[OF_MAX_LEVELS];
   const void* P2[OF_MAX_LEVELS];
   P1[0] = I1;
@@ -226,11 +235,18 @@ hipError_t enqueue_pair(const Geometry& g, char* ws, const void* I1, const void*
   }
   // Pyramid: runs of 2 or 3 levels whose first output plane has at most 2^20 pixels take one
   // fused chain launch each, other levels one reduction each (identical bits either way).
+  hipEvent_t span = nullptr;
+  double span_units = 0, span_bytes = 0;
+  long long span_launches = 0;
+  if (t && t->per_level() && g.L > 1) {
+    hipError_t e = t->begin(s, &span);
+    if (e != hipSuccess) return e;
+  }
   for (int l = 1; l < g.L;) {
     const int rest = g.L - l;
     const int D = (rest >= 2 && (long long)g.H[l] * g.W[l] <= (1ll << 20)) ? (rest >= 3 ? 3 : 2) : 1;
     hipEvent_t ev;
-    hipError_t e = t ? t->begin(s, &ev) : hipSuccess;
+    hipError_t e = t && t->per_launch() ? t->begin(s, &ev) : hipSuccess;
     if (e == hipSuccess) {
       if (D == 1) {
         e = launch_reduce(g.elem(l - 1), g.ep, P1[l - 1], P2[l - 1], g.H[l - 1], g.W[l - 1],
@@ -256,11 +272,18 @@ hipError_t enqueue_pair(const Geometry& g, char* ws, const void* I1, const void*
       double no = 0;
       for (int d = 0; d < D; ++d) no += (double)g.H[l + d] * g.W[l + d];
       const double ni = (double)g.H[l - 1] * g.W[l - 1];
-      e = t->end(s, ev, OF_KERNEL_REDUCE, 2 * no,
-                 2 * (ni * elem_bytes(g.elem(l - 1)) + no * elem_bytes(g.ep)));
+      const double by = 2 * (ni * elem_bytes(g.elem(l - 1)) + no * elem_bytes(g.ep));
+      if (t->per_launch()) e = t->end(s, ev, OF_KERNEL_REDUCE, 2 * no, by);
+      span_units += 2 * no;
+      span_bytes += by;
+      ++span_launches;
     }
     if (e != hipSuccess) return e;
     l += D;
+  }
+  if (span) {
+    hipError_t e = t->end(s, span, OF_KERNEL_REDUCE, span_units, span_bytes, span_launches);
+    if (e != hipSuccess) return e;
   }
   float* fu[2] = {(float*)(ws + g.off_flow[0]), (float*)(ws + g.off_flow[1])};
   float* fv[2] = {(float*)(ws + g.off_flow[2]), (float*)(ws + g.off_flow[3])};
@@ -268,6 +291,11 @@ hipError_t enqueue_pair(const Geometry& g, char* ws, const void* I1, const void*
   const float* cv = nullptr;
   int cH = 0, cW = 0, buf = 0;
   for (int l = g.L - 1; l >= 0; --l) {
+    hipEvent_t lspan = nullptr;
+    if (t && t->per_level()) {
+      hipError_t e = t->begin(s, &lspan);
+      if (e != hipSuccess) return e;
+    }
     for (int k = 0; k < g.K; ++k) {
       IterArgs a{};
       a.I1 = P1[l];
@@ -284,11 +312,15 @@ hipError_t enqueue_pair(const Geometry& g, char* ws, const void* I1, const void*
       const bool last = (l == 0 && k == g.K - 1);
       a.uout = last ? u : fu[buf];
       a.vout = last ? v : fv[buf];
+      if (last) {
+        a.bthr = g.bthr;
+        a.bcount = g.bcount;
+      }
       hipEvent_t ev;
-      hipError_t e = t ? t->begin(s, &ev) : hipSuccess;
+      hipError_t e = t && t->per_launch() ? t->begin(s, &ev) : hipSuccess;
       const int variant = window_variant(g, l, a);
       if (e == hipSuccess) e = launch_iter(g.elem(l), a, g.R, g.nb[l], variant, s);
-      if (e == hipSuccess && t) {
+      if (e == hipSuccess && t && t->per_launch()) {
         const double n = (double)a.H * a.W;
         e = t->end(s, ev, OF_KERNEL_ITERATE, n, n * (2.0 * elem_bytes(g.elem(l)) + 16.0));
       }
@@ -298,6 +330,12 @@ hipError_t enqueue_pair(const Geometry& g, char* ws, const void* I1, const void*
       cH = a.H;
       cW = a.W;
       buf ^= 1;
+    }
+    if (lspan) {
+      const double n = (double)g.H[l] * g.W[l] * g.K;
+      hipError_t e = t->end(s, lspan, OF_KERNEL_LEVEL(l), n,
+                            n * (2.0 * elem_bytes(g.elem(l)) + 16.0), g.K);
+      if (e != hipSuccess) return e;
     }
   }
   return hipSuccess;
@@ -584,6 +622,20 @@ int of_levels_for_displacement(float dmax, int H, int W) {
   return L;
 }
 
+of_status of_plan_set_bubble(of_plan* p, const float* threshold, unsigned long long* count) {
+  if (!p) return set_error("NULL plan"), OF_EINVAL;
+  if ((threshold == nullptr) != (count == nullptr))
+    return set_error("threshold and count are set or removed together"), OF_EINVAL;
+  if (((uintptr_t)threshold & 3) || ((uintptr_t)count & 7))
+    return set_error("misaligned threshold or count"), OF_EINVAL;
+  DeviceGuard guard(p->device);
+  hipDeviceSynchronize();   // captured schedules hold the old pointers
+  p->graphs.clear();
+  p->g.bthr = threshold;
+  p->g.bcount = count;
+  return OF_OK;
+}
+
 of_status of_plan_get_config(const of_plan* p, int* bands, int* variant) {
   if (!p || !bands || !variant) return set_error("NULL argument"), OF_EINVAL;
   for (int l = 0; l < p->g.L; ++l) {
@@ -624,7 +676,9 @@ of_status of_plan_autotune(of_plan* p, const void* I1, const void* I2, float* u,
   hipStream_t s = (hipStream_t)stream;
   Geometry& g = p->g;
   const bool was_on = p->timer.on;
+  const int was_mode = p->timer.mode;
   p->timer.on = true;
+  p->timer.mode = OF_TIMING_LAUNCH;
   static const int kBands[] = {1, 2, 3, 4, 8};
   hipError_t e = hipSuccess;
   for (int l = 0; l < g.L && e == hipSuccess && g.K > 0; ++l) {
@@ -675,6 +729,7 @@ of_status of_plan_autotune(of_plan* p, const void* I1, const void* I2, float* u,
     if (e == hipSuccess && g.mask[l]) e = upload_tile_flags(p, l);
   }
   p->timer.on = was_on;
+  p->timer.mode = was_mode;
   hipDeviceSynchronize();
   p->graphs.clear();
   if (e != hipSuccess) return hip_fail("autotune", e);
@@ -683,14 +738,17 @@ of_status of_plan_autotune(of_plan* p, const void* I1, const void* I2, float* u,
 
 of_status of_plan_set_timing(of_plan* p, int enable) {
   if (!p) return set_error("NULL plan"), OF_EINVAL;
+  if (enable < 0 || enable > OF_TIMING_LEVEL) return set_error("unknown timing mode"), OF_EINVAL;
   p->timer.on = enable != 0;
+  if (enable) p->timer.mode = enable;
   return OF_OK;
 }
 
 of_status of_plan_read_timing(of_plan* p, int kernel, double* total_ms, long long* launches,
                               double* units, double* bytes) {
   if (!p) return set_error("NULL plan"), OF_EINVAL;
-  if (kernel != OF_KERNEL_ITERATE && kernel != OF_KERNEL_REDUCE)
+  if (kernel != OF_KERNEL_ITERATE && kernel != OF_KERNEL_REDUCE &&
+      !(kernel >= OF_KERNEL_LEVEL(0) && kernel < OF_KERNEL_LEVEL(OF_MAX_LEVELS)))
     return set_error("unknown kernel id"), OF_EINVAL;
   DeviceGuard guard(p->device);
   hipError_t e = p->timer.read(kernel, total_ms, launches, units, bytes);

@@ -3,13 +3,22 @@
 // field needs only one new image processed).  A server admits streams against an HBM budget
 // and pushes the new frames of many streams together: one batched launch per pyramid step
 // and per (level, iteration) phase over the tiles of every stream in the push.
+//
+// A push's launch arguments (pyramid jobs, per-session iteration arguments, tile lists) are
+// packed on the host into one of kRing pinned staging slots, copied to the matching device
+// slot on the push's stream and read by the kernels there.  Slots are sized when a session
+// opens, for a push of every open session, so a push never allocates; a slot is reused only
+// once the event recorded after its push's last launch has completed, and a push that finds
+// its slot still in flight returns OF_ESTATE instead of waiting.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/ofmi.h"
@@ -38,6 +47,8 @@ of_status hip_fail(const char* what, hipError_t e) {
   return OF_EHIP;
 }
 
+constexpr int kRing = OF_SERVER_RING;   // staging slots per server (pushes in flight at once)
+
 }  // namespace
 
 struct of_server;
@@ -45,14 +56,14 @@ struct of_server;
 struct of_session {
   of_server* server = nullptr;
   int H = 0, W = 0;
-  Geometry g;                     // level sizes; flow offsets are relative to `flow`
-  char* mem = nullptr;            // slots and flow planes (server allocation)
+  Geometry g;                     // level sizes
+  char* mem = nullptr;            // slots and flow planes
+  bool owns_mem = false;          // allocated by the library (else caller workspace)
   size_t bytes = 0;
   size_t slot_off[2][OF_MAX_LEVELS];  // pyramid planes of the two frame slots
   char* flow = nullptr;           // four level-0 FP32 planes
   int cur = 0;                    // slot that receives the next frame
   bool has_prev = false;
-  bool closed = false;
 };
 
 struct of_server {
@@ -61,14 +72,15 @@ struct of_server {
   int device = 0;
   size_t budget = 0;
   size_t resident = 0;
+  bool hidden = false;            // created for of_session_create (no budget)
   std::vector<of_session*> sessions;
-  // per-push argument block (grown on demand) and its pinned staging
-  char* blk = nullptr;
-  size_t blk_bytes = 0;
-  char* pinned = nullptr;
-  size_t pinned_bytes = 0;
-  hipEvent_t staged = nullptr;
-  bool staged_pending = false;
+  // staging ring: kRing device and pinned host slots of slot_bytes each
+  char* dev_blk = nullptr;
+  char* host_blk = nullptr;
+  size_t slot_bytes = 0;
+  hipEvent_t done[kRing] = {};
+  bool in_use[kRing] = {};
+  int next = 0;
   std::mutex mu;
 };
 
@@ -89,7 +101,7 @@ size_t session_bytes(int H, int W, int L, int R, int K, unsigned flags, Geometry
   return off;
 }
 
-// Host-side description of one push, packed into one argument block.
+// Host-side description of one push, packed into one staging slot.
 struct Push {
   std::vector<std::vector<ReduceJob>> jobs;   // per output level 1..L-1
   std::vector<std::vector<int2>> items;
@@ -127,47 +139,67 @@ void pack(const Push& p, char* dst) {
 // Tile height (bands) of a push level: taller tiles when many pixels fill the device.
 int push_bands(long long px) { return px >= (24ll << 20) ? 4 : (px >= (4ll << 20) ? 2 : 1); }
 
-}  // namespace
-
-extern "C" {
-
-size_t of_session_bytes(int H, int W, int levels, int radius, int iters, unsigned flags) {
-  if (!check_params(H, W, levels, radius, iters, flags)) return 0;
-  if (flags & (OF_FLAG_NORMALIZE | OF_FLAG_GAUSSIAN_WINDOW | OF_FLAG_GRAPH))
-    return set_error("OF_FLAG_NORMALIZE, OF_FLAG_GAUSSIAN_WINDOW and OF_FLAG_GRAPH apply to plans only"), 0;
-  return session_bytes(H, W, levels, radius, iters, flags, nullptr, nullptr, nullptr);
-}
-
-of_server* of_server_create(int levels, int radius, int iters, unsigned flags,
-                            size_t hbm_budget_bytes) {
-  if (flags & OF_FLAG_NO_GRAPH) flags &= ~OF_FLAG_NO_GRAPH;
-  if (flags & OF_FLAG_NORMALIZE) return set_error("OF_FLAG_NORMALIZE applies to plans only"), nullptr;
-  if (flags & OF_FLAG_GAUSSIAN_WINDOW)
-    return set_error("OF_FLAG_GAUSSIAN_WINDOW applies to plans only"), nullptr;
-  if (flags & OF_FLAG_GRAPH) return set_error("OF_FLAG_GRAPH applies to plans only"), nullptr;
-  if (!check_params(1 << (levels > 0 ? levels - 1 : 0), 1 << (levels > 0 ? levels - 1 : 0), levels,
-                    radius, iters, flags))
-    return nullptr;
-  of_server* s = new of_server();
-  s->L = levels;
-  s->R = radius;
-  s->K = iters;
-  s->flags = flags;
-  s->budget = hbm_budget_bytes;
-  hipError_t e = hipGetDevice(&s->device);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->staged, hipEventDisableTiming);
-  if (e != hipSuccess) {
-    hip_fail("server set-up", e);
-    delete s;
-    return nullptr;
+// Upper bound of the staging bytes of a push of every session in `ss` (all flowing, one-band
+// tiles, every array padded to 256 bytes): a push of any subset packs into fewer bytes.
+size_t push_bound(const std::vector<of_session*>& ss, int L, int R, int K) {
+  const int TW = strip_width_for(R), N = 2 * R + 1;
+  const size_t n = ss.size();
+  size_t b = 0;
+  for (int l = 1; l < L; ++l) {
+    size_t items = 0;
+    for (const of_session* x : ss) items += reduce_blocks(x->g.H[l], x->g.W[l]);
+    b += align256(n * sizeof(ReduceJob)) + align256(items * sizeof(int2));
   }
-  return s;
+  b += (size_t)L * (K > 0 ? K : 0) * align256(n * sizeof(IterArgs));
+  for (int l = 0; l < L; ++l) {
+    size_t tiles = 0;
+    for (const of_session* x : ss)
+      tiles += (size_t)((x->g.W[l] + TW - 1) / TW) * ((x->g.H[l] + N - 1) / N);
+    b += align256(tiles * sizeof(int4));
+  }
+  return b;
 }
 
-size_t of_server_resident_bytes(const of_server* s) { return s ? s->resident : 0; }
+void free_ring(of_server* s) {
+  if (s->dev_blk) hipFree(s->dev_blk);
+  if (s->host_blk) hipHostFree(s->host_blk);
+  s->dev_blk = nullptr;
+  s->host_blk = nullptr;
+  s->slot_bytes = 0;
+  for (int i = 0; i < kRing; ++i) s->in_use[i] = false;
+}
 
-of_session* of_server_open(of_server* s, int H, int W) {
-  if (!s) return set_error("NULL server"), nullptr;
+// Grows the staging ring to `need` bytes per slot (set-up calls only: waits for the device,
+// since pushes in flight read the old slots).
+hipError_t reserve_ring(of_server* s, size_t need) {
+  if (need <= s->slot_bytes) return hipSuccess;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return e;
+  free_ring(s);
+  const size_t sb = align256(need + need / 4);
+  e = hipMalloc((void**)&s->dev_blk, sb * kRing);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->host_blk, sb * kRing, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    free_ring(s);
+    return e;
+  }
+  s->slot_bytes = sb;
+  return hipSuccess;
+}
+
+bool check_server_flags(unsigned flags) {
+  if (flags & OF_FLAG_NORMALIZE) return set_error("OF_FLAG_NORMALIZE applies to plans only"), false;
+  if (flags & OF_FLAG_GAUSSIAN_WINDOW)
+    return set_error("OF_FLAG_GAUSSIAN_WINDOW applies to plans only"), false;
+  if (flags & OF_FLAG_GRAPH) return set_error("OF_FLAG_GRAPH applies to plans only"), false;
+  return true;
+}
+
+// Servers behind of_session_create, one per (device, levels, radius, iters, flags).
+std::mutex g_hidden_mu;
+std::map<std::tuple<int, int, int, int, unsigned>, of_server*> g_hidden;
+
+of_session* open_session(of_server* s, int H, int W, void* workspace, size_t workspace_bytes) {
   if (!check_params(H, W, s->L, s->R, s->K, s->flags)) return nullptr;
   std::lock_guard<std::mutex> lock(s->mu);
   of_session* ss = new of_session();
@@ -179,20 +211,104 @@ of_session* of_server_open(of_server* s, int H, int W) {
     delete ss;
     return nullptr;
   }
-  DeviceGuard guard(s->device);
-  hipError_t e = hipMalloc((void**)&ss->mem, ss->bytes);
-  if (e != hipSuccess) {
-    hip_fail("hipMalloc(session)", e);
-    delete ss;
-    return nullptr;
+  if (workspace) {
+    if (workspace_bytes < ss->bytes) {
+      set_error("workspace smaller than of_session_bytes()");
+      delete ss;
+      return nullptr;
+    }
+    if ((uintptr_t)workspace & 255) {
+      set_error("workspace must be 256-byte aligned");
+      delete ss;
+      return nullptr;
+    }
   }
+  DeviceGuard guard(s->device);
   ss->server = s;
   ss->H = H;
   ss->W = W;
+  std::vector<of_session*> all = s->sessions;
+  all.push_back(ss);
+  hipError_t e = reserve_ring(s, push_bound(all, s->L, s->R, s->K));
+  if (e != hipSuccess) {
+    hip_fail("staging ring", e);
+    delete ss;
+    return nullptr;
+  }
+  if (workspace) {
+    ss->mem = (char*)workspace;
+  } else {
+    e = hipMalloc((void**)&ss->mem, ss->bytes);
+    if (e != hipSuccess) {
+      hip_fail("hipMalloc(session)", e);
+      delete ss;
+      return nullptr;
+    }
+    ss->owns_mem = true;
+  }
   ss->flow = ss->mem + flow_off;
   s->resident += ss->bytes;
   s->sessions.push_back(ss);
   return ss;
+}
+
+void destroy_server(of_server* s) {
+  DeviceGuard guard(s->device);
+  hipDeviceSynchronize();
+  for (of_session* ss : s->sessions) {
+    if (ss->owns_mem) hipFree(ss->mem);
+    delete ss;
+  }
+  free_ring(s);
+  for (int i = 0; i < kRing; ++i)
+    if (s->done[i]) hipEventDestroy(s->done[i]);
+  delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t of_session_bytes(int H, int W, int levels, int radius, int iters, unsigned flags) {
+  if (!check_params(H, W, levels, radius, iters, flags)) return 0;
+  if (!check_server_flags(flags & ~OF_FLAG_NO_GRAPH)) return 0;
+  return session_bytes(H, W, levels, radius, iters, flags, nullptr, nullptr, nullptr);
+}
+
+of_server* of_server_create(int levels, int radius, int iters, unsigned flags,
+                            size_t hbm_budget_bytes) {
+  flags &= ~OF_FLAG_NO_GRAPH;
+  if (!check_server_flags(flags)) return nullptr;
+  if (!check_params(1 << (levels > 0 ? levels - 1 : 0), 1 << (levels > 0 ? levels - 1 : 0), levels,
+                    radius, iters, flags))
+    return nullptr;
+  of_server* s = new of_server();
+  s->L = levels;
+  s->R = radius;
+  s->K = iters;
+  s->flags = flags;
+  s->budget = hbm_budget_bytes;
+  hipError_t e = hipGetDevice(&s->device);
+  for (int i = 0; i < kRing && e == hipSuccess; ++i)
+    e = hipEventCreateWithFlags(&s->done[i], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    hip_fail("server set-up", e);
+    destroy_server(s);
+    return nullptr;
+  }
+  return s;
+}
+
+size_t of_server_resident_bytes(const of_server* s) { return s ? s->resident : 0; }
+
+of_session* of_server_open(of_server* s, int H, int W) {
+  if (!s) return set_error("NULL server"), nullptr;
+  return open_session(s, H, W, nullptr, 0);
+}
+
+of_session* of_server_open_ex(of_server* s, int H, int W, void* workspace, size_t workspace_bytes) {
+  if (!s) return set_error("NULL server"), nullptr;
+  return open_session(s, H, W, workspace, workspace_bytes);
 }
 
 size_t of_session_resident_bytes(const of_session* ss) { return ss ? ss->bytes : 0; }
@@ -202,7 +318,7 @@ of_status of_server_close(of_server* s, of_session* ss) {
   std::lock_guard<std::mutex> lock(s->mu);
   DeviceGuard guard(s->device);
   hipDeviceSynchronize();
-  hipFree(ss->mem);
+  if (ss->owns_mem) hipFree(ss->mem);
   s->resident -= ss->bytes;
   s->sessions.erase(std::remove(s->sessions.begin(), s->sessions.end(), ss), s->sessions.end());
   delete ss;
@@ -224,17 +340,16 @@ of_status of_server_push(of_server* s, of_session* const* ss, int n, const void*
   std::lock_guard<std::mutex> lock(s->mu);
   DeviceGuard guard(s->device);
   hipStream_t st = (hipStream_t)stream;
+  const int slot = s->next;
+  if (s->in_use[slot]) {
+    const hipError_t q = hipEventQuery(s->done[slot]);
+    if (q == hipErrorNotReady)
+      return set_error("busy: every staging slot is held by a push still in flight"), OF_ESTATE;
+    if (q != hipSuccess) return hip_fail("staging slot", q);
+  }
   const int L = s->L, K = s->K, R = s->R;
   const Geometry& gg = ss[0]->g;
-  hipError_t e = hipSuccess;
-  // 1. new frames into their slots (level 0)
-  for (int i = 0; i < n && e == hipSuccess; ++i) {
-    of_session* x = ss[i];
-    e = hipMemcpyAsync(x->mem + x->slot_off[x->cur][0], frames[i],
-                       (size_t)x->H * x->W * elem_bytes(x->g.e0), hipMemcpyDeviceToDevice, st);
-  }
-  if (e != hipSuccess) return hip_fail("frame copy", e);
-  // 2. describe the push
+  // 1. describe the push
   Push p;
   p.jobs.resize(L > 1 ? L - 1 : 0);
   p.items.resize(L > 1 ? L - 1 : 0);
@@ -268,9 +383,9 @@ of_status of_server_push(of_server* s, of_session* const* ss, int n, const void*
     const int i = flowing[q];
     of_session* x = ss[i];
     const int prev = x->cur ^ 1;
-    float* fu[2] = {(float*)(x->flow), (float*)(x->flow + align256((size_t)x->H * x->W * 4))};
-    float* fv[2] = {(float*)(x->flow + 2 * align256((size_t)x->H * x->W * 4)),
-                    (float*)(x->flow + 3 * align256((size_t)x->H * x->W * 4))};
+    const size_t fb = align256((size_t)x->H * x->W * 4);
+    float* fu[2] = {(float*)(x->flow), (float*)(x->flow + fb)};
+    float* fv[2] = {(float*)(x->flow + 2 * fb), (float*)(x->flow + 3 * fb)};
     const float* cu = nullptr;
     const float* cv = nullptr;
     int cH = 0, cW = 0, buf = 0, phase = 0;
@@ -298,46 +413,32 @@ of_status of_server_push(of_server* s, of_session* const* ss, int n, const void*
       }
   }
   layout(p);
-  // 3. upload through pinned staging (wait until the previous push consumed it)
-  if (s->staged_pending) {
-    e = hipEventSynchronize(s->staged);
-    if (e != hipSuccess) return hip_fail("staging wait", e);
-    s->staged_pending = false;
+  if (p.bytes > s->slot_bytes)   // cannot happen for sessions opened on this server
+    return set_error("internal: push larger than the staging slots"), OF_ESTATE;
+  char* hblk = s->host_blk + (size_t)slot * s->slot_bytes;
+  char* dblk = s->dev_blk + (size_t)slot * s->slot_bytes;
+  pack(p, hblk);
+  // 2. new frames into their slots (level 0), the arguments into the device slot
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    of_session* x = ss[i];
+    e = hipMemcpyAsync(x->mem + x->slot_off[x->cur][0], frames[i],
+                       (size_t)x->H * x->W * elem_bytes(x->g.e0), hipMemcpyDeviceToDevice, st);
   }
-  if (p.bytes > s->pinned_bytes) {
-    if (s->pinned) hipHostFree(s->pinned);
-    s->pinned = nullptr;
-    e = hipHostMalloc((void**)&s->pinned, p.bytes * 2, hipHostMallocDefault);
-    if (e != hipSuccess) return hip_fail("hipHostMalloc(staging)", e);
-    s->pinned_bytes = p.bytes * 2;
-  }
-  if (p.bytes > s->blk_bytes) {
-    // The old block may still be read by earlier pushes on this stream.
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail("stream sync", e);
-    if (s->blk) hipFree(s->blk);
-    s->blk = nullptr;
-    e = hipMalloc((void**)&s->blk, p.bytes * 2);
-    if (e != hipSuccess) return hip_fail("hipMalloc(arguments)", e);
-    s->blk_bytes = p.bytes * 2;
-  }
-  pack(p, s->pinned);
-  e = hipMemcpyAsync(s->blk, s->pinned, p.bytes, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipEventRecord(s->staged, st);
-  if (e != hipSuccess) return hip_fail("argument upload", e);
-  s->staged_pending = true;
-  // 4. new pyramids, then the iterations of the flowing sessions
+  if (e == hipSuccess) e = hipMemcpyAsync(dblk, hblk, p.bytes, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail("push copies", e);
+  // 3. new pyramids, then the iterations of the flowing sessions
   for (int l = 1; l < L && e == hipSuccess; ++l) {
     const int ni = (int)p.items[l - 1].size();
-    e = launch_reduce_batch(gg.elem(l - 1), gg.ep, (const ReduceJob*)(s->blk + p.off_jobs[l - 1]),
-                            (const int2*)(s->blk + p.off_items[l - 1]), ni, std::min(ni, 8192), st);
+    e = launch_reduce_batch(gg.elem(l - 1), gg.ep, (const ReduceJob*)(dblk + p.off_jobs[l - 1]),
+                            (const int2*)(dblk + p.off_items[l - 1]), ni, std::min(ni, 8192), st);
   }
   int phase = 0;
   for (int l = L - 1; l >= 0 && e == hipSuccess && !flowing.empty(); --l)
     for (int k = 0; k < K && e == hipSuccess; ++k, ++phase) {
       BatchLaunch bl;
-      bl.args = (const IterArgs*)(s->blk + p.off_args[phase]);
-      bl.tiles = (const int4*)(s->blk + p.off_tiles[l]);
+      bl.args = (const IterArgs*)(dblk + p.off_args[phase]);
+      bl.tiles = (const int4*)(dblk + p.off_tiles[l]);
       bl.ntiles = (int)p.tiles[l].size();
       bl.grid = (bl.ntiles + 7) / 8 * 8;
       bl.variant = default_tile_variant(bl.ntiles);
@@ -348,8 +449,11 @@ of_status of_server_push(of_server* s, of_session* const* ss, int n, const void*
     of_session* x = ss[i];
     if (x->has_prev && K == 0) e = launch_zero(u[i], v[i], (size_t)x->H * x->W, st);
   }
+  if (e == hipSuccess) e = hipEventRecord(s->done[slot], st);
   if (e != hipSuccess) return hip_fail("push launch", e);
-  // 5. the new frame becomes the previous one
+  s->in_use[slot] = true;
+  s->next = (slot + 1) % kRing;
+  // 4. the new frame becomes the previous one
   for (int i = 0; i < n; ++i) {
     of_session* x = ss[i];
     has_flow[i] = x->has_prev ? 1 : 0;
@@ -365,18 +469,61 @@ of_status of_session_push(of_session* ss, const void* frame, float* u, float* v,
   return of_server_push(ss->server, &ss, 1, &frame, &u, &v, has_flow, stream);
 }
 
-void of_server_destroy(of_server* s) {
-  if (!s) return;
-  DeviceGuard guard(s->device);
-  hipDeviceSynchronize();
-  for (of_session* ss : s->sessions) {
-    hipFree(ss->mem);
-    delete ss;
+of_session* of_session_create(int H, int W, int levels, int radius, int iters, unsigned flags,
+                              void* workspace, size_t workspace_bytes) {
+  flags &= ~OF_FLAG_NO_GRAPH;
+  if (!check_server_flags(flags)) return nullptr;
+  if (!check_params(H, W, levels, radius, iters, flags)) return nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail("hipGetDevice", e), nullptr;
+  // The registry lock is held across the open so that of_session_destroy cannot retire the
+  // server in between.
+  std::lock_guard<std::mutex> lock(g_hidden_mu);
+  const auto key = std::make_tuple(dev, levels, radius, iters, flags);
+  auto it = g_hidden.find(key);
+  of_server* s;
+  if (it == g_hidden.end()) {
+    s = of_server_create(levels, radius, iters, flags, 0);
+    if (!s) return nullptr;
+    s->hidden = true;
+    g_hidden[key] = s;
+  } else {
+    s = it->second;
   }
-  if (s->blk) hipFree(s->blk);
-  if (s->pinned) hipHostFree(s->pinned);
-  if (s->staged) hipEventDestroy(s->staged);
-  delete s;
+  return open_session(s, H, W, workspace, workspace_bytes);
+}
+
+of_status of_session_push_many(of_session* const* ss, int n, const void* const* frames,
+                               float* const* u, float* const* v, int* has_flow, void* stream) {
+  if (!ss || n < 1 || !ss[0]) return set_error("NULL or empty session array"), OF_EINVAL;
+  return of_server_push(ss[0]->server, ss, n, frames, u, v, has_flow, stream);
+}
+
+void of_session_destroy(of_session* ss) {
+  if (!ss) return;
+  of_server* s = ss->server;
+  if (!s->hidden) {
+    of_server_close(s, ss);
+    return;
+  }
+  std::lock_guard<std::mutex> lock(g_hidden_mu);
+  of_server_close(s, ss);
+  {
+    if (s->sessions.empty()) {
+      for (auto it = g_hidden.begin(); it != g_hidden.end(); ++it)
+        if (it->second == s) {
+          g_hidden.erase(it);
+          break;
+        }
+      destroy_server(s);
+    }
+  }
+}
+
+void of_server_destroy(of_server* s) {
+  if (!s || s->hidden) return;
+  destroy_server(s);
 }
 
 }  // extern "C"

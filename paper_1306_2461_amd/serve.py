@@ -10,9 +10,10 @@ resident memory fits the HBM budget; a stream that can never fit is rejected.  C
 observed by polling the pushes' events; each request records arrival and completion times.
 
 Executors implement ``open(H, W) -> handle`` (raising ``BudgetExceeded``),
-``session_bytes(H, W)``, ``budget``, ``close(handle)``, ``submit([(handle, frame)]) -> token``,
-``ready(token) -> bool`` and ``finish(token) -> [(u, v, has_flow)]``.  ``GpuExecutor`` runs the
-HIP library (``of_server_*``).
+``session_bytes(H, W)``, ``budget``, ``close(handle)``,
+``submit([(handle, frame)], keep) -> token`` (raising ``Busy`` when it cannot take a push now),
+``ready(token) -> bool``, ``wait(token)`` and ``finish(token) -> [(u, v, has_flow)]``.
+``GpuExecutor`` runs the HIP library (``of_server_*``).
 """
 from __future__ import annotations
 
@@ -26,6 +27,10 @@ import numpy as np
 
 class BudgetExceeded(RuntimeError):
     """Opening a stream would exceed the executor's HBM budget."""
+
+
+class Busy(RuntimeError):
+    """The executor holds as many pushes in flight as it can stage; retry after one completes."""
 
 
 @dataclasses.dataclass
@@ -48,10 +53,13 @@ class Request:
 class Server:
     """Continuous-batching request loop over an executor."""
 
-    def __init__(self, executor, max_batch: int = 64, clock=time.perf_counter):
+    def __init__(self, executor, max_batch: int = 64, clock=time.perf_counter, keep=None):
+        """``keep(request) -> bool`` selects the requests whose flow is kept (default: all);
+        the others are only timed, and their output planes go back to the executor's pool."""
         self.ex = executor
         self.max_batch = max_batch
         self.clock = clock
+        self.keep = keep
         self.pending: collections.deque[Request] = collections.deque()
         self.inflight: collections.deque = collections.deque()
         self.sessions: dict[int, Any] = {}
@@ -59,6 +67,7 @@ class Server:
         self.done: list[Request] = []
         self.rejected: list[Request] = []
         self.admission_log: list[tuple] = []
+        self.busy = False
 
     # ------------------------------------------------------------------ requests
     def submit(self, stream_id: int, frame, t_arrival: float | None = None) -> Request:
@@ -119,10 +128,19 @@ class Server:
         self.pending = keep
         if not batch:
             return 0
+        keep = [True if self.keep is None else bool(self.keep(r)) for _, r in batch]
+        try:
+            token = self.ex.submit([(h, r.frame) for h, r in batch], keep)
+        except Busy:
+            # nothing was pushed: the requests go back in front, in order, and wait for a
+            # push in flight to complete
+            self.pending.extendleft(reversed([r for _, r in batch]))
+            self.busy = True
+            return 0
+        self.busy = False
         t = self.clock()
         for _, r in batch:
             r.t_launch = t
-        token = self.ex.submit([(h, r.frame) for h, r in batch])
         self.inflight.append((token, [r for _, r in batch]))
         return len(batch)
 
@@ -168,7 +186,7 @@ class Server:
             launched = self.step() if self.pending else 0
             completed = self.poll()
             if not launched and not completed:
-                if self.inflight and (i >= len(arrivals) or not realtime):
+                if self.inflight and (i >= len(arrivals) or not realtime or self.busy):
                     self.ex.wait(self.inflight[0][0])
                 elif realtime and i < len(arrivals):
                     time.sleep(max(0.0, min(2e-4, arrivals[i][0] - (self.clock() - t0))))
@@ -190,7 +208,17 @@ class Server:
 
 
 class GpuExecutor:
-    """Executor over the HIP server ABI (``of_server_*``) on one device stream."""
+    """Executor over the HIP server ABI (``of_server_*``) on one device.
+
+    Session memory is a torch allocation per stream (``of_server_open_ex``).  A push stages each
+    frame into a pinned host buffer and copies it to a device staging frame on a copy stream;
+    the compute stream waits for that copy (an event) and runs the push, so frame uploads
+    overlap the kernels of earlier pushes.  Output planes come from per-shape pools; planes of
+    results that are not kept go back to their pool when the push completes.  At most
+    ``OF_SERVER_RING`` pushes are in flight; beyond that ``submit`` raises ``Busy``.
+    """
+
+    RING = 8   # OF_SERVER_RING
 
     def __init__(self, levels, radius, iters, fp16=False, budget_bytes=0, device=None,
                  keep_on_device=True):
@@ -207,61 +235,96 @@ class GpuExecutor:
         self.keep_on_device = keep_on_device
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.Stream(self.device)
+            self.copy_stream = torch.cuda.Stream(self.device)
             h = self.lib.of_server_create(levels, radius, iters, self.flags, self.budget)
         if not h:
             raise B.OfError(f"of_server_create failed: {B.last_error()}")
         self._h = h
-        self._pinned: dict[tuple, list] = collections.defaultdict(list)
+        self._ws: dict[int, Any] = {}
+        self._host: dict[tuple, list] = collections.defaultdict(list)      # pinned frames
+        self._dev: dict[tuple, list] = collections.defaultdict(list)       # device frames
+        self._planes: dict[tuple, list] = collections.defaultdict(list)    # output planes
+        self._events: collections.deque = collections.deque()              # pushes in flight
 
     def session_bytes(self, H, W):
         return int(self.lib.of_session_bytes(H, W, self.levels, self.radius, self.iters, self.flags))
 
     def open(self, H, W):
-        with self.torch.cuda.device(self.device):
-            s = self.lib.of_server_open(self._h, H, W)
+        torch = self.torch
+        nbytes = self.session_bytes(H, W)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            s = self.lib.of_server_open_ex(self._h, H, W, ws.data_ptr(), nbytes)
         if not s:
             msg = self.B.last_error()
             if "budget" in msg:
                 raise BudgetExceeded(msg)
-            raise self.B.OfError(f"of_server_open failed: {msg}")
+            raise self.B.OfError(f"of_server_open_ex failed: {msg}")
+        self._ws[s] = ws
         return s
 
     def close(self, handle):
         self.B.check(self.lib.of_server_close(self._h, handle), "of_server_close")
+        self._ws.pop(handle, None)
 
     def resident_bytes(self):
         return int(self.lib.of_server_resident_bytes(self._h))
 
-    def _host_buffer(self, shape):
-        pool = self._pinned[shape]
-        if pool:
-            return pool.pop()
-        return self.torch.empty(shape, dtype=self.torch.uint8, pin_memory=True)
+    @staticmethod
+    def _take(pool, make):
+        return pool.pop() if pool else make()
 
-    def submit(self, items):
+    def submit(self, items, keep=None):
         import ctypes
         torch = self.torch
         n = len(items)
-        frames_host, frames_dev, us, vs = [], [], [], []
-        with torch.cuda.stream(self.stream):
+        keep = [True] * n if keep is None else list(keep)
+        while self._events and self._events[0].query():
+            self._events.popleft()
+        if len(self._events) >= self.RING:
+            raise Busy("every staging slot holds a push in flight")
+        hosts, devs, us, vs = [], [], [], []
+        with torch.cuda.stream(self.copy_stream):
             for _, f in items:
-                hb = self._host_buffer(tuple(f.shape))
+                shape = tuple(f.shape)
+                hb = self._take(self._host[shape], lambda: torch.empty(shape, dtype=torch.uint8, pin_memory=True))
+                db = self._take(self._dev[shape], lambda: torch.empty(shape, dtype=torch.uint8, device=self.device))
                 hb.numpy()[...] = f
-                frames_host.append(hb)
-                frames_dev.append(hb.to(self.device, non_blocking=True))
-                us.append(torch.empty(tuple(f.shape), dtype=torch.float32, device=self.device))
-                vs.append(torch.empty(tuple(f.shape), dtype=torch.float32, device=self.device))
+                db.copy_(hb, non_blocking=True)
+                hosts.append(hb)
+                devs.append(db)
+        copied = torch.cuda.Event()
+        copied.record(self.copy_stream)
+        for _, f in items:
+            shape = tuple(f.shape)
+            mk = lambda: torch.empty(shape, dtype=torch.float32, device=self.device)  # noqa: E731
+            us.append(self._take(self._planes[shape], mk))
+            vs.append(self._take(self._planes[shape], mk))
+        self.stream.wait_event(copied)
         sess = (ctypes.c_void_p * n)(*[h for h, _ in items])
-        pf, _a = self.B.ptr_array([t.data_ptr() for t in frames_dev])
+        pf, _a = self.B.ptr_array([t.data_ptr() for t in devs])
         pu, _b = self.B.ptr_array([t.data_ptr() for t in us])
         pv, _c = self.B.ptr_array([t.data_ptr() for t in vs])
         has = (ctypes.c_int * n)()
         st = self.lib.of_server_push(self._h, ctypes.cast(sess, self.B._VPP), n, pf, pu, pv, has,
                                      self.stream.cuda_stream)
+        if st == self.B.OF_ESTATE:
+            self._give_back(hosts, devs, us, vs)
+            raise Busy(self.B.last_error())
         self.B.check(st, "of_server_push")
         ev = torch.cuda.Event()
         ev.record(self.stream)
-        return {"event": ev, "us": us, "vs": vs, "has": list(has), "keep": (frames_host, frames_dev)}
+        self._events.append(ev)
+        return {"event": ev, "us": us, "vs": vs, "has": list(has), "keep": keep,
+                "frames": (hosts, devs)}
+
+    def _give_back(self, hosts, devs, us, vs):
+        for t in hosts:
+            self._host[tuple(t.shape)].append(t)
+        for t in devs:
+            self._dev[tuple(t.shape)].append(t)
+        for t in list(us) + list(vs):
+            self._planes[tuple(t.shape)].append(t)
 
     def ready(self, token):
         return token["event"].query()
@@ -270,22 +333,27 @@ class GpuExecutor:
         token["event"].synchronize()
 
     def finish(self, token):
-        for hb in token["keep"][0]:
-            self._pinned[tuple(hb.shape)].append(hb)
-        out = []
-        for u, v, has in zip(token["us"], token["vs"], token["has"]):
-            if not has:
-                out.append((None, None, 0))
+        hosts, devs = token["frames"]
+        out, back_u, back_v = [], [], []
+        for u, v, has, k in zip(token["us"], token["vs"], token["has"], token["keep"]):
+            if not has or not k:
+                out.append((None, None, has))
+                back_u.append(u)
+                back_v.append(v)
             elif self.keep_on_device:
                 out.append((u, v, 1))
             else:
                 out.append((u.cpu().numpy(), v.cpu().numpy(), 1))
+                back_u.append(u)
+                back_v.append(v)
+        self._give_back(hosts, devs, back_u, back_v)
         return out
 
     def close_all(self):
         if getattr(self, "_h", None):
             self.lib.of_server_destroy(self._h)
             self._h = None
+            self._ws.clear()
 
     def __del__(self):
         try:

@@ -16,7 +16,7 @@ class FakeClock:
 
 
 class FakeExecutor:
-    def __init__(self, levels, radius, iters, budget_bytes=0, delay=0.01, clock=None):
+    def __init__(self, levels, radius, iters, budget_bytes=0, delay=0.01, clock=None, ring=0):
         self.levels, self.radius, self.iters = levels, radius, iters
         self.budget = budget_bytes
         self.delay = delay
@@ -26,6 +26,9 @@ class FakeExecutor:
         self.pushes = []
         self.next_handle = 1
         self.open_handles = {}
+        self.ring = ring            # pushes in flight at most (0 = unbounded)
+        self.inflight = []
+        self.busy_count = 0
 
     def session_bytes(self, H, W):
         return 2 * H * W * 2 + 16 * H * W
@@ -44,7 +47,13 @@ class FakeExecutor:
         self.resident -= self.open_handles.pop(h)
         self.prev.pop(h, None)
 
-    def submit(self, items):
+    def submit(self, items, keep=None):
+        from paper_1306_2461_amd.serve import Busy
+        self.inflight = [d for d in self.inflight if self.clock() < d]
+        if self.ring and len(self.inflight) >= self.ring:
+            self.busy_count += 1
+            raise Busy("ring full")
+        keep = [True] * len(items) if keep is None else keep
         out = []
         for h, f in items:
             if h in self.prev:
@@ -54,6 +63,8 @@ class FakeExecutor:
                 out.append((None, None, 0))
             self.prev[h] = f
         self.pushes.append(len(items))
+        self.inflight.append(self.clock() + self.delay)
+        out = [o if k else (None, None, o[2]) for o, k in zip(out, keep)]
         return {"due": self.clock() + self.delay, "out": out}
 
     def ready(self, token):

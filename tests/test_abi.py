@@ -70,3 +70,27 @@ def test_workspace_bytes_and_validation(lib):
     assert lib.of_compute(None, None, None, None, None, None) == 1
     assert b"NULL plan" in lib.of_last_error()
     lib.of_plan_destroy(None)
+
+
+def test_host_side_rejections_of_the_newer_entry_points(lib):
+    """Argument checks that reject before any HIP call."""
+    import ctypes
+    from paper_1306_2461_amd import _binding as B
+    assert lib.of_session_create(0, 5, 3, 4, 4, 0, None, 0) is None
+    assert lib.of_session_create(64, 64, 3, 4, 4, B.OF_FLAG_NORMALIZE, None, 0) is None
+    assert b"plans only" in lib.of_last_error()
+    assert lib.of_session_push_many(None, 0, None, None, None, None, None) == B.OF_EINVAL
+    lib.of_session_destroy(None)
+    assert lib.of_server_open_ex(None, 64, 64, None, 0) is None
+    assert lib.of_plan_set_bubble(None, None, None) == B.OF_EINVAL
+    assert lib.of_bubble_step(None, None, 1, 0, None, None, None, None, None) == B.OF_EINVAL
+    assert lib.of_plan_set_timing(None, 1) == B.OF_EINVAL
+    assert lib.of_compute_noalloc(64, 64, 3, 4, 2, B.OF_FLAG_GRAPH, None, None, None, None, None) == B.OF_EINVAL
+    assert lib.of_compute_noalloc(64, 64, 9, 4, 2, 0, None, None, None, None, None) == B.OF_EINVAL
+    # the allocation-free form holds a 1024 x 1024 FP32 pair at 4 levels, not a 2048 x 2048 one
+    cap = lib.of_noalloc_scratch_bytes()
+    assert lib.of_plan_workspace_bytes(1024, 1024, 4, 8, 4, 0) <= cap < lib.of_plan_workspace_bytes(2048, 2048, 4, 8, 4, 0)
+    # batch workspace grows by the argument blocks of the graph slots and the eager ring
+    hs, ws = (ctypes.c_int * 2)(64, 96), (ctypes.c_int * 2)(80, 33)
+    assert lib.of_batch_workspace_bytes(2, hs, ws, 2, 3, 2, 0) > lib.of_plan_workspace_bytes(64, 80, 2, 3, 2, 0) + \
+        lib.of_plan_workspace_bytes(96, 33, 2, 3, 2, 0)

@@ -41,21 +41,44 @@ def test_plan_with_normalisation_matches_oracle(gpu_lib):
     plan.close()
 
 
-def test_bubble_monitor_matches_oracle(gpu_lib):
+def test_bubble_surface_fused_count_matches_oracle(gpu_lib):
+    """eq. 3 over a served sequence: the plan's final iteration counts u <= T_v as it writes u
+    (threshold and count on the device), of_bubble_step finishes S_bubble and moves the mean and
+    threshold on.  Against the oracle's series on the same fields: the mean and threshold agree
+    to rounding, and S_bubble exactly up to vectors within rounding of the threshold; against a
+    count of the GPU field with the GPU's own threshold, exactly."""
     import torch
     ofmi = gpu_lib
-    rng = np.random.default_rng(5)
-    fields = [rng.normal(2.0, 3.0, size=(70, 90)).astype(np.float32) for _ in range(4)]
-    mon = ofmi.BubbleMonitor(70, 90, device=dev())
-    mean = np.zeros((70, 90))
-    announce("bubble monitor x4")
-    for t, f in enumerate(fields):
-        s = mon.update(to_dev(f))
-        mean = oracle.running_mean(mean, f, t)
-        thr = oracle.bubble_threshold(mean)
-        np.testing.assert_allclose(mon.mean.cpu().numpy(), mean, rtol=1e-5, atol=1e-5)
-        # counts can differ only for values within rounding of the threshold
-        near = np.abs(f - thr) < 1e-4
-        lo = oracle.bubble_surface(f, thr) - near.mean()
-        hi = oracle.bubble_surface(f, thr) + near.mean()
-        assert lo - 1e-12 <= s <= hi + 1e-12
+    H, W = 96, 128
+    frames = [to_dev(f) for f, _, _ in synth.stream_frames(0, 7, size=(H, W))]
+    plan = ofmi.Plan(H, W, 3, 4, 3, device=dev())
+    mon = ofmi.BubbleMonitor(H, W, device=dev())
+    mon.attach(plan)
+    fields, surf, thr_used = [], [], []
+    announce("bubble surface over 6 fields")
+    for t in range(6):
+        thr_used.append(float(mon.threshold.item()))
+        u, _ = plan.compute(frames[t], frames[t + 1])
+        s = mon.step(u)
+        torch.cuda.synchronize()
+        fields.append(u.cpu().numpy().astype(np.float64))
+        surf.append(float(s.item()))
+    ref = oracle.bubble_series(fields)
+    mean = np.mean(fields, axis=0)
+    np.testing.assert_allclose(mon.mean.cpu().numpy(), mean, rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(float(mon.threshold.item()), oracle.bubble_threshold(mean), rtol=1e-5, atol=1e-5)
+    n = H * W
+    for t in range(6):
+        # exact: the fused count is the count of the written field against the threshold in force
+        own = thr_used[t] if t > 0 else float(np.float32(oracle.bubble_threshold(fields[0])))
+        if t > 0:
+            assert surf[t] == np.float32(np.count_nonzero(fields[t] <= np.float32(own)) / n), t
+        # oracle: up to vectors within rounding of its threshold
+        m = np.mean(fields[:max(t, 1)], axis=0)
+        othr = oracle.bubble_threshold(m)
+        near = np.count_nonzero(np.abs(fields[t] - othr) < 1e-4 * max(1.0, abs(othr)))
+        assert abs(surf[t] - ref[t]) * n <= near + 0.5, (t, surf[t], ref[t], near)
+    mon.detach(plan)
+    u0, _ = plan.compute(frames[0], frames[1])
+    torch.cuda.synchronize()
+    plan.close()

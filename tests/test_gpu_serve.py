@@ -96,3 +96,114 @@ def test_session_budget_and_single_push(gpu_lib):
     dd = flow_error(u.cpu().numpy(), v.cpu().numpy(), ou, ov)
     print(floor_util.check_all_pixels(dd, 1e-3, floor_util.load_floor("serve_0_0"), "session push"))
     lib.of_server_destroy(srv)
+
+
+def _long_stream_work(torch, stream, ms_target=60):
+    """Finite GPU work queued on `stream` (a few large matrix products) so that calls made
+    right after can be seen to return before it completes."""
+    a = torch.randn(6144, 6144, device=dev())
+    with torch.cuda.stream(stream):
+        for _ in range(12):
+            a = (a @ a) * 1e-3
+    return a
+
+
+def test_session_entry_points_with_caller_workspace(gpu_lib):
+    """of_session_create with torch-owned workspace, of_session_push_many over two sessions and
+    of_session_destroy: flows equal the plain path bitwise; the pushes return while earlier work
+    on the stream is still running; a full staging ring makes a push return OF_ESTATE (busy)
+    without enqueueing anything, and the next push after the ring drains succeeds."""
+    import ctypes
+    import time
+
+    import torch
+    ofmi = gpu_lib
+    from paper_1306_2461_amd import _binding as B
+    lib = B.load()
+    streams = _streams(3)
+    sizes = SIZES[:2]
+    ws = [torch.empty(lib.of_session_bytes(H, W, L, R, K, 0), dtype=torch.uint8, device=dev()) for H, W in sizes]
+    ss = [lib.of_session_create(H, W, L, R, K, 0, w.data_ptr(), w.numel()) for (H, W), w in zip(sizes, ws)]
+    assert all(ss), B.last_error()
+    assert lib.of_session_resident_bytes(ss[0]) == ws[0].numel()
+    sarr = (ctypes.c_void_p * 2)(*ss)
+    frames = [[torch.from_numpy(f).to(dev()) for f in streams[s]] for s in range(2)]
+    outs = [[(torch.empty(sz, device=dev()), torch.empty(sz, device=dev())) for _ in range(3)] for sz in sizes]
+    stream = torch.cuda.Stream()
+    st = stream.cuda_stream
+    torch.cuda.synchronize()
+    keep = []
+    for t in range(3):
+        if t == 1:
+            keep.append(_long_stream_work(torch, stream))
+        pf, _a = B.ptr_array([frames[s][t].data_ptr() for s in range(2)])
+        pu, _b = B.ptr_array([outs[s][max(t - 1, 0)][0].data_ptr() for s in range(2)])
+        pv, _c = B.ptr_array([outs[s][max(t - 1, 0)][1].data_ptr() for s in range(2)])
+        has = (ctypes.c_int * 2)()
+        t0 = time.perf_counter()
+        assert lib.of_session_push_many(ctypes.cast(sarr, B._VPP), 2, pf, pu, pv, has, st) == 0, B.last_error()
+        dt = time.perf_counter() - t0
+        if t == 1:
+            ev = torch.cuda.Event()
+            ev.record(stream)
+            assert not ev.query(), "the push waited for earlier work on its stream"
+            announce(f"push returned in {dt * 1e3:.2f} ms with earlier work still running")
+        assert list(has) == ([0, 0] if t == 0 else [1, 1])
+    # fill the staging ring behind long work: the push after OF_SERVER_RING in flight is busy
+    keep.append(_long_stream_work(torch, stream))
+    s0 = ctypes.c_void_p(ss[0])
+    has1 = ctypes.c_int()
+    statuses = []
+    for i in range(10):
+        u0, v0 = outs[0][2]
+        statuses.append(lib.of_session_push(s0, frames[0][i % 3].data_ptr(), u0.data_ptr(), v0.data_ptr(), st,
+                                            ctypes.byref(has1)))
+    # pushes succeed until the ring is full (earlier pushes may still hold slots), then busy
+    assert B.OF_ESTATE in statuses, statuses
+    first_busy = statuses.index(B.OF_ESTATE)
+    assert 1 <= first_busy <= 8 and all(x == 0 for x in statuses[:first_busy]), statuses
+    assert all(x in (0, B.OF_ESTATE) for x in statuses), statuses
+    torch.cuda.synchronize()
+    st2 = lib.of_session_push(s0, frames[0][0].data_ptr(), outs[0][2][0].data_ptr(), outs[0][2][1].data_ptr(), st,
+                              ctypes.byref(has1))
+    assert st2 == 0
+    torch.cuda.synchronize()
+    for s, (H, W) in enumerate(sizes):
+        plan = ofmi.Plan(H, W, L, R, K, device=dev())
+        for t in range(2):
+            pu_, pv_ = plan.compute(frames[s][t], frames[s][t + 1])
+            torch.cuda.synchronize()
+            if t == 0:
+                assert np.array_equal(outs[s][0][0].cpu().numpy(), pu_.cpu().numpy())
+                assert np.array_equal(outs[s][0][1].cpu().numpy(), pv_.cpu().numpy())
+            elif s == 1:
+                assert np.array_equal(outs[s][1][0].cpu().numpy(), pu_.cpu().numpy())
+        plan.close()
+    for x in ss:
+        lib.of_session_destroy(x)
+    del keep
+
+
+def test_executor_keeps_only_selected_flows(gpu_lib):
+    """The request loop over the GPU executor with a keep predicate: kept flows equal the plain
+    path bitwise, the others are dropped and their planes reused."""
+    import torch
+    ofmi = gpu_lib
+    from paper_1306_2461_amd.serve import GpuExecutor, Server
+    ex = GpuExecutor(L, R, K, device=dev(), keep_on_device=False)
+    srv = Server(ex, keep=lambda r: r.stream_id == 1)
+    streams = _streams(4)
+    reqs = {s: [srv.submit(s, f) for f in streams[s]] for s in range(3)}
+    srv.drain()
+    ex.close_all()
+    for s in range(3):
+        assert [r.has_flow for r in reqs[s]] == [False, True, True, True]
+        for t in range(1, 4):
+            assert (reqs[s][t].u is not None) == (s == 1)
+    H, W = SIZES[1]
+    plan = ofmi.Plan(H, W, L, R, K, device=dev())
+    from gpu_util import to_dev
+    pu, pv = plan.compute(to_dev(streams[1][2]), to_dev(streams[1][3]))
+    torch.cuda.synchronize()
+    assert np.array_equal(reqs[1][3].u, pu.cpu().numpy()) and np.array_equal(reqs[1][3].v, pv.cpu().numpy())
+    plan.close()

@@ -63,3 +63,15 @@ def test_bubble_surface_and_threshold():
     for t, x in enumerate([np.array([1.0, 2, 3]), np.array([3.0, 2, 1]), np.array([2.0, 2, 2])]):
         m = oracle.running_mean(m, x, t)
     np.testing.assert_allclose(m, [2.0, 2.0, 2.0])
+
+
+def test_bubble_series_causal_threshold():
+    """Closed form on constructed fields: field 0 = [0, 1, 2, 3] (T_v = 1.5, S = 2/4);
+    field 1 = [4, 4, 4, -4] thresholded with T_v of field 0 (1.5): S = 1/4; the mean becomes
+    [2, 2.5, 3, -0.5] (T_v = 1.25); field 2 = [1, 1.25, 1.5, 2] against 1.25: S = 2/4."""
+    f = [np.array([0.0, 1, 2, 3]), np.array([4.0, 4, 4, -4]), np.array([1.0, 1.25, 1.5, 2])]
+    S = oracle.bubble_series(f)
+    assert S == [0.5, 0.25, 0.5]
+    # one field alone: its own threshold, as bubble_surface(u, bubble_threshold(u))
+    u = np.random.default_rng(3).normal(size=(7, 9))
+    assert oracle.bubble_series([u]) == [oracle.bubble_surface(u, oracle.bubble_threshold(u))]

@@ -105,3 +105,22 @@ def test_poisson_arrivals_keep_stream_order():
     for s in range(3):
         vals = [int(f[0, 0]) for t, sid, f in arr if sid == s]
         assert vals == sorted(vals)
+
+
+def test_busy_executor_keeps_order_and_keep_predicate():
+    """A full staging ring makes the executor refuse a push (Busy): the requests stay pending in
+    order and go out after an earlier push completes; flows of requests not kept are dropped."""
+    clock = FakeClock()
+    ex = FakeExecutor(1, 2, 1, delay=1.0, clock=clock, ring=1)
+    srv = Server(ex, clock=clock, keep=lambda r: r.stream_id == 0)
+    fr = {s: _frames(s, 3, (24, 24)) for s in (0, 1)}
+    reqs = {s: [srv.submit(s, f) for f in fr[s]] for s in (0, 1)}
+    assert srv.step() == 2                       # push 1: first frames of both streams
+    assert srv.step() == 0 and srv.busy          # ring of one is full
+    assert len(srv.pending) == 4 and ex.busy_count == 1
+    srv.drain()
+    assert ex.pushes == [2, 2, 2]
+    for t in (1, 2):
+        u, v = oracle.flow(fr[0][t - 1], fr[0][t], 1, 2, 1)
+        assert np.array_equal(reqs[0][t].u, u) and reqs[0][t].has_flow
+        assert reqs[1][t].u is None and reqs[1][t].has_flow
