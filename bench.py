@@ -5,15 +5,19 @@ Workload (one step = one frame pair through the whole method): synthetic 1024x10
 particle images (0.03 particles/px, sigma 1.2 px, shear layer 4 + 4 tanh((y - 512)/40) px plus
 a reverse Lamb-Oseen vortex), 4 pyramid levels, window radius 8, 4 iterations per level,
 FP32 storage, one of_compute call per pair on one stream.  Inputs rotate over 16 distinct
-pairs already resident in HBM.  Also reported: the FP16-storage form of the same workload,
-per-pair latency percentiles, the live per-kernel event timing of the fused iteration kernel
-against MI355X HBM peak, and the FP64 CPU oracle timed on this host on a bounded sample.
+pairs already resident in HBM.  Also reported, in the same JSON line: the FP16-storage form,
+the 256x256 workload (3 levels, r = 4), per-pair latency percentiles, the fused iteration
+kernel per level against MI355X HBM peak (hipEvent spans on the launch stream), parity with
+the FP64 oracle and accuracy against the generator's ground truth, the batched and mixed-size
+forms, the Gaussian window and masks, the served streams, and the FP64 CPU oracle timed on
+this host's cores.
 """
 from __future__ import annotations
 
 import argparse
 import concurrent.futures as cf
 import json
+import multiprocessing as mp
 import os
 import sys
 import time
@@ -25,9 +29,8 @@ METRIC = "frame pairs/s at 1024² (FP32 vs FP16-stored, % HBM peak); p50/p99 lat
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "c2"
 
-
-# Launch configuration the plan autotuner settles on for this workload (FP32 and FP16): used by
-# the --probe run, which profilers wrap, so that it needs no autotuning launches.
+# Launch configuration the plan autotuner settles on for this workload: used by the --probe
+# run, which profilers wrap, so that it needs no autotuning launches.
 PROBE_CONFIG = {"bands": [4, 1, 1, 1], "variant": [3, 1, 6, 6]}
 # One of the configurations the batch autotuner picks for 16 pairs of this workload.
 PROBE_BATCH_CONFIG = {"bands": [8, 8, 4, 1], "grid": [512, 0, 512, 512], "variant": [0, 0, 1, 1]}
@@ -41,6 +44,8 @@ COUNTER_SUMMARY = "profiles/lk_iter_1024_plain_path_counters.md"
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
+
+# --------------------------------------------------------------------------- host helpers
 
 def kernel_source_hash():
     """SHA-256 of the iteration kernel's sources with // comments and blank lines removed (a
@@ -58,84 +63,116 @@ def kernel_source_hash():
 
 
 def measured_traffic():
-    """HBM bytes per iteration launch from the committed counter summary (rocprofv3 FETCH_SIZE
-    and WRITE_SIZE runs, copy-calibrated), or None when the kernel sources changed since."""
+    """HBM bytes per level-0 iteration launch from the committed counter summary (rocprofv3
+    FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None when the kernel sources changed
+    since the counters were taken."""
     import re
     try:
         text = open(os.path.join(ROOT, COUNTER_SUMMARY)).read()
     except OSError:
         return None
     m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
-    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.]+)", text)
+    m_val = re.search(r"level0_traffic_bytes_per_launch:\s*([0-9.]+)", text)
     if not m_hash or not m_val or m_hash.group(1) != kernel_source_hash():
         return None
     return float(m_val.group(1))
 
 
-def probe(args):
-    """Fixed short run for counter collection: a 256 MiB device copy (calibration of the
-    FETCH_SIZE / WRITE_SIZE counters), then 5 plain FP32 pairs (graphs off, so every launch is
-    a kernel dispatch of its own) at PROBE_CONFIG, then one 16-pair batch at
-    PROBE_BATCH_CONFIG; no timing, no JSON line."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_workers():
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _noop(x):
+    return x
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, int(q * len(xs)))]
+
+
+def err_stats(u, v, ou, ov):
+    """max-abs and RMS (over both components) of a flow against a reference, in px."""
+    import numpy as np
+    du = u.astype(np.float64) - ou
+    dv = v.astype(np.float64) - ov
+    return {"max_abs_px": float(max(np.abs(du).max(), np.abs(dv).max())),
+            "rms_px": float(np.sqrt(0.5 * ((du ** 2).mean() + (dv ** 2).mean())))}
+
+
+def truth_stats(u, v, gu, gv, margin):
+    """Method accuracy against the generator's ground-truth field on the interior (pixels at
+    least `margin` px from every border): RMS and max of the end-point error."""
+    import numpy as np
+    sl = (slice(margin, -margin), slice(margin, -margin))
+    e = np.hypot(u[sl].astype(np.float64) - gu[sl], v[sl].astype(np.float64) - gv[sl])
+    return {"rms_px": float(np.sqrt((e ** 2).mean())), "max_px": float(e.max()), "interior_margin_px": margin}
+
+
+def floor_max(case):
+    """Largest committed FP32 rounding floor of a parity case (tests/golden/floor), or None."""
+    import numpy as np
+    try:
+        with np.load(os.path.join(ROOT, "tests", "golden", "floor", f"{case}.npz"), allow_pickle=False) as z:
+            return float(z["max"])
+    except OSError:
+        return None
+
+
+# --------------------------------------------------------------------------- CPU workers
+# (forked before the GPU is touched; they run numpy only)
+
+def _gen(args):
     import synth
-    import torch
-    import paper_1306_2461_amd as ofmi
-    dev = torch.device("cuda", 0)
-    # calibration: a plain copy of 256 MiB (reads and writes 2^28 bytes each)
-    src = torch.ones(1 << 26, dtype=torch.float32, device=dev)
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    del src, dst
-    pairs = [synth.make_pair(WORKLOAD, i)[:2] for i in range(4)]
-    d1 = [torch.from_numpy(p[0]).to(dev) for p in pairs]
-    d2 = [torch.from_numpy(p[1]).to(dev) for p in pairs]
-    wl = synth.workload(WORKLOAD)
-    plan = ofmi.Plan(wl.H, wl.W, wl.levels, wl.radius, wl.iters, device=dev, graph=False)
-    plan.set_config(PROBE_CONFIG)
-    u, v = plan.compute(d1[0], d2[0])
-    for i in range(4):
-        plan.compute(d1[i], d2[i], u, v)
-    torch.cuda.synchronize()
-    log(f"probe: plain path done, kernel sources {kernel_source_hash()}")
-    plan.close()
-    b = ofmi.Batch([(wl.H, wl.W)] * 16, wl.levels, wl.radius, wl.iters, device=dev, graph=False)
-    b.set_config(PROBE_BATCH_CONFIG)
-    bu, bv = b.outputs()
-    b.compute([d1[i % 4] for i in range(16)], [d2[i % 4] for i in range(16)], bu, bv)
-    torch.cuda.synchronize()
-    log("probe: 16-pair batch done")
-    b.close()
+    name, i = args
+    I1, I2, gu, gv = synth.make_pair(name, i)
+    return I1, I2, gu.astype("float32"), gv.astype("float32")
 
 
-def _gen(i):
-    import synth
-    I1, I2, _, _ = synth.make_pair(WORKLOAD, i)
-    return I1, I2
+def _gen_c4(i_and_size):
+    from synth import particles as P
+    i, (H, W) = i_and_size
+    wl = P.WORKLOADS["c4"]
+    rngs = P._rngs(wl.index, i)
+    field = P._vortex_field(rngs[4], H, W)
+    I1, I2, gu, gv, _ = P._pair_from_field(field, H, W, wl.rho, wl.sigma, rngs, wl.levels)
+    return I1, I2, gu.astype("float32"), gv.astype("float32")
 
 
-def _oracle_pair(args):
-    os.environ["OMP_NUM_THREADS"] = "1"
+def _oracle_job(args):
+    """The FP64 oracle on one pair, one thread; returns (flow as float32, seconds)."""
+    import numpy as np
     import oracle
     I1, I2, L, r, K = args
     t = time.perf_counter()
-    oracle.flow(I1, I2, L, r, K)
-    return time.perf_counter() - t
+    u, v = oracle.flow(I1, I2, L, r, K)
+    return u.astype(np.float32), v.astype(np.float32), time.perf_counter() - t
 
 
-def cpu_baseline(pairs, L, r, K, n_pairs, workers):
-    """The FP64 oracle on `n_pairs` pairs over a pool of `workers` processes (no GPU touched)."""
-    jobs = [(pairs[i % len(pairs)][0], pairs[i % len(pairs)][1], L, r, K) for i in range(n_pairs)]
+def cpu_pool(pool, workers, pairs, L, r, K):
+    """The oracle over `pairs` [(I1, I2), ...] on the pool, longest first; returns the flows in
+    input order, the wall time and the per-pair CPU times."""
+    order = sorted(range(len(pairs)), key=lambda i: -pairs[i][0].size)
     t = time.perf_counter()
-    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
-        per = list(ex.map(_oracle_pair, jobs))
+    res = list(pool.map(_oracle_job, [(pairs[i][0], pairs[i][1], L, r, K) for i in order]))
     wall = time.perf_counter() - t
-    return {"value": n_pairs / wall, "unit": "frame pairs/s", "cores": workers, "kind": "oracle",
-            "sample": f"{n_pairs} distinct 1024x1024 pairs of the bench workload, FP64 numpy oracle, "
-                      f"one pair per worker process ({workers} processes, 1 thread each); "
-                      f"mean single-pair time {sum(per) / len(per):.2f} s",
-            "cpu_seconds": round(sum(per), 2)}
+    out = [None] * len(pairs)
+    for i, rr in zip(order, res):
+        out[i] = rr
+    return out, wall
 
+
+# --------------------------------------------------------------------------- GPU timing
 
 def _ptrs(d1, d2, us, vs):
     return [(a.data_ptr(), b.data_ptr(), u.data_ptr(), v.data_ptr()) for a, b, u, v in zip(d1, d2, us, vs)]
@@ -168,29 +205,93 @@ def latency(torch, plan, d1, d2, us, vs, n_calls):
         plan.compute_raw(*ptrs[i % n], st)
         stream.synchronize()
         out.append((time.perf_counter() - t) * 1e3)
-    out.sort()
-    return {"p50_ms": round(out[len(out) // 2], 4), "p99_ms": round(out[min(len(out) - 1, int(0.99 * len(out)))], 4)}
+    return {"p50_ms": round(pct(out, 0.5), 4), "p99_ms": round(pct(out, 0.99), 4)}
 
 
-def _gen_c4(i_and_size):
+def level_timing(torch, ofmi, obj, run, levels, n_runs):
+    """Per-level span timing (OF_TIMING_LEVEL): one hipEvent pair around each level's K
+    iteration launches and one around the pyramid launches, on the launch stream, with the
+    host enqueueing ahead of the GPU.  Returns [(level, ms, launches, units, bytes)] and the
+    pyramid record."""
+    obj.set_timing(ofmi.OF_TIMING_LEVEL)
+    for i in range(n_runs):
+        run(i)
+    torch.cuda.synchronize()
+    lv = [(l,) + tuple(obj.read_timing(ofmi.OF_KERNEL_LEVEL(l))) for l in range(levels)]
+    rd = obj.read_timing(ofmi.OF_KERNEL_REDUCE)
+    obj.read_timing(ofmi.OF_KERNEL_ITERATE)
+    obj.set_timing(False)
+    return lv, rd
+
+
+def roofline_from_levels(lv, sizes, frame_bytes):
+    """Per-level table and the dominant level (largest share of the iteration time)."""
+    total = sum(r[1] for r in lv)
+    per = []
+    for (l, ms, n, units, by), (H, W) in zip(lv, sizes):
+        avg_us = ms / max(n, 1) * 1e3
+        gbs = by / ms / 1e6 if ms > 0 else 0.0
+        per.append({"level": l, "H": H, "W": W, "frame_bytes_per_px": frame_bytes[l],
+                    "launches": n, "avg_launch_us": round(avg_us, 3),
+                    "bytes_per_launch": round(by / max(n, 1)), "achieved_GBs": round(gbs, 1),
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "time_share": round(ms / total, 4) if total else 0})
+    dom = max(per, key=lambda p: p["time_share"])
+    return per, dom
+
+
+# --------------------------------------------------------------------------- forms
+
+def bench_plain(torch, ofmi, dev, wl, d1, d2, us, vs, fp16, steps, warmup, tag):
+    plan = ofmi.Plan(wl.H, wl.W, wl.levels, wl.radius, wl.iters, fp16=fp16, device=dev)
+    tuned = plan.autotune(d1[0], d2[0], us[0], vs[0], reps=3)
+    el = time_plan(torch, plan, d1, d2, us, vs, steps, warmup)
+    lat = latency(torch, plan, d1, d2, us, vs, min(200, max(steps, 50)))
+    n = len(d1)
+    lv, rd = level_timing(torch, ofmi, plan, lambda i: plan.compute(d1[i % n], d2[i % n], us[i % n], vs[i % n]),
+                          wl.levels, max(50, min(steps, 200)))
+    sizes = [(wl.H, wl.W)]
+    for _ in range(wl.levels - 1):
+        sizes.append(((sizes[-1][0] + 1) // 2, (sizes[-1][1] + 1) // 2))
+    fb = [1] + [2 if fp16 else 4] * (wl.levels - 1)
+    per, dom = roofline_from_levels(lv, sizes, fb)
+    log(f"{tag}: {steps / el:.1f} pairs/s, {el / steps * 1e3:.4f} ms/pair, latency {lat}, config {tuned}, "
+        f"levels " + ", ".join(f"L{p['level']} {p['avg_launch_us']} us {p['frac']:.3f}" for p in per))
+    return plan, {"el": el, "lat": lat, "cfg": tuned, "per_level": per, "dominant": dom,
+                  "pyramid": {"launches": rd[1], "avg_launch_us": round(rd[0] / max(rd[1], 1) * 1e3, 3),
+                              "achieved_GBs": round(rd[3] / rd[0] / 1e6, 1) if rd[0] > 0 else 0.0}}
+
+
+def bench_c1(torch, ofmi, dev, pairs, oracle_flow, steps, warmup):
+    """The 256x256 workload (3 levels, r = 4, 4 iterations, FP32 plain path)."""
     import synth
-    i, size = i_and_size
-    H, W, I1, I2, _, _ = next(synth.batch_items(1, sizes=[size]))
-    return I1, I2
-
-
-def _gen_stream(args):
-    import synth
-    sid, n, size = args
-    return [f for f, _, _ in synth.stream_frames(sid, n, size=size)]
-
-
-def bench_batched(torch, ofmi, dev, pairs, wl, fp16, reps, tag):
-    """The 1024x1024 workload as one batch of all resident pairs per graph replay."""
-    n = len(pairs)
-    b = ofmi.Batch([(wl.H, wl.W)] * n, wl.levels, wl.radius, wl.iters, fp16=fp16, device=dev)
+    wl = synth.workload("c1")
     d1 = [torch.from_numpy(p[0]).to(dev) for p in pairs]
     d2 = [torch.from_numpy(p[1]).to(dev) for p in pairs]
+    us = [torch.empty((wl.H, wl.W), dtype=torch.float32, device=dev) for _ in pairs]
+    vs = [torch.empty((wl.H, wl.W), dtype=torch.float32, device=dev) for _ in pairs]
+    plan = ofmi.Plan(wl.H, wl.W, wl.levels, wl.radius, wl.iters, device=dev)
+    tuned = plan.autotune(d1[0], d2[0], us[0], vs[0], reps=3)
+    el = time_plan(torch, plan, d1, d2, us, vs, steps, warmup)
+    lat = latency(torch, plan, d1, d2, us, vs, min(200, max(steps, 50)))
+    plan.compute(d1[0], d2[0], us[0], vs[0])
+    torch.cuda.synchronize()
+    u, v = us[0].cpu().numpy(), vs[0].cpu().numpy()
+    plan.close()
+    ou, ov, osec = oracle_flow
+    out = {"value": round(steps / el, 3), "unit": "frame pairs/s", "ms_per_step": round(el / steps * 1e3, 5),
+           "latency_ms": lat, "config": {"workload": "256x256 uint8 particle pair, 3 levels, radius 4, 4 iterations, "
+                                                     "FP32 plain per-pair path", "launch_config": tuned},
+           "parity": dict(err_stats(u, v, ou, ov), tolerance_px=1e-3, fp32_floor_max_px=floor_max("c1")),
+           "accuracy_vs_truth": truth_stats(u, v, pairs[0][2], pairs[0][3], wl.radius + 4 + 2),
+           "cpu_oracle_single_pair_s": round(osec, 4)}
+    log(f"c1: {out['value']:.1f} pairs/s, latency {lat}, parity {out['parity']}")
+    return out
+
+
+def bench_batched(torch, ofmi, dev, d1, d2, wl, fp16, reps, tag):
+    """The 1024x1024 workload as one batch of all resident pairs per graph replay."""
+    n = len(d1)
+    b = ofmi.Batch([(wl.H, wl.W)] * n, wl.levels, wl.radius, wl.iters, fp16=fp16, device=dev)
     us, vs = b.outputs()
     cfg = b.autotune(d1, d2, us, vs, reps=2)
     arrs = b.pointer_arrays(d1, d2, us, vs)
@@ -203,29 +304,36 @@ def bench_batched(torch, ofmi, dev, pairs, wl, fp16, reps, tag):
         b.compute_raw(arrs, st)
     torch.cuda.synchronize()
     el = time.perf_counter() - t
-    b.set_timing(True)
-    b.compute(d1, d2, us, vs)
-    torch.cuda.synchronize()
-    it = b.read_timing(ofmi.OF_KERNEL_ITERATE)
-    b.read_timing(ofmi.OF_KERNEL_REDUCE)
-    b.set_timing(False)
+    lv, _ = level_timing(torch, ofmi, b, lambda i: b.compute(d1, d2, us, vs), wl.levels, 3)
     b.close()
-    ach = it[3] / it[0] / 1e6 if it[0] > 0 else 0.0
+    l0 = lv[0]
+    ach = l0[4] / l0[1] / 1e6 if l0[1] > 0 else 0.0
     log(f"batched {tag}: {n * reps / el:.1f} pairs/s ({el / reps * 1e3:.3f} ms per batch of {n}), "
-        f"iterate {ach:.0f} GB/s, config {cfg}")
+        f"level 0 {ach:.0f} GB/s, config {cfg}")
     return {"value": round(n * reps / el, 3), "unit": "frame pairs/s", "pairs_per_batch": n,
             "ms_per_batch": round(el / reps * 1e3, 4), "config": cfg,
-            "iterate_achieved_GBs": round(ach, 1), "iterate_frac_hbm": round(ach / HBM_PEAK_GBS, 4),
-            "iterate_avg_launch_us": round(it[0] / max(it[1], 1) * 1e3, 3)}
+            "level0_achieved_GBs": round(ach, 1), "level0_frac_hbm": round(ach / HBM_PEAK_GBS, 4),
+            "level0_avg_launch_us": round(l0[1] / max(l0[2], 1) * 1e3, 3)}
 
 
-def bench_c4(torch, ofmi, dev, workers, reps):
-    """64 mixed-size pairs (16x 512^2, 32x 1024x768, 16x 2048^2), FP16 storage, one replay per batch."""
+def bench_c4(torch, ofmi, dev, pool, workers, reps, with_cpu=True):
+    """64 mixed-size pairs (16x 512^2, 32x 1024x768, 16x 2048^2), FP16 storage, one replay per
+    batch; the plain per-pair path on the same 64 pairs; the oracle over all 64 pairs on the
+    host pool (parity of every pair and the CPU baseline)."""
+    import numpy as np
     import synth
     wl = synth.workload("c4")
     sizes = synth.particles.batch_sizes(64)
-    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
-        pairs = list(ex.map(_gen_c4, list(enumerate(sizes))))
+    t = time.perf_counter()
+    pairs = list(pool.map(_gen_c4, list(enumerate(sizes))))
+    log(f"c4: generated 64 pairs in {time.perf_counter() - t:.1f} s")
+    cpu = None
+    if with_cpu:
+        flows, wall = cpu_pool(pool, workers, [(p[0], p[1]) for p in pairs], wl.levels, wl.radius, wl.iters)
+        cpu = {"value": round(64 / wall, 4), "unit": "frame pairs/s", "cores": workers, "kind": "oracle",
+               "sample": "all 64 pairs of the mixed batch, FP64 numpy oracle, one pair per worker process at a time, "
+                         "longest first", "cpu_seconds": round(sum(f[2] for f in flows), 2), "wall_s": round(wall, 2)}
+        log(f"c4: oracle pool {cpu['value']} pairs/s on {workers} processes")
     b = ofmi.Batch(sizes, wl.levels, wl.radius, wl.iters, fp16=True, device=dev)
     d1 = [torch.from_numpy(p[0]).to(dev) for p in pairs]
     d2 = [torch.from_numpy(p[1]).to(dev) for p in pairs]
@@ -240,21 +348,54 @@ def bench_c4(torch, ofmi, dev, workers, reps):
         b.compute_raw(arrs, st)
     torch.cuda.synchronize()
     el = time.perf_counter() - t
-    b.set_timing(True)
-    b.compute(d1, d2, us, vs)
-    torch.cuda.synchronize()
-    it = b.read_timing(ofmi.OF_KERNEL_ITERATE)
-    rd = b.read_timing(ofmi.OF_KERNEL_REDUCE)
-    b.set_timing(False)
+    got = [(u.cpu().numpy(), v.cpu().numpy()) for u, v in zip(us, vs)]
+    lv, rd = level_timing(torch, ofmi, b, lambda i: b.compute(d1, d2, us, vs), wl.levels, 2)
     b.close()
-    alg = it[3] + rd[3]
-    ach = it[3] / it[0] / 1e6 if it[0] > 0 else 0.0
-    log(f"c4: {64 * reps / el:.1f} pairs/s, {el / reps * 1e3:.2f} ms per batch, iterate {ach:.0f} GB/s")
-    return {"value": round(64 * reps / el, 3), "unit": "frame pairs/s", "ms_per_batch": round(el / reps * 1e3, 3),
-            "algorithmic_GB_per_batch": round(alg / 1e9, 3),
-            "effective_frac_hbm": round(alg / (el / reps) / 1e9 / HBM_PEAK_GBS, 4),
-            "iterate_achieved_GBs": round(ach, 1), "iterate_frac_hbm": round(ach / HBM_PEAK_GBS, 4),
-            "config": cfg}
+    alg = sum(r[4] for r in lv) / 2 + rd[3] / 2
+    l0 = lv[0]
+    ach = l0[4] / l0[1] / 1e6 if l0[1] > 0 else 0.0
+    it_ms = sum(r[1] for r in lv)
+    it_ach = sum(r[4] for r in lv) / it_ms / 1e6 if it_ms > 0 else 0.0
+    # the plain per-pair path on the same 64 pairs (one plan per size, autotuned)
+    plans = {}
+    for i, s in enumerate(sizes):
+        if s not in plans:
+            p = ofmi.Plan(s[0], s[1], wl.levels, wl.radius, wl.iters, fp16=True, device=dev)
+            p.autotune(d1[i], d2[i], us[i], vs[i], reps=2)
+            plans[s] = p
+    ptr = _ptrs(d1, d2, us, vs)
+    for i, s in enumerate(sizes):
+        plans[s].compute_raw(*ptr[i], st)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        for i, s in enumerate(sizes):
+            plans[s].compute_raw(*ptr[i], st)
+    torch.cuda.synchronize()
+    el_plain = time.perf_counter() - t
+    for p in plans.values():
+        p.close()
+    out = {"value": round(64 * reps / el, 3), "unit": "frame pairs/s", "ms_per_batch": round(el / reps * 1e3, 3),
+           "plain_path_value": round(64 * reps / el_plain, 3),
+           "speedup_vs_plain_path": round(el_plain / el, 3),
+           "algorithmic_GB_per_batch": round(alg / 1e9, 3),
+           "effective_frac_hbm": round(alg / (el / reps) / 1e9 / HBM_PEAK_GBS, 4),
+           "iterate_achieved_GBs": round(it_ach, 1), "iterate_frac_hbm": round(it_ach / HBM_PEAK_GBS, 4),
+           "level0_achieved_GBs": round(ach, 1), "level0_frac_hbm": round(ach / HBM_PEAK_GBS, 4),
+           "level0_avg_launch_us": round(l0[1] / max(l0[2], 1) * 1e3, 3), "config": cfg}
+    # accuracy against ground truth, per pair, interior
+    tr = [truth_stats(g[0], g[1], p[2], p[3], wl.radius + 7 + 2) for g, p in zip(got, pairs)]
+    out["accuracy_vs_truth"] = {"rms_px_mean": round(float(np.mean([x["rms_px"] for x in tr])), 5),
+                                "max_px": round(max(x["max_px"] for x in tr), 4), "interior_margin_px": wl.radius + 9}
+    if cpu is not None:
+        es = [err_stats(g[0], g[1], f[0].astype(np.float64), f[1].astype(np.float64)) for g, f in zip(got, flows)]
+        out["parity"] = {"pairs": 64, "max_abs_px": max(e["max_abs_px"] for e in es),
+                         "rms_px_max_over_pairs": max(e["rms_px"] for e in es), "tolerance_px": 2e-2,
+                         "reference": "FP64 oracle rounded to float32"}
+        out["cpu_baseline"] = cpu
+    log(f"c4: {out['value']:.1f} pairs/s (plain path {out['plain_path_value']:.1f}), level 0 {ach:.0f} GB/s, "
+        f"parity {out.get('parity')}")
+    return out
 
 
 def bench_masked(torch, ofmi, dev, d1, d2, us, vs, wl, steps, warmup, unmasked_value):
@@ -289,14 +430,17 @@ def bench_gaussian(torch, ofmi, dev, d1, d2, us, vs, wl, steps, warmup, box_valu
             "config": tuned}
 
 
-def bench_serving(torch, ofmi, dev, workers, frames_per_stream):
-    """8 streams (sizes from {640x480, 1024^2, 2048^2}), Poisson arrivals at 250 frames/s each."""
+def bench_serving(torch, ofmi, dev, pool, workers, frames_per_stream, with_cpu=True):
+    """8 streams (sizes from {640x480, 1024^2, 2048^2}), Poisson arrivals at 250 frames/s each,
+    replayed in real time; one sampled pair per stream checked against the oracle."""
+    import numpy as np
     import synth
     from paper_1306_2461_amd.serve import GpuExecutor, Server, poisson_arrivals
     wl = synth.workload("c5")
     sizes = synth.particles.stream_sizes(8)
-    with cf.ProcessPoolExecutor(max_workers=min(8, workers)) as ex:
-        streams = list(ex.map(_gen_stream, [(s, frames_per_stream, sizes[s]) for s in range(8)]))
+    t = time.perf_counter()
+    streams = [synth.stream_frames_parallel(s, frames_per_stream, sizes[s], pool) for s in range(8)]
+    log(f"serving: generated 8 x {frames_per_stream} frames in {time.perf_counter() - t:.1f} s")
     arrivals = poisson_arrivals(streams, 250.0)
     exe = GpuExecutor(wl.levels, wl.radius, wl.iters, fp16=True, budget_bytes=8 << 30, device=dev)
     warm = Server(exe)                       # opens sessions, builds first pyramids, warms up
@@ -306,28 +450,101 @@ def bench_serving(torch, ofmi, dev, workers, frames_per_stream):
     warm.drain()
     for sid in range(8):
         warm.close_stream(sid)
-    srv = Server(exe)
+    # sampled pairs: the flow of frames (ts-1, ts) of every stream is kept; every other result
+    # is only timed and its output planes go back to the executor's pool
+    ts = frames_per_stream // 2
+    srv = Server(exe, keep=lambda r: r.frame is streams[r.stream_id][ts])
     st = srv.replay(arrivals, realtime=True)
+    sampled = []
+    for r in srv.done:
+        if r.has_flow and r.u is not None:
+            u = r.u.cpu().numpy() if hasattr(r.u, "cpu") else r.u
+            v = r.v.cpu().numpy() if hasattr(r.v, "cpu") else r.v
+            sampled.append((r.stream_id, ts - 1, u, v))
+    sampled.sort(key=lambda x: x[0])
     exe.close_all()
     st = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
     st.update({"streams": [f"{w}x{h}" for h, w in sizes], "frames_per_stream": frames_per_stream,
                "offered_frames_per_s": 2000})
+    if with_cpu and sampled:
+        jobs = [(streams[sid][t0], streams[sid][t0 + 1]) for sid, t0, _, _ in sampled]
+        flows, wall = cpu_pool(pool, workers, jobs, wl.levels, wl.radius, wl.iters)
+        es = [err_stats(u, v, f[0].astype(np.float64), f[1].astype(np.float64))
+              for (_, _, u, v), f in zip(sampled, flows)]
+        y = {}
+        tr = []
+        for sid, t0, u, v in sampled:
+            H, W = sizes[sid]
+            if (H, W) not in y:
+                y[(H, W)] = np.mgrid[0:H, 0:W].astype(np.float64)
+            gu, gv = synth.stream_field(H, W, t0)(y[(H, W)][1], y[(H, W)][0])
+            tr.append(truth_stats(u, v, gu, gv, wl.radius + 8 + 2))
+        st["parity"] = {"pairs": len(sampled), "max_abs_px": max(e["max_abs_px"] for e in es),
+                        "rms_px_max_over_pairs": max(e["rms_px"] for e in es), "tolerance_px": 2e-2}
+        st["accuracy_vs_truth"] = {"rms_px_mean": round(float(np.mean([x["rms_px"] for x in tr])), 5),
+                                   "max_px": round(max(x["max_px"] for x in tr), 4)}
+        st["cpu_baseline"] = {"value": round(len(jobs) / wall, 4), "unit": "frame pairs/s", "cores": workers,
+                              "kind": "oracle", "sample": f"{len(jobs)} served pairs, one per stream (frames "
+                                                          f"{ts - 1}->{ts}), FP64 numpy oracle",
+                              "cpu_seconds": round(sum(f[2] for f in flows), 2)}
     log(f"serving: {st}")
     return st
 
 
-def kernel_timing(torch, ofmi, plan, d1, d2, us, vs, steps):
-    """Average duration of each kernel from hipEvents recorded around its launches."""
-    n = len(d1)
-    plan.set_timing(True)
-    for i in range(steps):
-        plan.compute(d1[i % n], d2[i % n], us[i % n], vs[i % n])
-    torch.cuda.synchronize()
-    it = plan.read_timing(ofmi.OF_KERNEL_ITERATE)
-    rd = plan.read_timing(ofmi.OF_KERNEL_REDUCE)
-    plan.set_timing(False)
-    return it, rd
+def bench_table1(torch, dev, pool):
+    """Table 1's experiment in shape (Sec. 3.3): the paper's region of interest 1792x384, r = 10,
+    n_lev in {1, 3, 4}, n_iter 1..7; fields/s, error against the (4, 7) field and against the
+    ground truth (interior), FP32 plain path with default launch configuration."""
+    import numpy as np
+    from paper_1306_2461_amd.sweep import table1_sweep
+    I1, I2, gu, gv = pool.submit(_gen, ("t1", 0)).result()
+    res = table1_sweep(torch.from_numpy(I1).to(dev), torch.from_numpy(I2).to(dev), levels=(1, 3, 4),
+                       reps=50, truth=(torch.from_numpy(np.ascontiguousarray(gu)).to(dev),
+                                       torch.from_numpy(np.ascontiguousarray(gv)).to(dev)))
+    out = {"workload": "1792x384 uint8 particle pair (step shear layer + eddy, max 10 px), r = 10, FP32",
+           "n_iter": list(range(1, 8))}
+    for L, row in res.items():
+        out[f"n_lev_{L}"] = {k: [round(x, 4) for x in v] for k, v in row.items()}
+    log("table1: " + ", ".join(f"L{L} fields/s {[round(x) for x in r['fields_per_s']]}" for L, r in res.items()))
+    return out
 
+
+def probe(args):
+    """Fixed short run for counter collection: a 256 MiB device copy (calibration of the
+    FETCH_SIZE / WRITE_SIZE counters), then 5 plain FP32 pairs (eager launches, so every launch
+    is a kernel dispatch of its own) at PROBE_CONFIG, then one 16-pair batch at
+    PROBE_BATCH_CONFIG; no timing, no JSON line."""
+    import synth
+    import torch
+    import paper_1306_2461_amd as ofmi
+    dev = torch.device("cuda", 0)
+    src = torch.ones(1 << 26, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    pairs = [synth.make_pair(WORKLOAD, i)[:2] for i in range(4)]
+    d1 = [torch.from_numpy(p[0]).to(dev) for p in pairs]
+    d2 = [torch.from_numpy(p[1]).to(dev) for p in pairs]
+    wl = synth.workload(WORKLOAD)
+    plan = ofmi.Plan(wl.H, wl.W, wl.levels, wl.radius, wl.iters, device=dev, graph=False)
+    plan.set_config(PROBE_CONFIG)
+    u, v = plan.compute(d1[0], d2[0])
+    for i in range(4):
+        plan.compute(d1[i], d2[i], u, v)
+    torch.cuda.synchronize()
+    log(f"probe: plain path done, kernel sources {kernel_source_hash()}")
+    plan.close()
+    b = ofmi.Batch([(wl.H, wl.W)] * 16, wl.levels, wl.radius, wl.iters, device=dev, graph=False)
+    b.set_config(PROBE_BATCH_CONFIG)
+    bu, bv = b.outputs()
+    b.compute([d1[i % 4] for i in range(16)], [d2[i % 4] for i in range(16)], bu, bv)
+    torch.cuda.synchronize()
+    log("probe: 16-pair batch done")
+    b.close()
+
+
+# --------------------------------------------------------------------------- main
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -337,46 +554,69 @@ def main():
     ap.add_argument("--pairs", type=int, default=16, help="distinct resident pairs rotated over")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--cpu-pairs", type=int, default=8)
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched, mixed-batch and serving runs")
-    ap.add_argument("--serve-frames", type=int, default=24)
+    ap.add_argument("--no-extra", action="store_true", help="skip the c1, batched, mixed-batch, window, mask "
+                                                            "and serving runs")
+    ap.add_argument("--main-only", action="store_true",
+                    help="only the 1024x1024 FP32 and FP16 plain-path measurements (for profilers)")
+    ap.add_argument("--serve-frames", type=int, default=200)
     ap.add_argument("--c4-only", action="store_true",
                     help="only the 64-pair mixed batch (for profilers): autotune, 3 timed replays, no JSON line")
     ap.add_argument("--probe", action="store_true",
-                    help="short fixed run for profilers (4 plain pairs), no timing, no JSON line")
+                    help="short fixed run for profilers (5 plain pairs, one batch), no timing, no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); pairs are "
               "independent, so a multi-GPU run would deal pairs to GPUs with no exchange", file=sys.stderr)
         sys.exit(2)
-
     if args.probe:
         probe(args)
         return
+    if args.main_only:
+        args.no_extra = True
+        args.no_cpu_baseline = True
+        args.no_parity = True
+
+    import numpy as np
+    import synth
+    workers = host_workers()
+    # Worker processes are forked now, before anything touches the GPU, and reused throughout.
+    pool = cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork"))
+    list(pool.map(_noop, range(workers)))
+
     if args.c4_only:
         import torch
         import paper_1306_2461_amd as ofmi
         ofmi.load()
         dev = torch.device("cuda", 0)
         torch.cuda.set_device(dev)
-        bench_c4(torch, ofmi, dev, max(1, min(16, len(os.sched_getaffinity(0)))), 3)
+        bench_c4(torch, ofmi, dev, pool, workers, 3, with_cpu=False)
+        pool.shutdown()
         return
 
-    import numpy as np
-    import synth
     wl = synth.workload(WORKLOAD)
     L, r, K = wl.levels, wl.radius, wl.iters
-    workers = max(1, min(16, len(os.sched_getaffinity(0))))
     t = time.perf_counter()
-    with cf.ProcessPoolExecutor(max_workers=min(workers, args.pairs)) as ex:
-        pairs = list(ex.map(_gen, range(args.pairs)))
-    log(f"generated {len(pairs)} pairs in {time.perf_counter() - t:.1f} s")
+    pairs = list(pool.map(_gen, [(WORKLOAD, i) for i in range(args.pairs)]))
+    c1_pairs = [] if args.no_extra else list(pool.map(_gen, [("c1", i) for i in range(16)]))
+    log(f"generated {len(pairs)} + {len(c1_pairs)} pairs in {time.perf_counter() - t:.1f} s")
 
+    # CPU baseline (the oracle on this host's cores) and the oracle flows for parity
     cpu = None
-    if not args.no_cpu_baseline:
-        n_cpu = min(args.cpu_pairs, workers)
-        cpu = cpu_baseline(pairs, L, r, K, args.cpu_pairs, n_cpu)
-        log(f"cpu baseline: {cpu['value']:.3f} pairs/s on {cpu['cores']} processes")
+    oracle_c2 = None
+    oracle_c1 = None
+    if not args.no_cpu_baseline or not args.no_parity:
+        n_cpu = workers if not args.no_cpu_baseline else 1
+        flows, wall = cpu_pool(pool, workers, [(p[0], p[1]) for p in pairs[:n_cpu]], L, r, K)
+        oracle_c2 = flows[0]
+        if not args.no_cpu_baseline:
+            cpu = {"value": round(n_cpu / wall, 4), "unit": "frame pairs/s", "cores": workers, "kind": "oracle",
+                   "sample": f"{n_cpu} distinct 1024x1024 pairs of the bench workload, FP64 numpy oracle, one pair "
+                             f"per worker process ({workers} processes, 1 thread each)",
+                   "single_pair_s": round(float(np.mean([f[2] for f in flows])), 3),
+                   "cpu_seconds": round(sum(f[2] for f in flows), 2), "cpu_model": cpu_model()}
+            log(f"cpu baseline: {cpu['value']:.3f} pairs/s on {workers} processes ({cpu['cpu_model']})")
+        if c1_pairs:
+            oracle_c1 = cpu_pool(pool, workers, [(c1_pairs[0][0], c1_pairs[0][1])], 3, 4, 4)[0][0]
 
     import torch
     import paper_1306_2461_amd as ofmi
@@ -390,54 +630,48 @@ def main():
     torch.cuda.synchronize()
 
     results = {}
+    margin = r + 10 + 2
     for tag, fp16 in (("fp32", False), ("fp16", True)):
-        plan = ofmi.Plan(wl.H, wl.W, L, r, K, fp16=fp16, device=dev)
-        tuned = plan.autotune(d1[0], d2[0], us[0], vs[0], reps=3)
-        log(f"{tag}: autotuned launch configuration {tuned}")
-        el = time_plan(torch, plan, d1, d2, us, vs, args.steps, args.warmup)
-        lat = latency(torch, plan, d1, d2, us, vs, min(200, args.steps))
-        it, rd = kernel_timing(torch, ofmi, plan, d1, d2, us, vs, min(100, args.steps))
-        err = None
-        if not args.no_parity:
-            import oracle
-            plan.compute(d1[0], d2[0], us[0], vs[0])
-            torch.cuda.synchronize()
-            ou, ov = oracle.flow(pairs[0][0], pairs[0][1], L, r, K)
-            err = float(max(np.abs(us[0].cpu().numpy() - ou).max(), np.abs(vs[0].cpu().numpy() - ov).max()))
-        graphed = None
+        plan, res = bench_plain(torch, ofmi, dev, wl, d1, d2, us, vs, fp16, args.steps, args.warmup, tag)
+        plan.compute(d1[0], d2[0], us[0], vs[0])
+        torch.cuda.synchronize()
+        u, v = us[0].cpu().numpy(), vs[0].cpu().numpy()
+        res["truth"] = truth_stats(u, v, pairs[0][2], pairs[0][3], margin)
+        if oracle_c2 is not None:
+            res["parity"] = err_stats(u, v, oracle_c2[0].astype(np.float64), oracle_c2[1].astype(np.float64))
         if tag == "fp32":
             pg = ofmi.Plan(wl.H, wl.W, L, r, K, fp16=fp16, device=dev, graph=True)
-            pg.set_config(tuned)
-            graphed = args.steps / time_plan(torch, pg, d1, d2, us, vs, args.steps, args.warmup)
+            pg.set_config(res["cfg"])
+            res["graphed"] = args.steps / time_plan(torch, pg, d1, d2, us, vs, args.steps, args.warmup)
             pg.close()
-        results[tag] = {"el": el, "lat": lat, "it": it, "rd": rd, "err": err, "graphed": graphed,
-                        "cfg": tuned}
         plan.close()
-        log(f"{tag}: {args.steps / el:.1f} pairs/s, {el / args.steps * 1e3:.4f} ms/pair, "
-            f"latency {lat}, iterate kernel avg {it[0] / max(it[1], 1) * 1e3:.2f} us over {it[1]} launches, "
-            f"max |err| {err}")
+        results[tag] = res
 
     extra = {}
     if not args.no_extra:
-        for name, fn in (("batched_1024_fp32", lambda: bench_batched(torch, ofmi, dev, pairs, wl, False, 20, "fp32")),
-                         ("batched_1024_fp16", lambda: bench_batched(torch, ofmi, dev, pairs, wl, True, 20, "fp16")),
-                         ("mixed_batch_64", lambda: bench_c4(torch, ofmi, dev, workers, 5)),
-                         ("gaussian_window_1024_fp32", lambda: bench_gaussian(torch, ofmi, dev, d1, d2, us, vs, wl,
-                                                                             args.steps, args.warmup,
-                                                                             args.steps / results["fp32"]["el"])),
-                         ("masked_1024_fp32", lambda: bench_masked(torch, ofmi, dev, d1, d2, us, vs, wl,
-                                                                   args.steps, args.warmup,
-                                                                   args.steps / results["fp32"]["el"])),
-                         ("serving_8_streams", lambda: bench_serving(torch, ofmi, dev, workers, args.serve_frames))):
+        v32 = args.steps / results["fp32"]["el"]
+        runs = (("c1_256_fp32", lambda: bench_c1(torch, ofmi, dev, c1_pairs, oracle_c1, args.steps, args.warmup)),
+                ("batched_1024_fp32", lambda: bench_batched(torch, ofmi, dev, d1, d2, wl, False, 20, "fp32")),
+                ("batched_1024_fp16", lambda: bench_batched(torch, ofmi, dev, d1, d2, wl, True, 20, "fp16")),
+                ("mixed_batch_64", lambda: bench_c4(torch, ofmi, dev, pool, workers, 5, not args.no_cpu_baseline)),
+                ("table1_sweep", lambda: bench_table1(torch, dev, pool)),
+                ("gaussian_window_1024_fp32", lambda: bench_gaussian(torch, ofmi, dev, d1, d2, us, vs, wl,
+                                                                     args.steps, args.warmup, v32)),
+                ("masked_1024_fp32", lambda: bench_masked(torch, ofmi, dev, d1, d2, us, vs, wl, args.steps,
+                                                          args.warmup, v32)),
+                ("serving_8_streams", lambda: bench_serving(torch, ofmi, dev, pool, workers, args.serve_frames,
+                                                            not args.no_cpu_baseline)))
+        for name, fn in runs:
             try:
                 extra[name] = fn()
             except Exception as e:  # report, keep the main line
                 extra[name] = {"error": repr(e)}
                 log(f"{name} failed: {e!r}")
+    pool.shutdown()
 
-    r32 = results["fp32"]
-    ms_it, n_it, units_it, bytes_it = r32["it"]
-    achieved = bytes_it / ms_it / 1e6 if ms_it > 0 else 0.0
+    r32, r16 = results["fp32"], results["fp16"]
+    dom = r32["dominant"]
+    traffic = measured_traffic() if dom["level"] == 0 else None
     line = {
         "metric": METRIC,
         "value": round(args.steps / r32["el"], 3),
@@ -457,16 +691,25 @@ def main():
                    "distinct_pairs": args.pairs, "launch_config": r32["cfg"]},
         "latency_ms": r32["lat"],
         "graph_replay_value": round(r32["graphed"], 3),
-        "max_abs_err_px": r32["err"],
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "lk_iter (fused iteration)", "launches": n_it,
-                     "avg_launch_us": round(ms_it / max(n_it, 1) * 1e3, 3),
-                     "bytes_per_launch": round(bytes_it / max(n_it, 1))},
-        "fp16": {"value": round(args.steps / results["fp16"]["el"], 3),
-                 "ms_per_step": round(results["fp16"]["el"] / args.steps * 1e3, 5),
-                 "latency_ms": results["fp16"]["lat"], "max_abs_err_px": results["fp16"]["err"],
-                 "iterate_avg_launch_us": round(results["fp16"]["it"][0] / max(results["fp16"]["it"][1], 1) * 1e3, 3)},
+        "parity": dict(r32.get("parity", {}), tolerance_px=1e-3, fp32_floor_max_px=floor_max("c2")),
+        "accuracy_vs_truth": r32["truth"],
+        "roofline": {"bound": "hbm", "achieved": dom["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": dom["frac"], "traffic": traffic,
+                     "kernel": f"lk_iter_strip, level {dom['level']} ({dom['H']}x{dom['W']}, "
+                               f"{'uint8' if dom['level'] == 0 else 'float32'} frames), the largest share of the "
+                               f"iteration time",
+                     "avg_launch_us": dom["avg_launch_us"], "bytes_per_launch": dom["bytes_per_launch"],
+                     "launches": dom["launches"],
+                     "timing": "one hipEvent pair around each level's 4 back-to-back iteration launches on the launch "
+                               "stream, host enqueueing ahead; algorithmic bytes = pixels x (2 frame elements + 16 B)",
+                     "per_level": r32["per_level"], "pyramid": r32["pyramid"]},
+        "fp16": {"value": round(args.steps / r16["el"], 3),
+                 "ms_per_step": round(r16["el"] / args.steps * 1e3, 5),
+                 "speedup_vs_fp32": round(r32["el"] / r16["el"], 4),
+                 "latency_ms": r16["lat"],
+                 "parity": dict(r16.get("parity", {}), tolerance_px=2e-2, fp16_floor_max_px=floor_max("c3_fp16")),
+                 "accuracy_vs_truth": r16["truth"],
+                 "per_level": r16["per_level"], "launch_config": r16["cfg"]},
         "cpu_baseline": cpu,
     }
     line.update(extra)

@@ -14,6 +14,11 @@ from .particles import (  # noqa: F401
     render,
     workload,
     batch_items,
+    stream_field,
+    stream_frame,
     stream_frames,
+    stream_frames_parallel,
+    stream_particles,
+    stream_scale,
     table1_pair,
 )

@@ -186,9 +186,21 @@ def make_pair(name: str, item: int = 0):
     return I1, I2, gu, gv
 
 
-def table1_pair(item: int = 0):
-    """Pair at the paper's region of interest (1792x384), used by the Table-1 style sweep."""
-    return make_pair("t1", item)
+def table1_pair(item: int = 0, scale: float = 1.0):
+    """Pair at the paper's region of interest (1792x384), used by the Table-1 style sweep.
+    ``scale`` multiplies the displacement field (scale 0.25 keeps it under 3 px, where eq. 1
+    allows a single level, the paper's "n_lev -> 0" case)."""
+    if scale == 1.0:
+        return make_pair("t1", item)
+    wl = WORKLOADS["t1"]
+
+    def field(x, y):
+        du, dv = _field_t1(x, y)
+        return scale * du, scale * dv
+
+    rngs = _rngs(wl.index, 1000 + item)
+    I1, I2, gu, gv, dmax = _pair_from_field(field, wl.H, wl.W, wl.rho, wl.sigma, rngs)
+    return I1, I2, gu, gv
 
 
 # --------------------------------------------------------------------------- batch (c4)
@@ -250,7 +262,9 @@ def stream_sizes(n_streams: int = 8):
     return [C5_SIZES[int(k)] for k in rng.integers(0, len(C5_SIZES), size=n_streams)]
 
 
-def _stream_field(H, W, t):
+def _stream_raw(H, W, t):
+    """Unscaled displacement of stream frame t: a tanh shear layer whose centre line oscillates
+    (period 50 frames) plus a Lamb-Oseen vortex convecting downstream."""
     yc = H / 2 + 0.1 * H * math.sin(2 * math.pi * t / 50.0)
     delta = 0.04 * H
     xv = (0.25 * W + 0.5 * t * 4.0) % W
@@ -261,8 +275,15 @@ def _stream_field(H, W, t):
         du, dv = lamb_oseen(x, y, xv, yc - 0.1 * H, rc, 1.0, -1.0)
         return su + du, dv
 
-    scale = 8.0 / _grid_max(raw, H, W)
+    return raw
 
+
+def stream_scale(H: int, W: int, t: int) -> float:
+    """Factor that makes the largest displacement of frame t over the pixel grid 8 px."""
+    return 8.0 / _grid_max(_stream_raw(H, W, t), H, W)
+
+
+def _scaled(raw, scale):
     def field(x, y):
         du, dv = raw(x, y)
         return scale * du, scale * dv
@@ -270,25 +291,73 @@ def _stream_field(H, W, t):
     return field
 
 
-def stream_frames(stream: int, n_frames: int = 200, size=None) -> Iterator[tuple[np.ndarray, np.ndarray, np.ndarray]]:
-    """Yield ``(frame, gt_u, gt_v)`` of one stream; ``gt`` is the displacement to the next frame."""
+def stream_field(H: int, W: int, t: int, scale: float | None = None) -> Field:
+    """Displacement from stream frame t to frame t + 1 (max 8 px over the grid)."""
+    return _scaled(_stream_raw(H, W, t), stream_scale(H, W, t) if scale is None else scale)
+
+
+def stream_particles(stream: int, n_frames: int, size=None, scales=None):
+    """Particle states (x, y, amplitude) of frames 0 .. n_frames-1 of one stream: frame t + 1
+    moves every particle of frame t by stream_field(t) at its position; particles leaving the
+    extended domain are re-seeded uniformly (a sequential, cheap step).  ``scales``: the
+    per-frame scales if already computed (``stream_scale``)."""
     wl = WORKLOADS["c5"]
     H, W = stream_sizes()[stream] if size is None else size
     rngs = _rngs(wl.index, stream)
     margin = 8 + int(math.ceil(4.0 * wl.sigma))
     xp, yp, amp = _particles(rngs[0], rngs[1], H, W, wl.rho, margin)
-    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    out = []
     for t in range(n_frames):
-        field = _stream_field(H, W, t)
-        frame = render(xp, yp, amp, H, W, wl.sigma, rngs[2])
-        gu, gv = field(x, y)
-        yield frame, gu, gv
-        du, dv = field(xp, yp)
+        out.append((xp, yp, amp))
+        if t + 1 == n_frames:
+            break
+        sc = stream_scale(H, W, t) if scales is None else scales[t]
+        du, dv = stream_field(H, W, t, sc)(xp, yp)
         xp = xp + du
         yp = yp + dv
-        out = (xp < -margin) | (xp >= W + margin) | (yp < -margin) | (yp >= H + margin)
-        k = int(out.sum())
+        amp = amp.copy()
+        gone = (xp < -margin) | (xp >= W + margin) | (yp < -margin) | (yp >= H + margin)
+        k = int(gone.sum())
         if k:
-            xp[out] = rngs[4].uniform(-margin, W + margin, size=k)
-            yp[out] = rngs[4].uniform(-margin, H + margin, size=k)
-            amp[out] = rngs[4].uniform(AMP_LO, AMP_HI, size=k)
+            xp[gone] = rngs[4].uniform(-margin, W + margin, size=k)
+            yp[gone] = rngs[4].uniform(-margin, H + margin, size=k)
+            amp[gone] = rngs[4].uniform(AMP_LO, AMP_HI, size=k)
+    return out
+
+
+def stream_frame(stream: int, t: int, state, size) -> np.ndarray:
+    """Render frame t of a stream from its particle state; the noise of every frame has a
+    seed of its own, so frames can be rendered in any order or in parallel."""
+    wl = WORKLOADS["c5"]
+    H, W = size
+    xp, yp, amp = state
+    noise = np.random.default_rng(np.random.SeedSequence([2461, wl.index, stream, 1, t]))
+    return render(xp, yp, amp, H, W, wl.sigma, noise)
+
+
+def stream_frames(stream: int, n_frames: int = 200, size=None) -> Iterator[tuple[np.ndarray, np.ndarray, np.ndarray]]:
+    """Yield ``(frame, gt_u, gt_v)`` of one stream; ``gt`` is the displacement to the next frame."""
+    H, W = stream_sizes()[stream] if size is None else size
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    for t, state in enumerate(stream_particles(stream, n_frames, (H, W))):
+        gu, gv = stream_field(H, W, t)(x, y)
+        yield stream_frame(stream, t, state, (H, W)), gu, gv
+
+
+def _render_job(args):
+    stream, t, state, size = args
+    return stream_frame(stream, t, state, size)
+
+
+def _scale_job(args):
+    return stream_scale(*args)
+
+
+def stream_frames_parallel(stream: int, n_frames: int, size, pool) -> list:
+    """The frames of ``stream_frames`` (same bytes), rendered over a process pool (an
+    ``Executor``): per-frame scales in parallel, the advection in this process, then the
+    renders in parallel.  Ground truth is left out (``stream_field`` gives it per frame)."""
+    H, W = size
+    scales = list(pool.map(_scale_job, [(H, W, t) for t in range(n_frames)]))
+    states = stream_particles(stream, n_frames, size, scales)
+    return list(pool.map(_render_job, [(stream, t, st, size) for t, st in enumerate(states)]))

@@ -68,3 +68,16 @@ def test_batch_and_stream_shapes():
     frames = list(synth.stream_frames(0, 3, size=(64, 80)))
     assert len(frames) == 3 and frames[0][0].shape == (64, 80)
     assert abs(np.hypot(frames[1][1], frames[1][2]).max() - 8.0) < 1e-6
+
+
+def test_stream_frames_render_in_parallel_with_the_same_bytes():
+    import concurrent.futures as cf
+    seq = list(synth.stream_frames(3, 5, size=(72, 90)))
+    with cf.ThreadPoolExecutor(3) as ex:
+        par = synth.stream_frames_parallel(3, 5, (72, 90), ex)
+    assert all(np.array_equal(a[0], b) for a, b in zip(seq, par))
+    # ground truth of frame t is the field that moves frame t's particles to frame t + 1
+    y, x = np.mgrid[0:72, 0:90].astype(np.float64)
+    gu, gv = synth.stream_field(72, 90, 2)(x, y)
+    assert np.array_equal(gu, seq[2][1]) and np.array_equal(gv, seq[2][2])
+    assert abs(np.hypot(gu, gv).max() - 8.0) < 1e-9
