@@ -159,6 +159,45 @@ def _oracle_job(args):
     return u.astype(np.float32), v.astype(np.float32), time.perf_counter() - t
 
 
+def _floor_job(args):
+    """One float32 realisation of the oracle's operation order (tests/floor_util.py) of a pair:
+    its per-pixel departure from the FP64 flow is a sample of the rounding floor."""
+    import numpy as np
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import floor_util
+    import oracle
+    I1, I2, L, r, K, k, storage, ou, ov = args
+    f1, f2, tr = floor_util.realisations(I1, I2)[k]
+    uk, vk = oracle.flow(f1, f2, L, r, K, dtype=np.float32, coords="split", storage=storage)
+    if tr:
+        uk, vk = vk.T, uk.T
+    return np.maximum(np.abs(uk - ou), np.abs(vk - ov)).astype(np.float32)
+
+
+def floor_stats(pool, pairs, flows, gpu, L, r, K, tol, storage):
+    """Per-pixel parity of GPU flows against the oracle with the FP32 rounding floor of each
+    pair (five float32 realisations, window-dilated, as the GPU tests use): pixels over the
+    tolerance, and whether each is within tol + 3 x floor."""
+    import numpy as np
+    from scipy import ndimage
+    jobs = [(p[0], p[1], L, r, K, k, storage, f[0].astype(np.float64), f[1].astype(np.float64))
+            for p, f in zip(pairs, flows) for k in range(5)]
+    deps = list(pool.map(_floor_job, jobs))
+    over = bound = 0
+    worst = 0.0
+    for i, ((u, v), f) in enumerate(zip(gpu, flows)):
+        fl = np.max(deps[5 * i:5 * i + 5], axis=0)
+        fl = ndimage.maximum_filter(fl, size=2 * r + 1, mode="nearest").astype(np.float64)
+        d = np.maximum(np.abs(u - f[0].astype(np.float64)), np.abs(v - f[1].astype(np.float64)))
+        o = d > tol
+        over += int(o.sum())
+        bound += int((d > tol + 3.0 * fl).sum())
+        if o.any():
+            worst = max(worst, float(np.max((d[o] - tol) / np.maximum(fl[o], 1e-30))))
+    return {"px_over_tolerance": over, "px_beyond_tol_plus_3x_floor": bound,
+            "max_excess_over_floor": round(worst, 3)}
+
+
 def cpu_pool(pool, workers, pairs, L, r, K):
     """The oracle over `pairs` [(I1, I2), ...] on the pool, longest first; returns the flows in
     input order, the wall time and the per-pair CPU times."""
@@ -481,6 +520,9 @@ def bench_serving(torch, ofmi, dev, pool, workers, frames_per_stream, with_cpu=T
             tr.append(truth_stats(u, v, gu, gv, wl.radius + 8 + 2))
         st["parity"] = {"pairs": len(sampled), "max_abs_px": max(e["max_abs_px"] for e in es),
                         "rms_px_max_over_pairs": max(e["rms_px"] for e in es), "tolerance_px": 2e-2}
+        import numpy as np
+        st["parity"].update(floor_stats(pool, jobs, flows, [(u, v) for _, _, u, v in sampled], wl.levels,
+                                        wl.radius, wl.iters, 2e-2, np.float16))
         st["accuracy_vs_truth"] = {"rms_px_mean": round(float(np.mean([x["rms_px"] for x in tr])), 5),
                                    "max_px": round(max(x["max_px"] for x in tr), 4)}
         st["cpu_baseline"] = {"value": round(len(jobs) / wall, 4), "unit": "frame pairs/s", "cores": workers,
