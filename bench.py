@@ -480,11 +480,18 @@ def bench_serving(torch, ofmi, dev, pool, workers, frames_per_stream, with_cpu=T
     t = time.perf_counter()
     streams = [synth.stream_frames_parallel(s, frames_per_stream, sizes[s], pool) for s in range(8)]
     log(f"serving: generated 8 x {frames_per_stream} frames in {time.perf_counter() - t:.1f} s")
-    arrivals = poisson_arrivals(streams, 250.0)
+    # frames arrive in pinned host memory, as from a camera driver's DMA buffers (one pinned block
+    # per stream); the executor copies them to the device on its copy stream
+    pinned = []
+    for s in range(8):
+        blk = torch.empty((frames_per_stream,) + sizes[s], dtype=torch.uint8, pin_memory=True)
+        blk.numpy()[...] = np.stack(streams[s])
+        pinned.append([blk[t] for t in range(frames_per_stream)])
+    arrivals = poisson_arrivals(pinned, 250.0)
     exe = GpuExecutor(wl.levels, wl.radius, wl.iters, fp16=True, budget_bytes=8 << 30, device=dev)
     warm = Server(exe)                       # opens sessions, builds first pyramids, warms up
     for sid in range(8):
-        for f in streams[sid][:2]:
+        for f in pinned[sid][:2]:
             warm.submit(sid, f)
     warm.drain()
     for sid in range(8):
@@ -492,7 +499,7 @@ def bench_serving(torch, ofmi, dev, pool, workers, frames_per_stream, with_cpu=T
     # sampled pairs: the flow of frames (ts-1, ts) of every stream is kept; every other result
     # is only timed and its output planes go back to the executor's pool
     ts = frames_per_stream // 2
-    srv = Server(exe, keep=lambda r: r.frame is streams[r.stream_id][ts])
+    srv = Server(exe, keep=lambda r: r.frame is pinned[r.stream_id][ts])
     st = srv.replay(arrivals, realtime=True)
     sampled = []
     for r in srv.done:

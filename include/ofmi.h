@@ -71,10 +71,11 @@ typedef enum {
 #define OF_FLAG_NORMALIZE    (1u << 3) /* plans only: equalise both frames locally (see
                                           of_normalize; radius OF_NORMALIZE_RADIUS, eps
                                           OF_NORMALIZE_EPS) before the pyramid */
-#define OF_FLAG_GAUSSIAN_WINDOW (1u << 4) /* plans only: weight the window sums by separable
-                                          Gaussian taps exp(-d^2 / (2 sigma^2)), sigma = r/2,
-                                          over the same (2r+1)^2 support (a variant of the
-                                          unweighted interrogation window of Sec. 2.4) */
+#define OF_FLAG_GAUSSIAN_WINDOW (1u << 4) /* plans, batches and servers: weight the window
+                                          sums by separable Gaussian taps
+                                          exp(-d^2 / (2 sigma^2)), sigma = r/2, over the same
+                                          (2r+1)^2 support (a variant of the unweighted
+                                          interrogation window of Sec. 2.4) */
 #define OF_FLAG_GRAPH        (1u << 5) /* plans only: capture the schedule into a hipGraph
                                           per pointer tuple and replay it; plans launch kernels
                                           one by one otherwise (batches replay graphs unless
@@ -295,6 +296,16 @@ OF_API of_status of_batch_set_config(of_batch* b, const int* bands, const int* g
 OF_API of_status of_batch_autotune(of_batch* b, const void* const* I1, const void* const* I2,
                                    float* const* u, float* const* v, void* stream, int reps);
 
+/* Region-of-interest masks of a batch (the masking lever of Sec. 3.3, as of_plan_set_mask):
+ * masks is a HOST array of n DEVICE pointers, masks[i] an H[i] x W[i] uint8 plane (nonzero =
+ * compute) or NULL for an unmasked pair; masks == NULL removes every mask.  The batch builds
+ * each masked pair's mask pyramid and its tile flags (refreshed when the tile heights change):
+ * tiles without an unmasked pixel are skipped (zero flow written), masked pixels get zero flow,
+ * results equal of_compute of a plan with the same mask, bitwise.  Set-up call: waits for the
+ * device, drops the captured graphs, allocates the mask memory (freed by of_batch_destroy).
+ * Errors: OF_EINVAL (NULL batch), OF_EHIP. */
+OF_API of_status of_batch_set_masks(of_batch* b, const uint8_t* const* masks, void* stream);
+
 /* Kernel timing of a batch, as of_plan_set_timing / of_plan_read_timing. */
 OF_API of_status of_batch_set_timing(of_batch* b, int enable);
 OF_API of_status of_batch_read_timing(of_batch* b, int kernel, double* total_ms,
@@ -326,7 +337,7 @@ typedef struct of_session of_session;
 /* Device bytes one session of an H x W stream keeps resident (two frame pyramids including
  * level 0, four level-0 FP32 field planes); also the workspace size of of_session_create and
  * of_server_open_ex.  0 on invalid parameters, including the plan-only flags
- * OF_FLAG_NORMALIZE, OF_FLAG_GAUSSIAN_WINDOW and OF_FLAG_GRAPH. */
+ * OF_FLAG_NORMALIZE and OF_FLAG_GRAPH. */
 OF_API size_t of_session_bytes(int H, int W, int levels, int radius, int iters, unsigned flags);
 
 /* Server for streams sharing levels, radius, iters and flags (OF_FLAG_NO_GRAPH ignored).
@@ -365,6 +376,14 @@ OF_API of_status of_server_push(of_server* s, of_session* const* sessions, int n
  * allocates).  Returns NULL on invalid parameters or allocation failure. */
 OF_API of_session* of_session_create(int H, int W, int levels, int radius, int iters,
                                      unsigned flags, void* workspace, size_t workspace_bytes);
+
+/* Region-of-interest mask of one stream (as of_plan_set_mask; Sec. 3.3): `mask` is a DEVICE
+ * H x W uint8 plane of the session's size (nonzero = compute), NULL removes it.  Every later
+ * push computes that session's flow with the mask: masked pixels get zero flow, tiles without
+ * an unmasked pixel are skipped; equal to a plan with the same mask, bitwise.  Set-up call:
+ * waits for the device, allocates the mask pyramid and tile flags (freed with the session).
+ * Errors: OF_EINVAL (NULL session), OF_EHIP. */
+OF_API of_status of_session_set_mask(of_session* session, const uint8_t* mask, void* stream);
 
 /* of_server_push for one session. */
 OF_API of_status of_session_push(of_session* session, const void* frame, float* u, float* v,

@@ -65,6 +65,8 @@ SIGNATURES = {
                                       ctypes.POINTER(ctypes.c_longlong),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "of_batch_destroy": (None, [_vp]),
+    "of_batch_set_masks": (_c_int, [_vp, _VPP, _vp]),
+    "of_session_set_mask": (_c_int, [_vp, _vp, _vp]),
     "of_session_bytes": (_c_size, [_c_int, _c_int, _c_int, _c_int, _c_int, _c_uint]),
     "of_server_create": (_vp, [_c_int, _c_int, _c_int, _c_uint, _c_size]),
     "of_server_open": (_vp, [_vp, _c_int, _c_int]),

@@ -178,14 +178,15 @@ class Batch:
     """
 
     def __init__(self, sizes, levels, radius, iters, fp16=False, input_f32=False, device=None,
-                 graph=True):
+                 graph=True, gaussian_window=False):
         import ctypes
         lib = B.load()
         self.sizes = [(int(h), int(w)) for h, w in sizes]
         self.n = len(self.sizes)
         self.levels, self.radius, self.iters = levels, radius, iters
         self.flags = ((B.OF_FLAG_FP16_STORAGE if fp16 else 0) | (B.OF_FLAG_INPUT_F32 if input_f32 else 0)
-                      | (0 if graph else B.OF_FLAG_NO_GRAPH))
+                      | (0 if graph else B.OF_FLAG_NO_GRAPH)
+                      | (B.OF_FLAG_GAUSSIAN_WINDOW if gaussian_window else 0))
         self.frame_dtype = torch.float32 if input_f32 else torch.uint8
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self._H = (ctypes.c_int * self.n)(*[h for h, _ in self.sizes])
@@ -251,6 +252,23 @@ class Batch:
         grid = (ctypes.c_int * self.levels)(*cfg["grid"])
         variant = (ctypes.c_int * self.levels)(*cfg.get("variant", [-1] * self.levels))
         B.check(B.load().of_batch_set_config(self._h, bands, grid, variant), "of_batch_set_config")
+
+    def set_masks(self, masks, stream=None):
+        """Region-of-interest masks per pair (uint8 device tensors of each pair's size, nonzero =
+        compute, or None for an unmasked pair); ``masks=None`` removes them."""
+        if masks is None:
+            arr = None
+        else:
+            ptrs = []
+            for i, m in enumerate(masks):
+                if m is None:
+                    ptrs.append(0)
+                else:
+                    _check_frame(m, self.sizes[i][0], self.sizes[i][1], torch.uint8, self.device, f"mask[{i}]")
+                    ptrs.append(m.data_ptr())
+            arr, self._mask_keep = B.ptr_array(ptrs)
+        B.check(B.load().of_batch_set_masks(self._h, arr, _stream_handle(self.device, stream)),
+                "of_batch_set_masks")
 
     def set_timing(self, enable):
         """As Plan.set_timing."""

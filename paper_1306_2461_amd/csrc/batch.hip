@@ -60,6 +60,15 @@ struct of_batch {
   bool slot_used[kArgSlots] = {};
   int eager_next = 0;
   std::vector<std::pair<std::vector<uintptr_t>, int>> graph_slot;   // pointer set -> slot
+  // Masks (of_batch_set_masks): per pair, its mask pyramid in `maskbuf` (offsets per level,
+  // SIZE_MAX = unmasked pair), a host copy for the tile flags, and the flags of the current
+  // tile heights in `flagbuf`.
+  uint8_t* maskbuf = nullptr;
+  uint8_t* flagbuf = nullptr;
+  size_t flag_cap = 0;
+  std::vector<std::vector<size_t>> mask_off;      // [pair][level]
+  std::vector<std::vector<size_t>> flag_off;      // [pair][level]
+  std::vector<std::vector<std::vector<uint8_t>>> hmask;   // [pair][level] host copies
   KernelTimer timer;
   GraphCache graphs;
 };
@@ -93,8 +102,6 @@ bool check_batch(int n, const int* H, const int* W, int levels, int radius, int 
                  unsigned flags) {
   if (n < 1 || n > 65536) return set_error("batch size out of range"), false;
   if (flags & OF_FLAG_NORMALIZE) return set_error("OF_FLAG_NORMALIZE applies to plans only"), false;
-  if (flags & OF_FLAG_GAUSSIAN_WINDOW)
-    return set_error("OF_FLAG_GAUSSIAN_WINDOW applies to plans only"), false;
   if (flags & OF_FLAG_GRAPH) return set_error("OF_FLAG_GRAPH applies to plans only"), false;
   if (!H || !W) return set_error("NULL size arrays"), false;
   for (int i = 0; i < n; ++i)
@@ -127,6 +134,27 @@ std::vector<int4> tile_list(const of_batch* b, int l) {
   return t;
 }
 
+// Tile flags of every masked pair at the current tile heights (set-up calls only).
+hipError_t upload_flags(of_batch* b) {
+  if (!b->flagbuf) return hipSuccess;
+  const int TW = strip_width_for(b->R);
+  std::vector<uint8_t> all(b->flag_cap, 0);
+  for (int p = 0; p < b->n; ++p) {
+    if (b->mask_off[p].empty()) continue;
+    size_t off = 0;
+    for (int l = 0; l < b->L; ++l) {
+      const Geometry& g = b->g[p];
+      const std::vector<uint8_t> f =
+          tile_flags(b->hmask[p][l].data(), g.H[l], g.W[l], TW, (2 * b->R + 1) * b->cfg[l].nb);
+      const size_t o = b->flag_off[p][l];
+      memcpy(all.data() + o, f.data(), f.size());
+      off = o + f.size();
+    }
+    (void)off;
+  }
+  return hipMemcpy(b->flagbuf, all.data(), all.size(), hipMemcpyHostToDevice);
+}
+
 hipError_t upload_tiles(of_batch* b) {
   for (int l = 0; l < b->L; ++l) {
     std::vector<int4> t = tile_list(b, l);
@@ -136,7 +164,7 @@ hipError_t upload_tiles(of_batch* b) {
                              t.size() * sizeof(int4), hipMemcpyHostToDevice);
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  return upload_flags(b);
 }
 
 // Fill the argument block for the given caller buffers.
@@ -181,6 +209,11 @@ void fill_args(const of_batch* b, char* blk, const void* const* I1, const void* 
         const bool last = (l == 0 && k == K - 1);
         a.uout = last ? u[p] : fu[buf];
         a.vout = last ? v[p] : fv[buf];
+        if (b->flags & OF_FLAG_GAUSSIAN_WINDOW) gaussian_taps(a.taps, b->R);
+        if (b->maskbuf && !b->mask_off[p].empty()) {
+          a.mask = b->maskbuf + b->mask_off[p][l];
+          a.tiles = b->flagbuf + b->flag_off[p][l];
+        }
         cu = a.uout;
         cv = a.vout;
         cH = a.H;
@@ -254,6 +287,8 @@ hipError_t enqueue_batch(of_batch* b, char* blk, float* const* u, float* const* 
       bl.grid = b->cfg[l].grid > 0 ? std::min(b->cfg[l].grid, bl.ntiles) : bl.ntiles;
       bl.grid = (bl.grid + 7) / 8 * 8;
       bl.variant = b->cfg[l].variant >= 0 ? b->cfg[l].variant : default_tile_variant(bl.ntiles);
+      if (b->flags & OF_FLAG_GAUSSIAN_WINDOW) bl.variant |= kTileGauss;
+      bl.masked = b->maskbuf != nullptr;
       const int mode = k > 0 ? kFlowSame : (l == L - 1 ? kFlowZero : kFlowCoarse);
       hipEvent_t ev = nullptr;
       hipError_t e = t && t->per_launch() ? t->begin(s, &ev) : hipSuccess;
@@ -498,8 +533,72 @@ void of_batch_destroy(of_batch* b) {
   for (int i = 0; i < kArgSlots; ++i)
     if (b->slot_done[i]) hipEventDestroy(b->slot_done[i]);
   if (b->pinned) hipHostFree(b->pinned);
+  if (b->maskbuf) hipFree(b->maskbuf);
+  if (b->flagbuf) hipFree(b->flagbuf);
   if (b->owns_ws) hipFree(b->ws);
   delete b;
+}
+
+of_status of_batch_set_masks(of_batch* b, const uint8_t* const* masks, void* stream) {
+  if (!b) return set_error("NULL batch"), OF_EINVAL;
+  DeviceGuard guard(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipDeviceSynchronize();   // captured graphs and runs in flight hold the old masks
+  if (e != hipSuccess) return hip_fail("set_masks", e);
+  drop_graphs(b);
+  if (b->maskbuf) hipFree(b->maskbuf);
+  if (b->flagbuf) hipFree(b->flagbuf);
+  b->maskbuf = b->flagbuf = nullptr;
+  b->mask_off.assign(b->n, {});
+  b->flag_off.assign(b->n, {});
+  b->hmask.assign(b->n, {});
+  b->flag_cap = 0;
+  bool any = false;
+  for (int p = 0; masks && p < b->n; ++p) any |= masks[p] != nullptr;
+  if (!any) return OF_OK;
+  // layout: mask pyramids of the masked pairs; flag capacity at one-band tiles (the most tiles)
+  const int TW = strip_width_for(b->R), N = 2 * b->R + 1;
+  size_t mtotal = 0;
+  for (int p = 0; p < b->n; ++p) {
+    if (!masks[p]) continue;
+    for (int l = 0; l < b->L; ++l) {
+      const Geometry& g = b->g[p];
+      b->mask_off[p].push_back(mtotal);
+      mtotal += align256((size_t)g.H[l] * g.W[l]);
+      b->flag_off[p].push_back(b->flag_cap);
+      b->flag_cap += (size_t)((g.W[l] + TW - 1) / TW) * ((g.H[l] + N - 1) / N);
+    }
+  }
+  e = hipMalloc((void**)&b->maskbuf, mtotal);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->flagbuf, std::max<size_t>(b->flag_cap, 1));
+  for (int p = 0; p < b->n && e == hipSuccess; ++p) {
+    if (!masks[p]) continue;
+    const Geometry& g = b->g[p];
+    e = hipMemcpyAsync(b->maskbuf + b->mask_off[p][0], masks[p], (size_t)g.H[0] * g.W[0],
+                       hipMemcpyDeviceToDevice, s);
+    for (int l = 1; l < b->L && e == hipSuccess; ++l)
+      e = launch_mask_reduce(b->maskbuf + b->mask_off[p][l - 1], g.H[l - 1], g.W[l - 1],
+                             b->maskbuf + b->mask_off[p][l], g.H[l], g.W[l], s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  for (int p = 0; p < b->n && e == hipSuccess; ++p) {
+    if (!masks[p]) continue;
+    b->hmask[p].resize(b->L);
+    for (int l = 0; l < b->L && e == hipSuccess; ++l) {
+      b->hmask[p][l].resize((size_t)b->g[p].H[l] * b->g[p].W[l]);
+      e = hipMemcpy(b->hmask[p][l].data(), b->maskbuf + b->mask_off[p][l], b->hmask[p][l].size(),
+                    hipMemcpyDeviceToHost);
+    }
+  }
+  if (e == hipSuccess) e = upload_flags(b);
+  if (e != hipSuccess) {
+    if (b->maskbuf) hipFree(b->maskbuf);
+    if (b->flagbuf) hipFree(b->flagbuf);
+    b->maskbuf = b->flagbuf = nullptr;
+    b->mask_off.assign(b->n, {});
+    return hip_fail("set_masks", e);
+  }
+  return OF_OK;
 }
 
 of_status of_batch_set_timing(of_batch* b, int enable) {

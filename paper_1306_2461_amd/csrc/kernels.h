@@ -77,7 +77,8 @@ struct BatchLaunch {
   const int4* tiles;
   int ntiles;
   int grid;
-  int variant;   // TileVariant
+  int variant;   // TileVariant (narrow, wide, wide lean), plus kTileGauss for the Gaussian window
+  bool masked;   // some pair of the launch has a mask (IterArgs::mask)
 };
 
 // Strip width (output columns per tile) of the iteration kernel for radius R (variants 0-2).

@@ -535,9 +535,12 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW * BB) void lk_iter_strip(IterA
 }
 
 // Batched form: workgroups stride over a work list of tiles of many pairs at the same
-// (level, iteration) phase.  Work item = (pair, tile x, tile y, tile height).  Batches carry
-// no masks.
-template <typename T, int R, int TW, int MODE, bool WIDE, bool LEAN>
+// (level, iteration) phase.  Work item = (pair, tile x, tile y, tile height).  A pair with a
+// mask carries its level mask and tile flags in its arguments (flags indexed by tile row x
+// tiles per row at this tile height): tiles without an unmasked pixel are zero-filled.
+// MASK: launches of batches with masks (the mask code costs the unmasked launches about 5 %
+// more instructions and is compiled out of them).
+template <typename T, int R, int TW, int MODE, bool WIDE, bool LEAN, bool GAUSS, bool MASK>
 __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_batch(const IterArgs* __restrict__ args,
                                                                       const int4* __restrict__ tiles,
                                                                       int ntiles) {
@@ -548,13 +551,24 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_batch(const Iter
     const int4 w = tiles[t];
     const IterArgs a = args[w.x];
     const int nb = w.w / C::N + 1;
+    bool pixel_mask = false;
+    if constexpr (MASK) {
+      if (a.mask) {
+        const int f = a.tiles[w.z * ((a.W + TW - 1) / TW) + w.y];
+        if (f == 0) {
+          zero_tile<TW>(a, w.w, w.y, w.z);
+          continue;
+        }
+        pixel_mask = f == 1;
+      }
+    }
     constexpr bool kFR = MODE == kFlowCoarse;
     if (R <= 8 && tile_interior<R, TW>(a, w.w, nb, w.y, w.z))
-      strip_tile<T, R, TW, MODE, WIDE, true, true, LEAN, false, 1, kFR>(a, w.w, nb, w.y, w.z, false,
-                                                                        sm4);
+      strip_tile<T, R, TW, MODE, WIDE, true, true, LEAN, GAUSS, 1, kFR>(a, w.w, nb, w.y, w.z,
+                                                                        pixel_mask, sm4);
     else
-      strip_tile<T, R, TW, MODE, WIDE, true, false, LEAN, false, 1, kFR>(a, w.w, nb, w.y, w.z,
-                                                                         false, sm4);
+      strip_tile<T, R, TW, MODE, WIDE, true, false, LEAN, GAUSS, 1, kFR>(a, w.w, nb, w.y, w.z,
+                                                                         pixel_mask, sm4);
     __syncthreads();
   }
 }
@@ -621,28 +635,38 @@ hipError_t go_plain(const IterArgs& a, int nb, int variant, hipStream_t s) {
   return go_plain_g<T, R, MODE, false>(a, nb, variant, s);
 }
 
-template <typename T, int R, int MODE, bool WIDE, bool LEAN>
-hipError_t go_batch_v(const BatchLaunch& b, hipStream_t s) {
+template <typename T, int R, int MODE, bool WIDE, bool LEAN, bool GAUSS, bool MASK>
+hipError_t go_batch_m(const BatchLaunch& b, hipStream_t s) {
   constexpr int TW = strip_width<R>();
   using C = Cfg<R, TW, WIDE>;
   constexpr size_t kLds = lds_bytes<R, TW, WIDE, LEAN, 1, MODE == kFlowCoarse>();
   if constexpr (kLds > 65536) {
     static const hipError_t opt = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&lk_iter_batch<T, R, TW, MODE, WIDE, LEAN>),
+        reinterpret_cast<const void*>(&lk_iter_batch<T, R, TW, MODE, WIDE, LEAN, GAUSS, MASK>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds);
     if (opt != hipSuccess) return opt;
   }
-  hipLaunchKernelGGL((lk_iter_batch<T, R, TW, MODE, WIDE, LEAN>), dim3(b.grid), dim3(C::NT), kLds,
-                     s, b.args, b.tiles, b.ntiles);
+  hipLaunchKernelGGL((lk_iter_batch<T, R, TW, MODE, WIDE, LEAN, GAUSS, MASK>), dim3(b.grid),
+                     dim3(C::NT), kLds, s, b.args, b.tiles, b.ntiles);
   return hipGetLastError();
 }
 
+template <typename T, int R, int MODE, bool WIDE, bool LEAN, bool GAUSS>
+hipError_t go_batch_v(const BatchLaunch& b, hipStream_t s) {
+  return b.masked ? go_batch_m<T, R, MODE, WIDE, LEAN, GAUSS, true>(b, s)
+                  : go_batch_m<T, R, MODE, WIDE, LEAN, GAUSS, false>(b, s);
+}
+
+// b.variant: OF_TILE_NARROW, _WIDE or _WIDE_LEAN, plus kTileGauss for the Gaussian window.
 template <typename T, int R, int MODE>
 hipError_t go_batch(const BatchLaunch& b, hipStream_t s) {
   switch (b.variant) {
-    case kTileNarrow: return go_batch_v<T, R, MODE, false, true>(b, s);
-    case kTileWide: return go_batch_v<T, R, MODE, true, false>(b, s);
-    case kTileWideLean: return go_batch_v<T, R, MODE, true, true>(b, s);
+    case kTileNarrow: return go_batch_v<T, R, MODE, false, true, false>(b, s);
+    case kTileWide: return go_batch_v<T, R, MODE, true, false, false>(b, s);
+    case kTileWideLean: return go_batch_v<T, R, MODE, true, true, false>(b, s);
+    case kTileNarrow | kTileGauss: return go_batch_v<T, R, MODE, false, true, true>(b, s);
+    case kTileWide | kTileGauss: return go_batch_v<T, R, MODE, true, false, true>(b, s);
+    case kTileWideLean | kTileGauss: return go_batch_v<T, R, MODE, true, true, true>(b, s);
   }
   return hipErrorInvalidValue;
 }

@@ -130,6 +130,12 @@ hipError_t GraphCache::run(const std::vector<uintptr_t>& key, hipStream_t s, F&&
 }
 
 void set_error(const std::string& s);
+// Separable taps of the Gaussian-weighted window, g(d) = exp(-d^2 / (2 sigma^2)), sigma = R/2,
+// d = -R..R (a single tap of 1 for R = 0), into taps[0..2R].
+void gaussian_taps(float* taps, int R);
+// Flags of the iteration tiles (TW columns x TH rows) of an H x W mask level: 0 = no unmasked
+// pixel, 1 = some masked pixels, 2 = no masked pixel; row-major over tile rows.
+std::vector<uint8_t> tile_flags(const uint8_t* mask, int H, int W, int TW, int TH);
 int default_bands(int H, int W, int R);
 int default_tile_variant(long long ntiles);
 bool check_params(int H, int W, int levels, int radius, int iters, unsigned flags);

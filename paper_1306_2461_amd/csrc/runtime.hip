@@ -192,12 +192,32 @@ KernelTimer::~KernelTimer() {
 // Window taps and launch variant of one iteration: the Gaussian-weighted window
 // (OF_FLAG_GAUSSIAN_WINDOW) fills the taps g(d) = exp(-d^2 / (2 sigma^2)), sigma = r/2,
 // d = -r..r, and marks the variant.
+void gaussian_taps(float* taps, int R) {
+  for (int q = 0; q <= 2 * R; ++q) {
+    const double d = q - R;
+    taps[q] = R == 0 ? 1.0f : (float)std::exp(-2.0 * d * d / ((double)R * R));
+  }
+}
+
+std::vector<uint8_t> tile_flags(const uint8_t* m, int H, int W, int TW, int TH) {
+  const int tx = (W + TW - 1) / TW, ty = (H + TH - 1) / TH;
+  std::vector<uint8_t> f((size_t)tx * ty);
+  for (int by = 0; by < ty; ++by)
+    for (int bx = 0; bx < tx; ++bx) {
+      int on = 0, total = 0;
+      for (int y = by * TH; y < std::min(H, (by + 1) * TH); ++y)
+        for (int x = bx * TW; x < std::min(W, (bx + 1) * TW); ++x) {
+          on += m[(size_t)y * W + x] != 0;
+          ++total;
+        }
+      f[(size_t)by * tx + bx] = on == 0 ? 0 : (on == total ? 2 : 1);
+    }
+  return f;
+}
+
 int window_variant(const Geometry& g, int l, IterArgs& a) {
   if (!(g.flags & OF_FLAG_GAUSSIAN_WINDOW)) return g.variant[l];
-  for (int q = 0; q <= 2 * g.R; ++q) {
-    const double d = q - g.R;
-    a.taps[q] = g.R == 0 ? 1.0f : (float)std::exp(-2.0 * d * d / ((double)g.R * g.R));
-  }
+  gaussian_taps(a.taps, g.R);
   return g.variant[l] | kTileGauss;
 }
 
@@ -531,20 +551,7 @@ size_t tile_capacity(const Geometry& g, int l) {
 hipError_t upload_tile_flags(of_plan* p, int l) {
   Geometry& g = p->g;
   const int TW = tile_width(g.variant[l], g.R), TH = (2 * g.R + 1) * g.nb[l];
-  const int H = g.H[l], W = g.W[l];
-  const int tx = (W + TW - 1) / TW, ty = (H + TH - 1) / TH;
-  std::vector<uint8_t> f((size_t)tx * ty);
-  const std::vector<uint8_t>& m = p->hmask[l];
-  for (int by = 0; by < ty; ++by)
-    for (int bx = 0; bx < tx; ++bx) {
-      int on = 0, total = 0;
-      for (int y = by * TH; y < std::min(H, (by + 1) * TH); ++y)
-        for (int x = bx * TW; x < std::min(W, (bx + 1) * TW); ++x) {
-          on += m[(size_t)y * W + x] != 0;
-          ++total;
-        }
-      f[(size_t)by * tx + bx] = on == 0 ? 0 : (on == total ? 2 : 1);
-    }
+  const std::vector<uint8_t> f = tile_flags(p->hmask[l].data(), g.H[l], g.W[l], TW, TH);
   g.tflags[l] = p->tflags + p->tf_off[l];
   return hipMemcpy(p->tflags + p->tf_off[l], f.data(), f.size(), hipMemcpyHostToDevice);
 }

@@ -64,6 +64,11 @@ struct of_session {
   char* flow = nullptr;           // four level-0 FP32 planes
   int cur = 0;                    // slot that receives the next frame
   bool has_prev = false;
+  // mask (of_session_set_mask): mask pyramid and the tile flags of every push tile height
+  uint8_t* maskbuf = nullptr;
+  uint8_t* flagbuf = nullptr;
+  size_t mask_off[OF_MAX_LEVELS] = {};
+  size_t flag_off[3][OF_MAX_LEVELS] = {};
 };
 
 struct of_server {
@@ -189,11 +194,13 @@ hipError_t reserve_ring(of_server* s, size_t need) {
 
 bool check_server_flags(unsigned flags) {
   if (flags & OF_FLAG_NORMALIZE) return set_error("OF_FLAG_NORMALIZE applies to plans only"), false;
-  if (flags & OF_FLAG_GAUSSIAN_WINDOW)
-    return set_error("OF_FLAG_GAUSSIAN_WINDOW applies to plans only"), false;
   if (flags & OF_FLAG_GRAPH) return set_error("OF_FLAG_GRAPH applies to plans only"), false;
   return true;
 }
+
+// Tile heights (in bands) a push may choose (push_bands) and their slot in a session's flags.
+constexpr int kPushBands[3] = {1, 2, 4};
+int band_slot(int nb) { return nb == 1 ? 0 : (nb == 2 ? 1 : 2); }
 
 // Servers behind of_session_create, one per (device, levels, radius, iters, flags).
 std::mutex g_hidden_mu;
@@ -257,6 +264,8 @@ void destroy_server(of_server* s) {
   hipDeviceSynchronize();
   for (of_session* ss : s->sessions) {
     if (ss->owns_mem) hipFree(ss->mem);
+    if (ss->maskbuf) hipFree(ss->maskbuf);
+    if (ss->flagbuf) hipFree(ss->flagbuf);
     delete ss;
   }
   free_ring(s);
@@ -319,6 +328,8 @@ of_status of_server_close(of_server* s, of_session* ss) {
   DeviceGuard guard(s->device);
   hipDeviceSynchronize();
   if (ss->owns_mem) hipFree(ss->mem);
+  if (ss->maskbuf) hipFree(ss->maskbuf);
+  if (ss->flagbuf) hipFree(ss->flagbuf);
   s->resident -= ss->bytes;
   s->sessions.erase(std::remove(s->sessions.begin(), s->sessions.end(), ss), s->sessions.end());
   delete ss;
@@ -368,10 +379,12 @@ of_status of_server_push(of_server* s, of_session* const* ss, int n, const void*
   const int TW = strip_width_for(R), N = 2 * R + 1;
   p.args.resize((size_t)L * (K > 0 ? K : 0));
   p.tiles.resize(L);
+  int level_bands[OF_MAX_LEVELS];
   for (int l = L - 1; l >= 0; --l) {
     long long px = 0;
     for (int i : flowing) px += (long long)ss[i]->g.H[l] * ss[i]->g.W[l];
-    const int TH = N * push_bands(px);
+    level_bands[l] = push_bands(px);
+    const int TH = N * level_bands[l];
     for (int q = 0; q < (int)flowing.size(); ++q) {
       const of_session* x = ss[flowing[q]];
       const int tx = (x->g.W[l] + TW - 1) / TW, ty = (x->g.H[l] + TH - 1) / TH;
@@ -404,6 +417,11 @@ of_status of_server_push(of_server* s, of_session* const* ss, int n, const void*
         const bool last = (l == 0 && k == K - 1);
         a.uout = last ? u[i] : fu[buf];
         a.vout = last ? v[i] : fv[buf];
+        if (s->flags & OF_FLAG_GAUSSIAN_WINDOW) gaussian_taps(a.taps, R);
+        if (x->maskbuf) {
+          a.mask = x->maskbuf + x->mask_off[l];
+          a.tiles = x->flagbuf + x->flag_off[band_slot(level_bands[l])][l];
+        }
         p.args[phase].push_back(a);
         cu = a.uout;
         cv = a.vout;
@@ -442,6 +460,9 @@ of_status of_server_push(of_server* s, of_session* const* ss, int n, const void*
       bl.ntiles = (int)p.tiles[l].size();
       bl.grid = (bl.ntiles + 7) / 8 * 8;
       bl.variant = default_tile_variant(bl.ntiles);
+      if (s->flags & OF_FLAG_GAUSSIAN_WINDOW) bl.variant |= kTileGauss;
+      bl.masked = false;
+      for (int i : flowing) bl.masked |= ss[i]->maskbuf != nullptr;
       const int mode = k > 0 ? kFlowSame : (l == L - 1 ? kFlowZero : kFlowCoarse);
       e = launch_iter_batch(gg.elem(l), bl, R, mode, st);
     }
@@ -467,6 +488,59 @@ of_status of_session_push(of_session* ss, const void* frame, float* u, float* v,
                           int* has_flow) {
   if (!ss) return set_error("NULL session"), OF_EINVAL;
   return of_server_push(ss->server, &ss, 1, &frame, &u, &v, has_flow, stream);
+}
+
+of_status of_session_set_mask(of_session* ss, const uint8_t* mask, void* stream) {
+  if (!ss) return set_error("NULL session"), OF_EINVAL;
+  of_server* s = ss->server;
+  std::lock_guard<std::mutex> lock(s->mu);
+  DeviceGuard guard(s->device);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipDeviceSynchronize();   // pushes in flight read the old mask
+  if (e != hipSuccess) return hip_fail("set_mask", e);
+  if (ss->maskbuf) hipFree(ss->maskbuf);
+  if (ss->flagbuf) hipFree(ss->flagbuf);
+  ss->maskbuf = ss->flagbuf = nullptr;
+  if (!mask) return OF_OK;
+  const Geometry& g = ss->g;
+  const int L = s->L, TW = strip_width_for(s->R), N = 2 * s->R + 1;
+  size_t mt = 0, ft = 0;
+  for (int l = 0; l < L; ++l) {
+    ss->mask_off[l] = mt;
+    mt += align256((size_t)g.H[l] * g.W[l]);
+    for (int b = 0; b < 3; ++b) {
+      ss->flag_off[b][l] = ft;
+      const int TH = N * kPushBands[b];
+      ft += (size_t)((g.W[l] + TW - 1) / TW) * ((g.H[l] + TH - 1) / TH);
+    }
+  }
+  uint8_t* mb = nullptr;
+  uint8_t* fb = nullptr;
+  e = hipMalloc((void**)&mb, mt);
+  if (e == hipSuccess) e = hipMalloc((void**)&fb, ft);
+  if (e == hipSuccess) e = hipMemcpyAsync(mb, mask, (size_t)g.H[0] * g.W[0], hipMemcpyDeviceToDevice, st);
+  for (int l = 1; l < L && e == hipSuccess; ++l)
+    e = launch_mask_reduce(mb + ss->mask_off[l - 1], g.H[l - 1], g.W[l - 1], mb + ss->mask_off[l],
+                           g.H[l], g.W[l], st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  std::vector<uint8_t> flags(ft);
+  for (int l = 0; l < L && e == hipSuccess; ++l) {
+    std::vector<uint8_t> hm((size_t)g.H[l] * g.W[l]);
+    e = hipMemcpy(hm.data(), mb + ss->mask_off[l], hm.size(), hipMemcpyDeviceToHost);
+    for (int b = 0; b < 3 && e == hipSuccess; ++b) {
+      const std::vector<uint8_t> f = tile_flags(hm.data(), g.H[l], g.W[l], TW, N * kPushBands[b]);
+      memcpy(flags.data() + ss->flag_off[b][l], f.data(), f.size());
+    }
+  }
+  if (e == hipSuccess) e = hipMemcpy(fb, flags.data(), ft, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (mb) hipFree(mb);
+    if (fb) hipFree(fb);
+    return hip_fail("set_mask", e);
+  }
+  ss->maskbuf = mb;
+  ss->flagbuf = fb;
+  return OF_OK;
 }
 
 of_session* of_session_create(int H, int W, int levels, int radius, int iters, unsigned flags,

@@ -199,8 +199,21 @@ class Server:
         lat = sorted(r.latency for r in flows)
         out = {"requests": len(self.done), "flows": len(flows), "rejected": len(self.rejected)}
         if lat:
-            out["p50_ms"] = 1e3 * lat[len(lat) // 2]
-            out["p99_ms"] = 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))]
+            def q(xs, f):
+                xs = sorted(xs)
+                return 1e3 * xs[min(len(xs) - 1, int(f * len(xs)))]
+            out["p50_ms"] = q(lat, 0.5)
+            out["p99_ms"] = q(lat, 0.99)
+            # where the time goes: waiting for a push (arrival -> launch) and on the device
+            # (launch -> completion seen by the host)
+            wait = [r.t_launch - r.t_arrival for r in flows]
+            run = [r.t_done - r.t_launch for r in flows]
+            out["queue_p50_ms"], out["queue_p99_ms"] = q(wait, 0.5), q(wait, 0.99)
+            out["device_p50_ms"], out["device_p99_ms"] = q(run, 0.5), q(run, 0.99)
+            by_size = {}
+            for r in flows:
+                by_size.setdefault("x".join(str(d) for d in reversed(r.frame.shape)), []).append(r.latency)
+            out["p99_ms_by_size"] = {k: q(v, 0.99) for k, v in sorted(by_size.items())}
             t_first = min(r.t_arrival for r in self.done)
             t_last = max(r.t_done for r in flows)
             out["pairs_per_s"] = len(flows) / max(t_last - t_first, 1e-9)
@@ -221,7 +234,7 @@ class GpuExecutor:
     RING = 8   # OF_SERVER_RING
 
     def __init__(self, levels, radius, iters, fp16=False, budget_bytes=0, device=None,
-                 keep_on_device=True):
+                 keep_on_device=True, gaussian_window=False):
         import torch
 
         from . import _binding as B
@@ -230,7 +243,8 @@ class GpuExecutor:
         self.lib = B.load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.levels, self.radius, self.iters = levels, radius, iters
-        self.flags = B.OF_FLAG_FP16_STORAGE if fp16 else 0
+        self.flags = ((B.OF_FLAG_FP16_STORAGE if fp16 else 0)
+                      | (B.OF_FLAG_GAUSSIAN_WINDOW if gaussian_window else 0))
         self.budget = int(budget_bytes)
         self.keep_on_device = keep_on_device
         with torch.cuda.device(self.device):
@@ -263,6 +277,12 @@ class GpuExecutor:
         self._ws[s] = ws
         return s
 
+    def set_mask(self, handle, mask):
+        """Region-of-interest mask of one open stream (uint8 device tensor, nonzero = compute) or
+        None."""
+        self.B.check(self.lib.of_session_set_mask(handle, None if mask is None else mask.data_ptr(),
+                                                  self.stream.cuda_stream), "of_session_set_mask")
+
     def close(self, handle):
         self.B.check(self.lib.of_server_close(self._h, handle), "of_server_close")
         self._ws.pop(handle, None)
@@ -283,15 +303,19 @@ class GpuExecutor:
             self._events.popleft()
         if len(self._events) >= self.RING:
             raise Busy("every staging slot holds a push in flight")
-        hosts, devs, us, vs = [], [], [], []
+        hosts, devs, us, vs, producer = [], [], [], [], []
         with torch.cuda.stream(self.copy_stream):
             for _, f in items:
                 shape = tuple(f.shape)
-                hb = self._take(self._host[shape], lambda: torch.empty(shape, dtype=torch.uint8, pin_memory=True))
                 db = self._take(self._dev[shape], lambda: torch.empty(shape, dtype=torch.uint8, device=self.device))
-                hb.numpy()[...] = f
+                if isinstance(f, torch.Tensor) and f.is_pinned():
+                    hb = f            # a producer's pinned frame is copied as is (kept until done)
+                    producer.append(hb)
+                else:
+                    hb = self._take(self._host[shape], lambda: torch.empty(shape, dtype=torch.uint8, pin_memory=True))
+                    hb.numpy()[...] = f
+                    hosts.append(hb)
                 db.copy_(hb, non_blocking=True)
-                hosts.append(hb)
                 devs.append(db)
         copied = torch.cuda.Event()
         copied.record(self.copy_stream)
@@ -316,7 +340,7 @@ class GpuExecutor:
         ev.record(self.stream)
         self._events.append(ev)
         return {"event": ev, "us": us, "vs": vs, "has": list(has), "keep": keep,
-                "frames": (hosts, devs)}
+                "frames": (hosts, devs), "producer": producer}
 
     def _give_back(self, hosts, devs, us, vs):
         for t in hosts:

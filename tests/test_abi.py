@@ -58,13 +58,16 @@ def test_workspace_bytes_and_validation(lib):
     assert lib.of_plan_workspace_bytes(H, W, 3, 4, 4, 16) == expect
     # OF_FLAG_GRAPH changes the launch mode only
     assert lib.of_plan_workspace_bytes(H, W, 3, 4, 4, 32) == expect
-    # the plan-only flags are refused by batches and servers
+    # the plan-only flags (equalisation, graph capture) are refused by batches and servers; the
+    # Gaussian window is accepted by every form
     import ctypes
     hs, ws = (ctypes.c_int * 1)(H), (ctypes.c_int * 1)(W)
     assert lib.of_batch_workspace_bytes(1, hs, ws, 3, 4, 4, 0) > 0
-    for f in (8, 16, 32):
+    for f in (8, 32):
         assert lib.of_batch_workspace_bytes(1, hs, ws, 3, 4, 4, f) == 0
         assert lib.of_session_bytes(H, W, 3, 4, 4, f) == 0
+    assert lib.of_batch_workspace_bytes(1, hs, ws, 3, 4, 4, 16) == lib.of_batch_workspace_bytes(1, hs, ws, 3, 4, 4, 0)
+    assert lib.of_session_bytes(H, W, 3, 4, 4, 16) == lib.of_session_bytes(H, W, 3, 4, 4, 0)
     assert lib.of_plan_create(0, 5, 1, 1, 1) is None
     assert b"H and W" in lib.of_last_error()
     assert lib.of_compute(None, None, None, None, None, None) == 1
@@ -83,6 +86,8 @@ def test_host_side_rejections_of_the_newer_entry_points(lib):
     lib.of_session_destroy(None)
     assert lib.of_server_open_ex(None, 64, 64, None, 0) is None
     assert lib.of_plan_set_bubble(None, None, None) == B.OF_EINVAL
+    assert lib.of_batch_set_masks(None, None, None) == B.OF_EINVAL
+    assert lib.of_session_set_mask(None, None, None) == B.OF_EINVAL
     assert lib.of_bubble_step(None, None, 1, 0, None, None, None, None, None) == B.OF_EINVAL
     assert lib.of_plan_set_timing(None, 1) == B.OF_EINVAL
     assert lib.of_compute_noalloc(64, 64, 3, 4, 2, B.OF_FLAG_GRAPH, None, None, None, None, None) == B.OF_EINVAL

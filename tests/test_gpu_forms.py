@@ -1,0 +1,105 @@
+"""Region-of-interest masks and the Gaussian-weighted window in the batched and served forms:
+every result equals the plain per-pair path with the same mask or window, bitwise (window sums
+and mask handling do not depend on the tiling), and sampled pairs the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import announce, dev, flow_error, report, to_dev
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(160, 200), (96, 128), (256, 256)]
+L, R, K = 3, 4, 3
+
+
+def _pairs():
+    out = []
+    for i, (H, W) in enumerate(SIZES):
+        I1, I2, _, _ = synth.make_pair("c1", 20 + i)
+        out.append((np.tile(I1, (2, 2))[:H, :W].copy(), np.tile(I2, (2, 2))[:H, :W].copy()))
+    return out
+
+
+def _mask(H, W, k):
+    M = np.ones((H, W), dtype=np.uint8)
+    M[H // 2 + k:, :W // 3] = 0          # a step-like obstacle
+    M[:6 + k, :] = 0                     # a wall
+    return M
+
+
+def _plain(ofmi, I1, I2, mask=None, gaussian=False):
+    import torch
+    H, W = I1.shape
+    plan = ofmi.Plan(H, W, L, R, K, gaussian_window=gaussian, device=dev())
+    if mask is not None:
+        plan.set_mask(to_dev(mask))
+    u, v = plan.compute(to_dev(I1), to_dev(I2))
+    torch.cuda.synchronize()
+    out = u.cpu().numpy(), v.cpu().numpy()
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("gaussian", [False, True])
+def test_batch_masks_and_window_equal_plain_path(gpu_lib, gaussian):
+    import torch
+    ofmi = gpu_lib
+    pairs = _pairs()
+    masks = [_mask(*SIZES[0], 0), None, _mask(*SIZES[2], 3)]
+    announce(f"batch with masks, gaussian={gaussian}")
+    b = ofmi.Batch(SIZES, L, R, K, gaussian_window=gaussian, device=dev())
+    d1 = [to_dev(p[0]) for p in pairs]
+    d2 = [to_dev(p[1]) for p in pairs]
+    b.set_masks([None if m is None else to_dev(m) for m in masks])
+    for cfg in (None, {"bands": [2, 1, 1], "grid": [0, 16, 0], "variant": [0, 1, 2]},
+                {"bands": [1, 3, 2], "grid": [8, 0, 0], "variant": [2, 2, 0]}):
+        if cfg is not None:
+            b.set_config(cfg)
+        us, vs = b.outputs()
+        b.compute(d1, d2, us, vs)
+        torch.cuda.synchronize()
+        for i, (p, m) in enumerate(zip(pairs, masks)):
+            pu, pv = _plain(ofmi, p[0], p[1], m, gaussian)
+            assert np.array_equal(us[i].cpu().numpy(), pu) and np.array_equal(vs[i].cpu().numpy(), pv), (i, cfg)
+            if m is not None:
+                assert np.all(pu[m == 0] == 0) and np.all(pv[m == 0] == 0)
+    ou, ov = oracle.flow(pairs[0][0], pairs[0][1], L, R, K, mask=masks[0].astype(bool),
+                         window="gauss" if gaussian else "box")
+    d = flow_error(us[0].cpu().numpy(), vs[0].cpu().numpy(), ou, ov)
+    assert d.max() <= 1e-3, report(d, 1e-3)
+    # removing the masks gives the unmasked bits again
+    b.set_masks(None)
+    us, vs = b.outputs()
+    b.compute(d1, d2, us, vs)
+    torch.cuda.synchronize()
+    pu, pv = _plain(ofmi, pairs[2][0], pairs[2][1], None, gaussian)
+    assert np.array_equal(us[2].cpu().numpy(), pu) and np.array_equal(vs[2].cpu().numpy(), pv)
+    b.close()
+
+
+def test_served_streams_with_mask_and_window(gpu_lib):
+    """Two streams served together with the Gaussian window, one of them masked: each flow
+    equals the plain path's with the same window and mask, bitwise."""
+    ofmi = gpu_lib
+    from paper_1306_2461_amd.serve import GpuExecutor, Server
+    sizes = [(96, 128), (160, 120)]
+    streams = [[f for f, _, _ in synth.stream_frames(s, 3, size=sizes[s])] for s in range(2)]
+    M = _mask(*sizes[0], 1)
+    ex = GpuExecutor(L, R, K, device=dev(), keep_on_device=False, gaussian_window=True)
+    srv = Server(ex)
+    announce("served streams with mask and Gaussian window")
+    reqs = {s: [srv.submit(s, streams[s][0])] for s in range(2)}
+    srv.drain()
+    ex.set_mask(srv.sessions[0], to_dev(M))
+    for t in (1, 2):
+        for s in range(2):
+            reqs[s].append(srv.submit(s, streams[s][t]))
+    srv.drain()
+    ex.close_all()
+    for s in range(2):
+        for t in (1, 2):
+            pu, pv = _plain(ofmi, streams[s][t - 1], streams[s][t], M if s == 0 else None, True)
+            r = reqs[s][t]
+            assert r.has_flow and np.array_equal(r.u, pu) and np.array_equal(r.v, pv), (s, t)
