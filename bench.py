@@ -469,7 +469,7 @@ def bench_gaussian(torch, ofmi, dev, d1, d2, us, vs, wl, steps, warmup, box_valu
             "config": tuned}
 
 
-def bench_serving(torch, ofmi, dev, pool, workers, frames_per_stream, with_cpu=True):
+def bench_serving(torch, ofmi, dev, pool, workers, frames_per_stream, with_cpu=True, max_inflight=2):
     """8 streams (sizes from {640x480, 1024^2, 2048^2}), Poisson arrivals at 250 frames/s each,
     replayed in real time; one sampled pair per stream checked against the oracle."""
     import numpy as np
@@ -499,7 +499,7 @@ def bench_serving(torch, ofmi, dev, pool, workers, frames_per_stream, with_cpu=T
     # sampled pairs: the flow of frames (ts-1, ts) of every stream is kept; every other result
     # is only timed and its output planes go back to the executor's pool
     ts = frames_per_stream // 2
-    srv = Server(exe, keep=lambda r: r.frame is pinned[r.stream_id][ts])
+    srv = Server(exe, keep=lambda r: r.frame is pinned[r.stream_id][ts], max_inflight=max_inflight)
     st = srv.replay(arrivals, realtime=True)
     sampled = []
     for r in srv.done:

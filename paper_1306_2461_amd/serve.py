@@ -53,11 +53,17 @@ class Request:
 class Server:
     """Continuous-batching request loop over an executor."""
 
-    def __init__(self, executor, max_batch: int = 64, clock=time.perf_counter, keep=None):
+    def __init__(self, executor, max_batch: int = 64, clock=time.perf_counter, keep=None,
+                 max_inflight: int | None = 2):
         """``keep(request) -> bool`` selects the requests whose flow is kept (default: all);
-        the others are only timed, and their output planes go back to the executor's pool."""
+        the others are only timed, and their output planes go back to the executor's pool.
+        ``max_inflight`` bounds the pushes in flight (None: as many as the executor stages).
+        While the bound is reached, arriving frames wait on the host and join one larger push
+        instead of queueing on the device as many small ones: the default, one push running
+        and one queued behind it, keeps the device busy and turns bursts into batches."""
         self.ex = executor
         self.max_batch = max_batch
+        self.max_inflight = max_inflight
         self.clock = clock
         self.keep = keep
         self.pending: collections.deque[Request] = collections.deque()
@@ -110,6 +116,9 @@ class Server:
 
     def step(self) -> int:
         """Launch one push with the oldest pending frame of every admitted stream."""
+        self.busy = self.max_inflight is not None and len(self.inflight) >= self.max_inflight
+        if self.busy:
+            return 0
         batch, seen, keep = [], set(), collections.deque()
         while self.pending:
             req = self.pending.popleft()
@@ -137,7 +146,6 @@ class Server:
             self.pending.extendleft(reversed([r for _, r in batch]))
             self.busy = True
             return 0
-        self.busy = False
         t = self.clock()
         for _, r in batch:
             r.t_launch = t
@@ -186,7 +194,7 @@ class Server:
             launched = self.step() if self.pending else 0
             completed = self.poll()
             if not launched and not completed:
-                if self.inflight and (i >= len(arrivals) or not realtime or self.busy):
+                if self.inflight and (i >= len(arrivals) or not realtime or (self.busy and self.pending)):
                     self.ex.wait(self.inflight[0][0])
                 elif realtime and i < len(arrivals):
                     time.sleep(max(0.0, min(2e-4, arrivals[i][0] - (self.clock() - t0))))

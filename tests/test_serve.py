@@ -124,3 +124,23 @@ def test_busy_executor_keeps_order_and_keep_predicate():
         u, v = oracle.flow(fr[0][t - 1], fr[0][t], 1, 2, 1)
         assert np.array_equal(reqs[0][t].u, u) and reqs[0][t].has_flow
         assert reqs[1][t].u is None and reqs[1][t].has_flow
+
+
+def test_inflight_bound_merges_arrivals_into_one_push():
+    """With the in-flight bound reached, frames that arrive wait on the host and go out together
+    in one push once an earlier push completes; without the bound each goes out on its own."""
+    for bound, expect in ((1, [1, 3]), (None, [1, 1, 1, 1])):
+        clock = FakeClock()
+        ex = FakeExecutor(1, 2, 1, delay=1.0, clock=clock)
+        srv = Server(ex, clock=clock, max_inflight=bound)
+        fr = {s: _frames(s, 1, (24, 24)) for s in range(4)}
+        srv.submit(0, fr[0][0])
+        srv.step()
+        for s in (1, 2, 3):
+            clock.advance(0.1)
+            srv.submit(s, fr[s][0])
+            srv.step()
+            assert srv.busy == (bound is not None)
+        srv.drain()
+        assert ex.pushes == expect, (bound, ex.pushes)
+        assert len(srv.done) == 4 and all(not r.has_flow for r in srv.done)
