@@ -66,8 +66,9 @@ struct Cfg {
   // (SPLIT) have a region of their own after the warped rows, which saves P3's second barrier.
   static constexpr size_t LDS_FLOATS = 5 * (size_t)NR * PP + (size_t)WROWS * WP;
   static constexpr size_t HS_FLOATS = 5 * (size_t)NR * TW;
-  // Field ring (coarse-field launches, one band per pass): u and v of the warped-frame
-  // positions, kept for FRING rows so that P2 and P5 read them instead of re-interpolating.
+  // Field ring (launches that read a field, one band per pass): u and v of the warped-frame
+  // positions, kept for FRING rows so that P2 and P5 read them from LDS instead of loading
+  // (and, from a coarser field, re-interpolating) them again.
   static constexpr int FRING = 64;
   static constexpr size_t FR_FLOATS = 2 * (size_t)FRING * WP;
   static constexpr bool SPLIT_FITS = (LDS_FLOATS + HS_FLOATS) * sizeof(float) <= 65536;
@@ -85,11 +86,12 @@ constexpr size_t lds_bytes() {
   return (C::LDS_FLOATS + (split_hs<R, TW, WIDE, LEAN, BB>() ? C::HS_FLOATS : 0) +
           (FR ? C::FR_FLOATS : 0)) * sizeof(float);
 }
-// Plain coarse-field launches of the wide variants with one band per pass keep the field
-// ring (its 2*64 rows cost LDS that only these latency-bound launches can spare).
+// Plain launches of the wide variants with one band per pass keep the field ring when they
+// read a field (its 2*64 rows cost LDS that only these latency-bound launches can spare); the
+// batched kernel keeps it in every variant (measured faster there as well).
 template <int MODE, bool WIDE, bool LEAN, int BB>
 constexpr bool field_ring() {
-  return MODE == kFlowCoarse && WIDE && !LEAN && BB == 1;
+  return MODE != kFlowZero && WIDE && !LEAN && BB == 1;
 }
 
 // One tile: TW output columns from x0 = bx*TW and TH output rows from y0 = by*TH, walked in
@@ -109,9 +111,10 @@ constexpr bool field_ring() {
 // threads, so a tile of two bands (one output band and the band that primes the vertical
 // sums) is one pass of the dependent path instead of two; P4 walks the two bands in order,
 // with the same additions as two single-band passes.  nbands is then even.
-// FR (coarse field, one band per pass): P1 stores the interpolated field of every warped-frame
-// position in a ring of FRING rows; P2 and P5 read theirs from it (the same value at the same
-// clamped position) instead of eight more loads per value.  The next band's P1 may overwrite
+// FR (a field is read, one band per pass): P1 stores the field of every warped-frame position
+// (interpolated from the coarser level in the coarse-field mode) in a ring of FRING rows; P2
+// and P5 read theirs from it (the same value at the same clamped position) instead of loading
+// it again (eight loads per value from a coarser field, one from the current one).  The next band's P1 may overwrite
 // ring rows while slower threads are still in P5: it writes rows tb+N+1 .. tb+2N while P5
 // reads rows tb-R .. tb+R, at most 5R+2 < FRING apart, so no slot is shared.
 template <typename T, int R, int TW, int MODE, bool WIDE, bool DEFER, bool INTERIOR, bool LEAN,
@@ -122,8 +125,8 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
   constexpr int N = C::N, NR = C::NR, NT = C::NT, PC = C::PC, WC = C::WC, PP = C::PP, WP = C::WP;
   constexpr int RMASK = C::RING - 1;
   static_assert(BB == 1 || BB == 2, "one or two bands per pass");
-  static_assert(!FR || (MODE == kFlowCoarse && BB == 1 && 5 * R + 2 < C::FRING),
-                "field ring: coarse-field launches with one band per pass");
+  static_assert(!FR || (MODE != kFlowZero && BB == 1 && 5 * R + 2 < C::FRING),
+                "field ring: launches that read a field, one band per pass");
   float* sm = reinterpret_cast<float*>(sm4);
   constexpr bool kSplit = split_hs<R, TW, WIDE, LEAN, BB>();
   float* pr = sm;                               // [5][NR][PP] products (16-byte aligned rows)
@@ -562,7 +565,7 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_batch(const Iter
         pixel_mask = f == 1;
       }
     }
-    constexpr bool kFR = MODE == kFlowCoarse;
+    constexpr bool kFR = MODE != kFlowZero;
     if (R <= 8 && tile_interior<R, TW>(a, w.w, nb, w.y, w.z))
       strip_tile<T, R, TW, MODE, WIDE, true, true, LEAN, GAUSS, 1, kFR>(a, w.w, nb, w.y, w.z,
                                                                         pixel_mask, sm4);
@@ -639,7 +642,7 @@ template <typename T, int R, int MODE, bool WIDE, bool LEAN, bool GAUSS, bool MA
 hipError_t go_batch_m(const BatchLaunch& b, hipStream_t s) {
   constexpr int TW = strip_width<R>();
   using C = Cfg<R, TW, WIDE>;
-  constexpr size_t kLds = lds_bytes<R, TW, WIDE, LEAN, 1, MODE == kFlowCoarse>();
+  constexpr size_t kLds = lds_bytes<R, TW, WIDE, LEAN, 1, MODE != kFlowZero>();
   if constexpr (kLds > 65536) {
     static const hipError_t opt = hipFuncSetAttribute(
         reinterpret_cast<const void*>(&lk_iter_batch<T, R, TW, MODE, WIDE, LEAN, GAUSS, MASK>),
