@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import concurrent.futures as cf
+import gc
 import json
 import multiprocessing as mp
 import os
@@ -489,9 +490,11 @@ def bench_serving(torch, ofmi, dev, pool, workers, frames_per_stream, with_cpu=T
         pinned.append([blk[t] for t in range(frames_per_stream)])
     arrivals = poisson_arrivals(pinned, 250.0)
     exe = GpuExecutor(wl.levels, wl.radius, wl.iters, fp16=True, budget_bytes=8 << 30, device=dev)
-    warm = Server(exe)                       # opens sessions, builds first pyramids, warms up
+    # warm-up: opens sessions, builds first pyramids, fills the executor's frame and plane pools
+    # (its results are not kept, so their planes go back to the pools)
+    warm = Server(exe, keep=lambda r: False, max_inflight=max_inflight)
     for sid in range(8):
-        for f in pinned[sid][:2]:
+        for f in pinned[sid][:4]:
             warm.submit(sid, f)
     warm.drain()
     for sid in range(8):
@@ -500,6 +503,9 @@ def bench_serving(torch, ofmi, dev, pool, workers, frames_per_stream, with_cpu=T
     # is only timed and its output planes go back to the executor's pool
     ts = frames_per_stream // 2
     srv = Server(exe, keep=lambda r: r.frame is pinned[r.stream_id][ts], max_inflight=max_inflight)
+    for sid in range(8):                     # sessions open before the first frame arrives
+        srv.open_stream(sid, sizes[sid])
+    gc.collect()
     st = srv.replay(arrivals, realtime=True)
     sampled = []
     for r in srv.done:

@@ -120,7 +120,8 @@ typedef struct of_plan of_plan;
 OF_API size_t of_plan_workspace_bytes(int H, int W, int levels, int radius, int iters,
                                       unsigned flags);
 
-/* Plan for one frame size: H x W frames, `levels` pyramid levels including full resolution
+/* Plan for one frame size: H x W frames (1 <= H, W < 2^24, H * W < 2^30; every plan, batch
+ * and server checks these sizes), `levels` pyramid levels including full resolution
  * (1 <= levels <= min(OF_MAX_LEVELS, 1 + floor(log2(min(H, W))))), window radius
  * 0 <= radius <= OF_MAX_RADIUS, 0 <= iters <= OF_MAX_ITERS iterations per level (Sec. 2.4,
  * eq. 1).  uint8 frames, FP32 storage.  The plan allocates its own workspace.

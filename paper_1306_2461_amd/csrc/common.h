@@ -63,6 +63,37 @@ __device__ __forceinline__ void st(__half* p, unsigned i, float x) {
   at(reinterpret_cast<unsigned short*>(p), i) = __half_as_ushort(__float2half_rn(x));
 }
 
+// Row-major offset y * W + x with a 24-bit multiply: the full-rate v_mul_u32_u24 (the 32-bit
+// integer multiply issues at a quarter of the rate).  Plans keep H and W below 2^24 and H * W
+// below 2^30, so every product of an in-image row and a width fits.
+__device__ __forceinline__ unsigned rowofs(int y, int W, int x) {
+  return __umul24((unsigned)y, (unsigned)W) + (unsigned)x;
+}
+
+// i / D and i % D for a compile-time divisor D and 0 <= i < LIMIT: a 24-bit multiply by
+// floor(2^20 / D) + 1 and a shift (instead of the quarter-rate 32-bit high multiply), checked
+// exact for every i in range at compile time.
+template <int D, int LIMIT>
+struct ConstDiv {
+  static constexpr unsigned S = 20, M = (1u << S) / D + 1;
+  static constexpr bool exact() {
+    for (unsigned i = 0; i < (unsigned)LIMIT; ++i)
+      if (((i * M) >> S) != i / (unsigned)D) return false;
+    return true;
+  }
+  static_assert(D > 0 && (unsigned long long)LIMIT * M < (1ull << 32) && exact(),
+                "24-bit reciprocal multiply not exact over the index range");
+  __device__ static __forceinline__ unsigned q(unsigned i) {
+    if constexpr ((D & (D - 1)) == 0) return i / (unsigned)D;
+    else return __umul24(i, M) >> S;
+  }
+  // (a signed 24-bit multiply by -D, so that the subtraction folds into one full-rate
+  // multiply-add rather than a 32-bit one)
+  __device__ static __forceinline__ unsigned r(unsigned i, unsigned q) {
+    return i + (unsigned)__mul24((int)q, -D);
+  }
+};
+
 // Integer base and fraction of the sample coordinate x + d along one axis of length n,
 // clamped into [0, n-1].  Splitting d = floor(d) + frac keeps the coordinate exact in FP32
 // (x + d itself would round to the spacing of |x|).  The sample is interior when its base
@@ -85,7 +116,7 @@ __device__ __forceinline__ float warp_sample(const T* __restrict__ I, int H, int
   unsigned sx, sy;
   const int xi = split_coord(x, u, W, a, sx);
   const int yi = split_coord(y, v, H, b, sy);
-  const unsigned o00 = (unsigned)yi * (unsigned)W + (unsigned)xi;
+  const unsigned o00 = rowofs(yi, W, xi);
   const unsigned dy = sy * (unsigned)W;
   const float z00 = ld(I, o00), z01 = ld(I, o00 + sx);
   const float z10 = ld(I, o00 + dy), z11 = ld(I, o00 + dy + sx);
@@ -99,7 +130,7 @@ __device__ __forceinline__ float warp_sample(const T* __restrict__ I, int H, int
 template <int MODE>
 __device__ __forceinline__ void read_flow(const IterArgs& a, int x, int y, float& u, float& v) {
   if constexpr (MODE == kFlowSame) {
-    const unsigned i = (unsigned)y * (unsigned)a.W + (unsigned)x;
+    const unsigned i = rowofs(y, a.W, x);
     u = at(a.uin, i);
     v = at(a.vin, i);
   } else if constexpr (MODE == kFlowCoarse) {
@@ -108,7 +139,7 @@ __device__ __forceinline__ void read_flow(const IterArgs& a, int x, int y, float
     const unsigned dx = x0 < a.Wc - 1 ? 1u : 0u;
     const unsigned dy = y0 < a.Hc - 1 ? (unsigned)a.Wc : 0u;
     const float fa = (x & 1) ? 0.5f : 0.f, fb = (y & 1) ? 0.5f : 0.f;
-    const unsigned i00 = (unsigned)y0 * (unsigned)a.Wc + (unsigned)x0;
+    const unsigned i00 = rowofs(y0, a.Wc, x0);
     const unsigned i01 = i00 + dx, i10 = i00 + dy, i11 = i00 + dy + dx;
     const float u00 = at(a.uin, i00), u01 = at(a.uin, i01), u10 = at(a.uin, i10), u11 = at(a.uin, i11);
     const float v00 = at(a.vin, i00), v01 = at(a.vin, i01), v10 = at(a.vin, i10), v11 = at(a.vin, i11);

@@ -177,8 +177,9 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     float wu[C::K1], wv[C::K1];
 #pragma unroll
     for (int k = 0; k < C::K1; ++k) {
-      const int i = min(tid + k * NT, nw - 1);
-      const int w = wfirst + i / WC, lx = i % WC;
+      using DW = ConstDiv<WC, C::P1_ROWS_MAX * WC>;
+      const unsigned i = (unsigned)min(tid + k * NT, nw - 1), qi = DW::q(i);
+      const int w = wfirst + (int)qi, lx = (int)DW::r(i, qi);
       if constexpr (INTERIOR) {
         wgx[k] = x0 - R - 1 + lx;
         wgy[k] = y0 - R + w;
@@ -205,21 +206,22 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     if constexpr (!LEAN) {
 #pragma unroll
       for (int k = 0; k < C::K2; ++k) {
-        const int i = min(tid + k * NT, NR * PC - 1);
-        int gx = x0 - R + i % PC, gy = y0 - R + tb + i / PC;
+        using DP = ConstDiv<PC, NR * PC>;
+        const unsigned i = (unsigned)min(tid + k * NT, NR * PC - 1), qi = DP::q(i);
+        int gx = x0 - R + (int)DP::r(i, qi), gy = y0 - R + tb + (int)qi;
         if constexpr (!INTERIOR) {
           gx = min(max(gx, 0), W - 1);
           gy = min(max(gy, 0), H - 1);
         }
-        i1v[k] = ld(I1, (unsigned)gy * (unsigned)W + (unsigned)gx);
+        i1v[k] = ld(I1, rowofs(gy, W, gx));
         if constexpr (kLoadField) read_flow<MODE>(a, gx, gy, pu[k], pv[k]);
       }
       if constexpr (kLoadField) {
 #pragma unroll
         for (int k = 0; k < C::K5; ++k) {
           const int i = min(tid + k * NT, NR * TW - 1);
-          const int gx = INTERIOR ? x0 + i % TW : min(x0 + i % TW, W - 1);
-          const int gy = min(max(y0 + tb + i / TW - 2 * R, 0), H - 1);
+          const int gx = INTERIOR ? x0 + (int)((unsigned)i % TW) : min(x0 + (int)((unsigned)i % TW), W - 1);
+          const int gy = min(max(y0 + tb + (int)((unsigned)i / TW) - 2 * R, 0), H - 1);
           read_flow<MODE>(a, gx, gy, cu[k], cv[k]);
         }
       }
@@ -233,21 +235,22 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
       __builtin_amdgcn_sched_barrier(0);   // compiler-only fence
 #pragma unroll
       for (int k = 0; k < C::K2; ++k) {
-        const int i = min(tid + k * NT, NR * PC - 1);
-        int gx = x0 - R + i % PC, gy = y0 - R + tb + i / PC;
+        using DP = ConstDiv<PC, NR * PC>;
+        const unsigned i = (unsigned)min(tid + k * NT, NR * PC - 1), qi = DP::q(i);
+        int gx = x0 - R + (int)DP::r(i, qi), gy = y0 - R + tb + (int)qi;
         if constexpr (!INTERIOR) {
           gx = min(max(gx, 0), W - 1);
           gy = min(max(gy, 0), H - 1);
         }
-        i1v[k] = ld(I1, (unsigned)gy * (unsigned)W + (unsigned)gx);
+        i1v[k] = ld(I1, rowofs(gy, W, gx));
         if constexpr (kLoadField) read_flow<MODE>(a, gx, gy, pu[k], pv[k]);
       }
       if constexpr (kLoadField) {
 #pragma unroll
         for (int k = 0; k < C::K5; ++k) {
           const int i = min(tid + k * NT, NR * TW - 1);
-          const int gx = INTERIOR ? x0 + i % TW : min(x0 + i % TW, W - 1);
-          const int gy = min(max(y0 + tb + i / TW - 2 * R, 0), H - 1);
+          const int gx = INTERIOR ? x0 + (int)((unsigned)i % TW) : min(x0 + (int)((unsigned)i % TW), W - 1);
+          const int gy = min(max(y0 + tb + (int)((unsigned)i / TW) - 2 * R, 0), H - 1);
           read_flow<MODE>(a, gx, gy, cu[k], cv[k]);
         }
       }
@@ -257,8 +260,9 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     if constexpr (kDefer) {
 #pragma unroll
       for (int k = 0; k < C::K2; ++k) {
-        const int i = min(tid + k * NT, NR * PC - 1);
-        int gx = x0 - R + i % PC, gy = y0 - R + tb + i / PC;
+        using DP = ConstDiv<PC, NR * PC>;
+        const unsigned i = (unsigned)min(tid + k * NT, NR * PC - 1), qi = DP::q(i);
+        int gx = x0 - R + (int)DP::r(i, qi), gy = y0 - R + tb + (int)qi;
         if constexpr (!INTERIOR) {
           gx = min(max(gx, 0), W - 1);
           gy = min(max(gy, 0), H - 1);
@@ -270,7 +274,8 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     for (int k = 0; k < C::K2; ++k) {
       const int i = tid + k * NT;
       if (i < NR * PC) {
-        const int r = i / PC, c = i % PC;
+        using DP = ConstDiv<PC, NR * PC>;
+        const int r = (int)DP::q((unsigned)i), c = (int)DP::r((unsigned)i, (unsigned)r);
         const int t = tb + r;
         const int gx = x0 - R + c, gy = y0 - R + t;
         float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f, p4 = 0.f;
@@ -316,7 +321,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     for (int k = 0; k < C::K3; ++k) {
       const int i = tid + k * NT;
       if (i < 5 * NR * C::NSEG) {
-        const int seg = i % C::NSEG, rr = i / C::NSEG;   // rr = ch * NR + row
+        const int seg = (int)((unsigned)i % C::NSEG), rr = (int)((unsigned)i / C::NSEG);   // ch * NR + row
         typedef float f4v __attribute__((ext_vector_type(4)));
         const f4v* src = reinterpret_cast<const f4v*>(pr + rr * PP + 8 * seg);
         float vbuf[4 * C::HL4];
@@ -377,7 +382,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     for (int k = 0; k < C::K3; ++k) {
       const int i = tid + k * NT;
       if (i < 5 * NR * C::NSEG) {
-        const int seg = i % C::NSEG, rr = i / C::NSEG;
+        const int seg = (int)((unsigned)i % C::NSEG), rr = (int)((unsigned)i / C::NSEG);
         float4* dst = reinterpret_cast<float4*>(hs + rr * C::TW + 8 * seg);
         dst[0] = make_float4(hv[k][0], hv[k][1], hv[k][2], hv[k][3]);
         dst[1] = make_float4(hv[k][4], hv[k][5], hv[k][6], hv[k][7]);
@@ -427,8 +432,8 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
 #pragma unroll
       for (int k = 0; k < C::K5; ++k) {
         const int i = min(tid + k * NT, NR * TW - 1);
-        const int gx = INTERIOR ? x0 + i % TW : min(x0 + i % TW, W - 1);
-        const int gy = min(max(y0 + tb + i / TW - 2 * R, 0), H - 1);
+        const int gx = INTERIOR ? x0 + (int)((unsigned)i % TW) : min(x0 + (int)((unsigned)i % TW), W - 1);
+        const int gy = min(max(y0 + tb + (int)((unsigned)i / TW) - 2 * R, 0), H - 1);
         read_flow<MODE>(a, gx, gy, cu[k], cv[k]);
       }
     }
@@ -436,7 +441,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     for (int k = 0; k < C::K5; ++k) {
       const int i = tid + k * NT;
       if (i < NR * TW) {
-        const int r = i / TW, c = i % TW;
+        const int r = (int)((unsigned)i / TW), c = (int)((unsigned)i % TW);
         const int j = tb + r - 2 * R;
         const int gx = x0 + c, gy = y0 + j;
         if (j >= 0 && j < TH && (INTERIOR || (gx < W && gy < H))) {
@@ -452,7 +457,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
           float un, vn;
           solve_update(s[0], s[NR * TW], s[2 * NR * TW], s[3 * NR * TW], s[4 * NR * TW], fu, fv,
                        un, vn);
-          const unsigned o = (unsigned)gy * (unsigned)W + (unsigned)gx;
+          const unsigned o = rowofs(gy, W, gx);
           if (pixel_mask && at(a.mask, o) == 0) {   // masked-out pixel: zero flow
             un = 0.f;
             vn = 0.f;

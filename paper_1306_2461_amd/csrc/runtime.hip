@@ -24,6 +24,7 @@ static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 bool check_params(int H, int W, int levels, int radius, int iters, unsigned flags) {
   if (H < 1 || W < 1) return set_error("H and W must be >= 1"), false;
   if ((long long)H * W >= (1ll << 30)) return set_error("H * W must be below 2^30"), false;
+  if (H >= (1 << 24) || W >= (1 << 24)) return set_error("H and W must be below 2^24"), false;
   if (levels < 1 || levels > OF_MAX_LEVELS) return set_error("levels out of range"), false;
   int m = H < W ? H : W, maxl = 1;
   while (m >= 2) { m >>= 1; ++maxl; }

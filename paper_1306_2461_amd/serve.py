@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import gc
 import time
 from typing import Any
 
@@ -98,21 +99,39 @@ class Server:
 
     # ------------------------------------------------------------------ loop
     def _admit(self, req: Request):
-        h = self.sessions.get(req.stream_id)
+        h = self._open(req.stream_id, tuple(req.frame.shape))
+        if h == "reject":
+            H, W = req.frame.shape
+            req.error = (f"stream needs {self.ex.session_bytes(H, W)} bytes, more than the whole "
+                         f"budget {self.ex.budget}")
+        return h
+
+    def _open(self, stream_id: int, shape: tuple):
+        h = self.sessions.get(stream_id)
         if h is not None:
             return h
-        H, W = req.frame.shape
+        H, W = shape
         need = self.ex.session_bytes(H, W)
         if self.ex.budget and need > self.ex.budget:
-            req.error = f"stream needs {need} bytes, more than the whole budget {self.ex.budget}"
             return "reject"
         try:
             h = self.ex.open(H, W)
         except BudgetExceeded:
             return None
-        self.sessions[req.stream_id] = h
-        self.admission_log.append((self.clock(), "open", req.stream_id))
+        self.sessions[stream_id] = h
+        self.admission_log.append((self.clock(), "open", stream_id))
         return h
+
+    def open_stream(self, stream_id: int, shape: tuple) -> bool:
+        """Admits a stream before its first frame arrives, so that opening its session (which
+        may allocate) stays out of the request path; False if the budget has no room now."""
+        shape = tuple(shape)
+        if self.sizes.setdefault(stream_id, shape) != shape:
+            raise ValueError(f"stream {stream_id} has frames of size {self.sizes[stream_id]}")
+        h = self._open(stream_id, shape)
+        if h == "reject":
+            raise BudgetExceeded(f"stream {stream_id} of size {shape} can never fit the budget")
+        return h is not None
 
     def step(self) -> int:
         """Launch one push with the oldest pending frame of every admitted stream."""
@@ -182,7 +201,18 @@ class Server:
     def replay(self, arrivals, realtime: bool = True):
         """Serve (t, stream_id, frame) arrivals (sorted by t), optionally paced in real time.
 
-        Returns per-pair latency percentiles and throughput over the flows computed."""
+        Returns per-pair latency percentiles and throughput over the flows computed.  The
+        garbage collector is paused while the loop runs (its pauses would land in the tail)."""
+        gc_on = gc.isenabled()
+        gc.disable()
+        try:
+            self._replay(arrivals, realtime)
+        finally:
+            if gc_on:
+                gc.enable()
+        return self.stats()
+
+    def _replay(self, arrivals, realtime):
         t0 = self.clock()
         i = 0
         while i < len(arrivals) or self.pending or self.inflight:
@@ -200,7 +230,6 @@ class Server:
                     time.sleep(max(0.0, min(2e-4, arrivals[i][0] - (self.clock() - t0))))
                 elif self.pending and not self.inflight:
                     raise RuntimeError("pending requests cannot be admitted (HBM budget)")
-        return self.stats()
 
     def stats(self):
         flows = [r for r in self.done if r.has_flow]

@@ -51,8 +51,11 @@ def test_workspace_bytes_and_validation(lib):
     expect16 = sum(2 * a(h * w * 2) for h, w in sizes) + 4 * a(H * W * 4)
     assert lib.of_plan_workspace_bytes(H, W, 3, 4, 4, 1) == expect16
     for bad in [(0, 5, 1, 1, 1, 0), (5, 5, 0, 1, 1, 0), (4, 4, 4, 1, 1, 0), (64, 64, 2, -1, 1, 0),
-                (64, 64, 2, 99, 1, 0), (64, 64, 2, 2, -1, 0), (64, 64, 2, 2, 1, 64)]:
+                (64, 64, 2, 99, 1, 0), (64, 64, 2, 2, -1, 0), (64, 64, 2, 2, 1, 64),
+                (1, 1 << 24, 1, 1, 1, 0), (1 << 24, 1, 1, 1, 1, 0), (1 << 15, 1 << 15, 1, 1, 1, 0)]:
         assert lib.of_plan_workspace_bytes(*bad) == 0
+    # widths and heights up to 2^24 - 1 (24-bit row offsets) with H * W below 2^30
+    assert lib.of_plan_workspace_bytes(1, (1 << 24) - 1, 1, 1, 1, 0) > 0
     # OF_FLAG_NORMALIZE adds two level-0 float32 planes; the Gaussian window needs nothing more
     assert lib.of_plan_workspace_bytes(H, W, 3, 4, 4, 8) == expect + 2 * a(H * W * 4)
     assert lib.of_plan_workspace_bytes(H, W, 3, 4, 4, 16) == expect

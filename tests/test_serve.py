@@ -4,7 +4,7 @@ import pytest
 
 import oracle
 import synth
-from paper_1306_2461_amd.serve import Server, poisson_arrivals
+from paper_1306_2461_amd.serve import BudgetExceeded, Server, poisson_arrivals
 from serve_fake import FakeClock, FakeExecutor
 
 
@@ -144,3 +144,20 @@ def test_inflight_bound_merges_arrivals_into_one_push():
         srv.drain()
         assert ex.pushes == expect, (bound, ex.pushes)
         assert len(srv.done) == 4 and all(not r.has_flow for r in srv.done)
+
+
+def test_open_stream_admits_ahead_and_checks_size():
+    clock = FakeClock()
+    ex = FakeExecutor(1, 2, 1, delay=0.5, clock=clock, budget_bytes=3 * (2 * 24 * 24 * 2 + 16 * 24 * 24))
+    srv = Server(ex, clock=clock)
+    assert srv.open_stream(0, (24, 24)) and srv.open_stream(1, (24, 24))
+    assert ex.resident == 2 * ex.session_bytes(24, 24) and len(srv.admission_log) == 2
+    with pytest.raises(ValueError):
+        srv.open_stream(0, (32, 32))
+    with pytest.raises(BudgetExceeded):
+        srv.open_stream(2, (480, 640))           # never fits
+    assert srv.open_stream(3, (24, 24)) and not srv.open_stream(4, (24, 24))   # full for now
+    fr = _frames(0, 2, (24, 24))
+    reqs = [srv.submit(0, f) for f in fr]
+    srv.drain()
+    assert ex.pushes == [1, 1] and reqs[1].has_flow and len(srv.admission_log) == 3
