@@ -3,7 +3,8 @@
 // gradients of the warped frame, the five window sums, the 2x2 solve and the update.
 //
 // Work decomposition (gfx950, wave64):
-//   * a workgroup of 5*TW threads (narrow) or 10*TW threads (wide) owns a strip of TW output
+//   * a workgroup of 5*TW threads (narrow) or at least 10*TW threads (wide, rounded up so the
+//     warped-frame positions of a band take few rounds per thread) owns a strip of TW output
 //     columns and TH output rows;
 //   * it walks down the strip in bands of N = 2r+1 product rows; per band:
 //       P1  warped frame for the band's new rows into an LDS ring; all global loads of the
@@ -40,12 +41,31 @@ __device__ __forceinline__ void add_count(unsigned long long* dst, unsigned c) {
   if ((threadIdx.x & 63) == 0 && c) atomicAdd(dst, (unsigned long long)c);
 }
 
+// Threads per workgroup.  Narrow variants: 5 per output column.  Wide variants: at least 10
+// per column, rounded up so that the warped-frame positions of a steady band (every band but
+// a tile's first, which also samples the two rows above) take as few rounds of items per
+// thread as 10 per column would give with the remainder spread out: e.g. r = 8 on 64-column
+// strips samples 17 x 82 positions per band, 3 rounds at 640 threads (73 % of the lanes busy)
+// and 2 rounds at 704 (99 %).
+template <int R, int TW, bool WIDE, int BB>
+constexpr int group_threads() {
+  if (!WIDE) return 5 * TW * BB;
+  const int N = 2 * R + 1, WC = TW + 2 * R + 2;
+  const int items = (BB == 1 ? N : BB * N + 2) * WC;
+  const int base = 10 * TW * BB;
+  const int k = items / base > 1 ? items / base : 1;
+  int nt = ((items + k - 1) / k + 63) / 64 * 64;
+  if (nt < base) nt = base;
+  if (nt > 1024) nt = base;
+  return nt;
+}
+
 template <int R, int TW_, bool WIDE = false, int BB = 1>
 struct Cfg {
   static constexpr int N = 2 * R + 1;                 // band height = window height
   static constexpr int NR = BB * N;                   // product rows per pass (BB bands)
   static constexpr int TW = TW_;                      // output columns per strip
-  static constexpr int NT = (WIDE ? 10 : 5) * TW * BB;   // threads per workgroup
+  static constexpr int NT = group_threads<R, TW_, WIDE, BB>();   // threads per workgroup
   static constexpr int PC = TW + 2 * R;               // product columns
   static constexpr int WC = PC + 2;                   // warped-frame columns
   static constexpr int HL = 8 + 2 * R;                // products read per horizontal segment
@@ -59,6 +79,8 @@ struct Cfg {
   static constexpr int NSEG = TW / 8;
   static constexpr int P1_ROWS_MAX = NR + 2;
   static constexpr int K1 = (P1_ROWS_MAX * WC + NT - 1) / NT;   // P1 items per thread
+  // ... in a pass after a tile's first (one band per pass: N new rows)
+  static constexpr int K1S = ((BB == 1 ? N : P1_ROWS_MAX) * WC + NT - 1) / NT;
   static constexpr int K2 = (NR * PC + NT - 1) / NT;            // P2 items per thread
   static constexpr int K3 = (5 * NR * NSEG + NT - 1) / NT;      // P3 items per thread
   static constexpr int K5 = (NR * TW + NT - 1) / NT;            // P5 items per thread
@@ -177,6 +199,7 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     float wu[C::K1], wv[C::K1];
 #pragma unroll
     for (int k = 0; k < C::K1; ++k) {
+      if (k >= C::K1S && b != 0) break;   // uniform: only a tile's first pass has these
       using DW = ConstDiv<WC, C::P1_ROWS_MAX * WC>;
       const unsigned i = (unsigned)min(tid + k * NT, nw - 1), qi = DW::q(i);
       const int w = wfirst + (int)qi, lx = (int)DW::r(i, qi);
@@ -230,7 +253,10 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
     // value to the identical slot, so the stores need no guard: a guard lets the compiler
     // sink each item's gathers into its own branch and wait for them one item at a time.
 #pragma unroll
-    for (int k = 0; k < C::K1; ++k) w2[wofs[k]] = warp_sample(I2, H, W, wgx[k], wgy[k], wu[k], wv[k]);
+    for (int k = 0; k < C::K1; ++k) {
+      if (k >= C::K1S && b != 0) break;
+      w2[wofs[k]] = warp_sample(I2, H, W, wgx[k], wgy[k], wu[k], wv[k]);
+    }
     if constexpr (LEAN) {
       __builtin_amdgcn_sched_barrier(0);   // compiler-only fence
 #pragma unroll
@@ -516,7 +542,7 @@ __device__ __forceinline__ int xcd_order(int b, int nblocks) {
 }
 
 template <typename T, int R, int TW, int MODE, bool WIDE, bool LEAN, bool GAUSS, int BB>
-__global__ __launch_bounds__((WIDE ? 10 : 5) * TW * BB) void lk_iter_strip(IterArgs a, int TH,
+__global__ __launch_bounds__((group_threads<R, TW, WIDE, BB>())) void lk_iter_strip(IterArgs a, int TH,
                                                                            int nbands, int tiles_x,
                                                                            int ntiles) {
   extern __shared__ float4 sm4[];
@@ -549,7 +575,7 @@ __global__ __launch_bounds__((WIDE ? 10 : 5) * TW * BB) void lk_iter_strip(IterA
 // MASK: launches of batches with masks (the mask code costs the unmasked launches about 5 %
 // more instructions and is compiled out of them).
 template <typename T, int R, int TW, int MODE, bool WIDE, bool LEAN, bool GAUSS, bool MASK>
-__global__ __launch_bounds__((WIDE ? 10 : 5) * TW) void lk_iter_batch(const IterArgs* __restrict__ args,
+__global__ __launch_bounds__((group_threads<R, TW, WIDE, 1>())) void lk_iter_batch(const IterArgs* __restrict__ args,
                                                                       const int4* __restrict__ tiles,
                                                                       int ntiles) {
   extern __shared__ float4 sm4[];
