@@ -655,7 +655,7 @@ of_status of_batch_autotune(of_batch* b, const void* const* I1, const void* cons
   const int was_mode = b->timer.mode;
   b->timer.on = true;
   b->timer.mode = OF_TIMING_LAUNCH;
-  static const int kBands[] = {1, 2, 4, 8};
+  static const int kBands[] = {1, 2, 4, 8, 16};
   static const int kGrid[] = {0, 256, 512, 1024, 2048};
   static const int kVariant[] = {kTileNarrow, kTileWide, kTileWideLean};
   hipError_t e = hipSuccess;
