@@ -42,18 +42,18 @@ __device__ __forceinline__ void add_count(unsigned long long* dst, unsigned c) {
 }
 
 // Threads per workgroup.  Narrow variants: 5 per output column.  Wide variants: at least 10
-// per column, rounded up so that the warped-frame positions of a steady band (every band but
-// a tile's first, which also samples the two rows above) take as few rounds of items per
-// thread as 10 per column would give with the remainder spread out: e.g. r = 8 on 64-column
+// per column, and enough that the warped-frame positions of a steady pass (every pass but a
+// tile's first, which also samples the two rows above) take the fewest rounds of items per
+// thread that a workgroup of at most 1024 allows, spread evenly: e.g. r = 8 on 64-column
 // strips samples 17 x 82 positions per band, 3 rounds at 640 threads (73 % of the lanes busy)
-// and 2 rounds at 704 (99 %).
+// and 2 rounds at 704 (99 %); on 32-column strips 17 x 50 positions, one round at 896.
 template <int R, int TW, bool WIDE, int BB>
 constexpr int group_threads() {
   if (!WIDE) return 5 * TW * BB;
   const int N = 2 * R + 1, WC = TW + 2 * R + 2;
   const int items = (BB == 1 ? N : BB * N + 2) * WC;
   const int base = 10 * TW * BB;
-  const int k = items / base > 1 ? items / base : 1;
+  const int k = (items + 1023) / 1024;
   int nt = ((items + k - 1) / k + 63) / 64 * 64;
   if (nt < base) nt = base;
   if (nt > 1024) nt = base;
