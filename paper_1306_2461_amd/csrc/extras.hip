@@ -15,7 +15,7 @@ namespace {
 
 constexpr int NTW = 64, NTH = 16;    // output tile of the normalisation kernel
 
-// Window sums in FP64 (exact for 8-bit input), separable: the tile's input window is staged
+// Window sums in FP64 (float frames; 8-bit frames take the integer kernel below), separable: the tile's input window is staged
 // in LDS first (every load of a thread in flight together; pixels outside the image held as
 // 0), then row sums of the tile's rows into LDS, then column sums per output pixel.  The sums
 // run over the in-image pixels in ascending order, as a direct sum over the frame would.
@@ -92,6 +92,96 @@ __global__ __launch_bounds__(256) void normalize_kernel(const T* __restrict__ in
     const unsigned o = (unsigned)gy * (unsigned)W + (unsigned)gx;
     const double c = (double)win[(ly + r) * cols + lx + r];
     at(out, o) = (float)((c - m) / (sd + (double)eps));
+  }
+}
+
+// 8-bit frames: the window sums of I and I^2 are integers below 2^31 (at most 33 x 33 x 255^2),
+// so they are formed exactly in int32 as sliding sums (one addition and one subtraction per
+// step instead of 2r+1 FP64 additions): the same values as the FP64 sums above, hence the
+// same bits after the FP64 division and square root below.
+constexpr int kSeg = 8;              // outputs per thread of a sliding row or column sum
+
+inline size_t normalize_u8_lds_bytes(int r) {
+  const size_t rows = NTH + 2 * (size_t)r, cols = NTW + 2 * (size_t)r;
+  return sizeof(int) * (2 * rows * NTW + rows * cols);
+}
+
+__global__ __launch_bounds__(256) void normalize_u8_kernel(const uint8_t* __restrict__ in,
+                                                           float* __restrict__ out, int H, int W,
+                                                           int r, float eps) {
+  extern __shared__ int ri[];        // [rows * NTW] sums of I, the same of I^2, then the window
+  const int x0 = blockIdx.x * NTW, y0 = blockIdx.y * NTH;
+  const int rows = NTH + 2 * r, cols = NTW + 2 * r;
+  int* s1 = ri;
+  int* s2 = ri + rows * NTW;
+  int* win = s2 + rows * NTW;        // [rows][cols] from (y0-r, x0-r), 0 outside the image
+  {
+    constexpr int NL = (kNormRowsMax * kNormColsMax + 255) / 256;
+    const int n = rows * cols;
+    int v[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      if (256 * k >= n) break;   // uniform across the workgroup
+      const int e = min((int)threadIdx.x + 256 * k, n - 1);
+      const int ly = e / cols, lx = e - ly * cols;
+      const int gy = y0 - r + ly, gx = x0 - r + lx;
+      const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
+      const unsigned o = (unsigned)min(max(gy, 0), H - 1) * (unsigned)W + (unsigned)min(max(gx, 0), W - 1);
+      const int val = (int)at(in, o);
+      v[k] = inside ? val : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      if (256 * k >= n) break;
+      win[min((int)threadIdx.x + 256 * k, n - 1)] = v[k];
+    }
+  }
+  __syncthreads();
+  // row sums: output column lx covers window columns lx .. lx + 2r (pixels outside the image
+  // are 0, which truncates the window at the border)
+  for (int i = threadIdx.x; i < rows * (NTW / kSeg); i += 256) {
+    const int ly = i / (NTW / kSeg), lx0 = (i - ly * (NTW / kSeg)) * kSeg;
+    const int* row = win + ly * cols;
+    int a = 0, b = 0;
+    for (int x = lx0; x <= lx0 + 2 * r; ++x) {
+      a += row[x];
+      b += row[x] * row[x];
+    }
+    s1[ly * NTW + lx0] = a;
+    s2[ly * NTW + lx0] = b;
+#pragma unroll
+    for (int j = 1; j < kSeg; ++j) {
+      const int add = row[lx0 + j + 2 * r], sub = row[lx0 + j - 1];
+      a += add - sub;
+      b += add * add - sub * sub;
+      s1[ly * NTW + lx0 + j] = a;
+      s2[ly * NTW + lx0 + j] = b;
+    }
+  }
+  __syncthreads();
+  // column sums and the equalised value: thread (column, group of NTH/4 rows), sliding down
+  constexpr int RG = NTH / 4;
+  const int lx = threadIdx.x % NTW, ly0 = (threadIdx.x / NTW) * RG;
+  const int gx = x0 + lx;
+  int a = 0, b = 0;
+  for (int dy = 0; dy <= 2 * r; ++dy) {
+    a += s1[(ly0 + dy) * NTW + lx];
+    b += s2[(ly0 + dy) * NTW + lx];
+  }
+  for (int j = 0; j < RG; ++j) {
+    if (j > 0) {
+      a += s1[(ly0 + j + 2 * r) * NTW + lx] - s1[(ly0 + j - 1) * NTW + lx];
+      b += s2[(ly0 + j + 2 * r) * NTW + lx] - s2[(ly0 + j - 1) * NTW + lx];
+    }
+    const int gy = y0 + ly0 + j;
+    if (gy >= H || gx >= W) continue;
+    const int nx = min(gx + r, W - 1) - max(gx - r, 0) + 1;
+    const int ny = min(gy + r, H - 1) - max(gy - r, 0) + 1;
+    const double n = (double)nx * ny;
+    const double m = (double)a / n, m2 = (double)b / n;
+    const double sd = sqrt(fmax(m2 - m * m, 0.0));
+    const double c = (double)win[(ly0 + j + r) * cols + lx + r];
+    at(out, (unsigned)gy * (unsigned)W + (unsigned)gx) = (float)((c - m) / (sd + (double)eps));
   }
 }
 
@@ -236,16 +326,12 @@ hipError_t launch_normalize(Elem t, const void* in, float* out, int H, int W, in
   dim3 grid((W + NTW - 1) / NTW, (H + NTH - 1) / NTH);
   const size_t lds = normalize_lds_bytes(r);
   // Up to 67.5 KB at the largest radius: opt in to more than 64 KB of dynamic LDS, once.
-  static const hipError_t opt8 = hipFuncSetAttribute(
-      reinterpret_cast<const void*>(&normalize_kernel<uint8_t>),
-      hipFuncAttributeMaxDynamicSharedMemorySize, (int)normalize_lds_bytes(OF_MAX_NORMALIZE_RADIUS));
   static const hipError_t opt32 = hipFuncSetAttribute(
       reinterpret_cast<const void*>(&normalize_kernel<float>),
       hipFuncAttributeMaxDynamicSharedMemorySize, (int)normalize_lds_bytes(OF_MAX_NORMALIZE_RADIUS));
   if (t == Elem::U8) {
-    if (opt8 != hipSuccess) return opt8;
-    hipLaunchKernelGGL(normalize_kernel<uint8_t>, grid, dim3(256), lds, s, (const uint8_t*)in, out,
-                       H, W, r, eps);
+    hipLaunchKernelGGL(normalize_u8_kernel, grid, dim3(256), normalize_u8_lds_bytes(r), s,
+                       (const uint8_t*)in, out, H, W, r, eps);
   } else if (t == Elem::F32) {
     if (opt32 != hipSuccess) return opt32;
     hipLaunchKernelGGL(normalize_kernel<float>, grid, dim3(256), lds, s, (const float*)in, out, H,

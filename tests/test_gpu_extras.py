@@ -18,10 +18,14 @@ def test_normalize_matches_oracle(gpu_lib, shape, r):
     announce(f"normalize {shape} r={r}")
     out = ofmi.normalize(to_dev(I), r, 1.0)
     fout = ofmi.normalize(to_dev(I.astype(np.float32) * np.float32(0.5)), r, 0.5)
+    f1 = ofmi.normalize(to_dev(I.astype(np.float32)), r, 1.0)
     torch.cuda.synchronize()
     ref = oracle.local_normalize(I, r, 1.0)
     np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=2e-6, atol=2e-6)
     np.testing.assert_allclose(fout.cpu().numpy(), ref, rtol=2e-6, atol=2e-6)
+    # the 8-bit kernel's exact integer sliding sums equal the float kernel's FP64 sums of the
+    # same values, so the two give the same bits
+    assert np.array_equal(out.cpu().numpy(), f1.cpu().numpy())
 
 
 def test_plan_with_normalisation_matches_oracle(gpu_lib):

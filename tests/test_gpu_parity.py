@@ -301,3 +301,51 @@ def test_two_band_variants_at_radius_8(gpu_lib):
             big.set_config({"bands": [1], "variant": [w]})
     big.set_config({"bands": [1], "variant": [4]})
     big.close()
+
+
+DEGENERATE = [((1, 1), 1, 0, 2), ((1, 1), 1, 2, 2), ((1, 37), 1, 2, 3), ((29, 1), 1, 3, 3),
+              ((2, 3), 2, 1, 2), ((5, 5), 3, 1, 2), ((7, 300), 3, 4, 3), ((300, 7), 3, 4, 3),
+              ((3, 64), 2, 8, 2)]
+
+
+def _crop(H, W):
+    I1, I2, _, _ = synth.make_pair("c1", 7)
+    I1, I2 = np.tile(I1, (2, 2)), np.tile(I2, (2, 2))
+    assert 40 + H <= I1.shape[0] and 50 + W <= I1.shape[1]
+    return (np.ascontiguousarray(I1[40:40 + H, 50:50 + W]),
+            np.ascontiguousarray(I2[40:40 + H, 50:50 + W]))
+
+
+@pytest.mark.parametrize("shape,L,r,K", DEGENERATE)
+def test_degenerate_shapes_all_pixels(gpu_lib, shape, L, r, K):
+    """Single pixels, single rows and columns, frames narrower than one window and pyramids
+    down to one-pixel levels: every pixel against the oracle (the windows are truncated at
+    the borders and one-row frames have no vertical gradient, so the solve takes its rank-1
+    branch), with the FP32 floor computed here on the CPU for these few pixels."""
+    I1, I2 = _crop(*shape)
+    u, v = gpu_flow(gpu_lib, I1, I2, L, r, K)
+    ou, ov = oracle.flow(I1, I2, L, r, K)
+    d = flow_error(u, v, ou, ov)
+    floor, _ = floor_util.ensemble_floor(I1, I2, L, r, K)
+    print(floor_util.check_all_pixels(d, TOL32, floor, f"{shape} L={L} r={r} K={K}"))
+    if shape[0] == 1:
+        assert np.all(v == 0.0)      # no vertical gradient anywhere: v stays exactly zero
+    if shape[1] == 1:
+        assert np.all(u == 0.0)
+
+
+def test_degenerate_shapes_in_one_batch(gpu_lib):
+    """The degenerate one-level shapes as one batch: each flow equals its plain path's bits."""
+    import torch
+    ofmi = gpu_lib
+    shapes = [(1, 1), (1, 37), (29, 1), (2, 3), (4, 70)]
+    pairs = [_crop(*s) for s in shapes]
+    announce("batch of degenerate shapes")
+    b = ofmi.Batch(shapes, 1, 2, 3, device=dev())
+    us, vs = b.outputs()
+    b.compute([to_dev(p[0]) for p in pairs], [to_dev(p[1]) for p in pairs], us, vs)
+    torch.cuda.synchronize()
+    for i, p in enumerate(pairs):
+        pu, pv = gpu_flow(ofmi, p[0], p[1], 1, 2, 3)
+        assert np.array_equal(us[i].cpu().numpy(), pu) and np.array_equal(vs[i].cpu().numpy(), pv), shapes[i]
+    b.close()
