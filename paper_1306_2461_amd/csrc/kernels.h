@@ -79,6 +79,10 @@ struct BatchLaunch {
   int grid;
   int variant;   // TileVariant (narrow, wide, wide lean), plus kTileGauss for the Gaussian window
   bool masked;   // some pair of the launch has a mask (IterArgs::mask)
+  // Load the kernel this launch would run on the current device, without launching it (a
+  // kernel's first launch loads its code: milliseconds that a latency-bound caller primes
+  // ahead instead of paying on a request).
+  bool prime = false;
 };
 
 // Strip width (output columns per tile) of the iteration kernel for radius R (variants 0-2).
@@ -114,6 +118,9 @@ hipError_t launch_normalize(Elem t, const void* in, float* out, int H, int W, in
 
 // u = v = 0 over n elements (a fill kernel, safe under stream capture).
 hipError_t launch_zero(float* u, float* v, size_t n, hipStream_t s);
+// Copy of `bytes` bytes by a kernel on stream s (device memory, or pinned host memory through
+// its device mapping).
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 // *c = 0 (a one-thread kernel, safe under stream capture).
 hipError_t launch_zero_count(unsigned long long* c, hipStream_t s);

@@ -1,4 +1,7 @@
 // Dispatch of the fused iteration kernel by frame element type, and the zero fill.
+#include <algorithm>
+#include <cstdint>
+
 #include "kernels.h"
 
 namespace ofmi {
@@ -27,7 +30,29 @@ __global__ void zero_kernel(float* u, float* v, size_t n) {
   }
 }
 
+// dst[0..bytes) = src[0..bytes): 16-byte words when both are 16-byte aligned, then the tail.
+__global__ void copy_kernel(char* __restrict__ dst, const char* __restrict__ src, size_t bytes) {
+  const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t done = 0;
+  if ((((uintptr_t)dst | (uintptr_t)src) & 15) == 0) {
+    const size_t n16 = bytes / 16;
+    for (size_t i = tid; i < n16; i += stride)
+      reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
+    done = n16 * 16;
+  }
+  for (size_t i = done + tid; i < bytes; i += stride) dst[i] = src[i];
+}
+
 }  // namespace
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  const size_t words = (bytes + 15) / 16;
+  const unsigned grid = (unsigned)std::min<size_t>((words + 255) / 256, 1024);
+  hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, s, (char*)dst, (const char*)src, bytes);
+  return hipGetLastError();
+}
 
 hipError_t launch_iter(Elem t, const IterArgs& a, int R, int nb, int variant, hipStream_t s) {
   switch (t) {

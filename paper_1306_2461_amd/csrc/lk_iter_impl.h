@@ -680,6 +680,11 @@ hipError_t go_batch_m(const BatchLaunch& b, hipStream_t s) {
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds);
     if (opt != hipSuccess) return opt;
   }
+  if (b.prime) {
+    hipFuncAttributes attr;
+    return hipFuncGetAttributes(
+        &attr, reinterpret_cast<const void*>(&lk_iter_batch<T, R, TW, MODE, WIDE, LEAN, GAUSS, MASK>));
+  }
   hipLaunchKernelGGL((lk_iter_batch<T, R, TW, MODE, WIDE, LEAN, GAUSS, MASK>), dim3(b.grid),
                      dim3(C::NT), kLds, s, b.args, b.tiles, b.ntiles);
   return hipGetLastError();

@@ -82,6 +82,7 @@ struct of_server {
   // staging ring: kRing device and pinned host slots of slot_bytes each
   char* dev_blk = nullptr;
   char* host_blk = nullptr;
+  char* host_blk_dev = nullptr;   // the pinned slots' device mapping (read by the copy kernel)
   size_t slot_bytes = 0;
   hipEvent_t done[kRing] = {};
   bool in_use[kRing] = {};
@@ -90,6 +91,26 @@ struct of_server {
 };
 
 namespace {
+
+// Loads every iteration kernel a push of this server may launch (each level's frame type and
+// field source, the wide and wide lean tiles, with or without masks) on the current device, so
+// that no push pays a kernel's first-launch code load (about 10 ms measured on a request).
+hipError_t prime_push_kernels(const of_server* s, bool masked) {
+  const int side = 1 << (s->L - 1);
+  const Geometry g = make_geometry(side, side, s->L, s->R, s->K, s->flags);
+  BatchLaunch bl{};
+  bl.prime = true;
+  bl.masked = masked;
+  for (int l = 0; l < s->L; ++l)
+    for (int k = 0; k < std::min(s->K, 2); ++k)
+      for (int v : {(int)kTileWide, (int)kTileWideLean}) {
+        bl.variant = v | ((s->flags & OF_FLAG_GAUSSIAN_WINDOW) ? kTileGauss : 0);
+        const int mode = k > 0 ? kFlowSame : (l == s->L - 1 ? kFlowZero : kFlowCoarse);
+        const hipError_t e = launch_iter_batch(g.elem(l), bl, s->R, mode, nullptr);
+        if (e != hipSuccess) return e;
+      }
+  return hipSuccess;
+}
 
 size_t session_bytes(int H, int W, int L, int R, int K, unsigned flags, Geometry* gout,
                      size_t slot_off[2][OF_MAX_LEVELS], size_t* flow_off) {
@@ -168,6 +189,7 @@ size_t push_bound(const std::vector<of_session*>& ss, int L, int R, int K) {
 void free_ring(of_server* s) {
   if (s->dev_blk) hipFree(s->dev_blk);
   if (s->host_blk) hipHostFree(s->host_blk);
+  s->host_blk_dev = nullptr;
   s->dev_blk = nullptr;
   s->host_blk = nullptr;
   s->slot_bytes = 0;
@@ -183,7 +205,8 @@ hipError_t reserve_ring(of_server* s, size_t need) {
   free_ring(s);
   const size_t sb = align256(need + need / 4);
   e = hipMalloc((void**)&s->dev_blk, sb * kRing);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&s->host_blk, sb * kRing, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->host_blk, sb * kRing, hipHostMallocMapped);
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&s->host_blk_dev, s->host_blk, 0);
   if (e != hipSuccess) {
     free_ring(s);
     return e;
@@ -300,6 +323,7 @@ of_server* of_server_create(int levels, int radius, int iters, unsigned flags,
   hipError_t e = hipGetDevice(&s->device);
   for (int i = 0; i < kRing && e == hipSuccess; ++i)
     e = hipEventCreateWithFlags(&s->done[i], hipEventDisableTiming);
+  if (e == hipSuccess) e = prime_push_kernels(s, false);
   if (e != hipSuccess) {
     hip_fail("server set-up", e);
     destroy_server(s);
@@ -436,14 +460,18 @@ of_status of_server_push(of_server* s, of_session* const* ss, int n, const void*
   char* hblk = s->host_blk + (size_t)slot * s->slot_bytes;
   char* dblk = s->dev_blk + (size_t)slot * s->slot_bytes;
   pack(p, hblk);
-  // 2. new frames into their slots (level 0), the arguments into the device slot
+  // 2. new frames into their slots (level 0), the arguments into the device slot.  Both are
+  // copy kernels on the push's stream (the arguments read from the pinned slot through its
+  // device mapping): the runtime's asynchronous host-to-device copy from pinned memory blocked
+  // the calling thread for about 9 ms once in a few hundred pushes, which dominated the
+  // latency tail of served streams.
   hipError_t e = hipSuccess;
   for (int i = 0; i < n && e == hipSuccess; ++i) {
     of_session* x = ss[i];
-    e = hipMemcpyAsync(x->mem + x->slot_off[x->cur][0], frames[i],
-                       (size_t)x->H * x->W * elem_bytes(x->g.e0), hipMemcpyDeviceToDevice, st);
+    e = launch_copy(x->mem + x->slot_off[x->cur][0], frames[i],
+                    (size_t)x->H * x->W * elem_bytes(x->g.e0), st);
   }
-  if (e == hipSuccess) e = hipMemcpyAsync(dblk, hblk, p.bytes, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_copy(dblk, s->host_blk_dev + (size_t)slot * s->slot_bytes, p.bytes, st);
   if (e != hipSuccess) return hip_fail("push copies", e);
   // 3. new pyramids, then the iterations of the flowing sessions
   for (int l = 1; l < L && e == hipSuccess; ++l) {
@@ -502,6 +530,8 @@ of_status of_session_set_mask(of_session* ss, const uint8_t* mask, void* stream)
   if (ss->flagbuf) hipFree(ss->flagbuf);
   ss->maskbuf = ss->flagbuf = nullptr;
   if (!mask) return OF_OK;
+  e = prime_push_kernels(s, true);
+  if (e != hipSuccess) return hip_fail("set_mask", e);
   const Geometry& g = ss->g;
   const int L = s->L, TW = strip_width_for(s->R), N = 2 * s->R + 1;
   size_t mt = 0, ft = 0;
