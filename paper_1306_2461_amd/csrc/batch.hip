@@ -56,6 +56,7 @@ struct of_batch {
   // copies in `pinned`): kGraphSlots for captured graphs, then kEagerSlots as a ring for eager
   // runs.  slot_done[i] is recorded after the last launch that reads slot i.
   char* pinned = nullptr;
+  char* pinned_dev = nullptr;   // the pinned slots' device mapping (read by the copy kernel)
   hipEvent_t slot_done[kArgSlots] = {};
   bool slot_used[kArgSlots] = {};
   int eager_next = 0;
@@ -308,6 +309,12 @@ hipError_t enqueue_batch(of_batch* b, char* blk, float* const* u, float* const* 
 
 char* dev_slot(const of_batch* b, int i) { return b->ws + b->off_args + (size_t)i * b->arg_bytes; }
 char* host_slot(const of_batch* b, int i) { return b->pinned + (size_t)i * b->arg_bytes; }
+// A slot's arguments reach the device through a copy kernel that reads the pinned slot through
+// its device mapping (the runtime's asynchronous host-to-device copy from pinned memory was seen
+// to block the calling thread for milliseconds now and then).
+hipError_t upload_slot(const of_batch* b, int i, hipStream_t s) {
+  return launch_copy(dev_slot(b, i), b->pinned_dev + (size_t)i * b->arg_bytes, b->arg_bytes, s);
+}
 
 // Is slot i free for new arguments (no launch in flight reads it)?  hipErrorNotReady if busy.
 hipError_t slot_free(of_batch* b, int i) {
@@ -323,7 +330,7 @@ hipError_t run_eager(of_batch* b, const void* const* I1, const void* const* I2, 
   hipError_t e = slot_free(b, slot);
   if (e != hipSuccess) return e;
   fill_args(b, host_slot(b, slot), I1, I2, u, v);
-  e = hipMemcpyAsync(dev_slot(b, slot), host_slot(b, slot), b->arg_bytes, hipMemcpyHostToDevice, s);
+  e = upload_slot(b, slot, s);
   if (e == hipSuccess) e = enqueue_batch(b, dev_slot(b, slot), u, v, s, t);
   if (e == hipSuccess) e = hipEventRecord(b->slot_done[slot], s);
   if (e != hipSuccess) return e;
@@ -442,7 +449,8 @@ of_batch* of_batch_create(int n, const int* H, const int* W, int levels, int rad
     e = hipMemcpy(b->ws + b->items_at[l], items[l].data(), items[l].size() * sizeof(int2),
                   hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = hipHostMalloc((void**)&b->pinned, kArgSlots * b->arg_bytes, hipHostMallocDefault);
+    e = hipHostMalloc((void**)&b->pinned, kArgSlots * b->arg_bytes, hipHostMallocMapped);
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&b->pinned_dev, b->pinned, 0);
   for (int i = 0; i < kArgSlots && e == hipSuccess; ++i)
     e = hipEventCreateWithFlags(&b->slot_done[i], hipEventDisableTiming);
   if (e != hipSuccess) {
@@ -508,8 +516,7 @@ of_status of_batch_compute(of_batch* b, const void* const* I1, const void* const
       }
       if (e == hipSuccess) {
         fill_args(b, host_slot(b, slot), I1, I2, u, v);
-        e = hipMemcpyAsync(dev_slot(b, slot), host_slot(b, slot), b->arg_bytes,
-                           hipMemcpyHostToDevice, s);
+        e = upload_slot(b, slot, s);
       }
     }
     char* blk = dev_slot(b, slot);
