@@ -349,3 +349,47 @@ def test_degenerate_shapes_in_one_batch(gpu_lib):
         pu, pv = gpu_flow(ofmi, p[0], p[1], 1, 2, 3)
         assert np.array_equal(us[i].cpu().numpy(), pu) and np.array_equal(vs[i].cpu().numpy(), pv), shapes[i]
     b.close()
+
+
+def test_concurrent_plans_on_two_streams(gpu_lib):
+    """Two plans driven from two streams at once (their launches interleave on the device, a
+    batch of two pairs beside them on a third): every result equals its sequential bits, so
+    plans and batches share no hidden device state."""
+    import torch
+    ofmi = gpu_lib
+    pairs = [synth.make_pair("c1", 30 + i)[:2] for i in range(3)]
+    d = [(to_dev(p[0]), to_dev(p[1])) for p in pairs]
+    announce("two plans and a batch on three streams")
+    plans = [ofmi.Plan(256, 256, 3, 4, 4, device=dev()) for _ in range(2)]
+    batch = ofmi.Batch([(256, 256), (256, 256)], 3, 4, 4, device=dev())
+    ref = []
+    for k in range(2):
+        u, v = plans[k].compute(*d[k])
+        torch.cuda.synchronize()
+        ref.append((u.cpu().numpy(), v.cpu().numpy()))
+    bu, bv = batch.outputs()
+    batch.compute([d[2][0], d[0][0]], [d[2][1], d[0][1]], bu, bv)
+    torch.cuda.synchronize()
+    bref = [(bu[i].cpu().numpy(), bv[i].cpu().numpy()) for i in range(2)]
+    streams = [torch.cuda.Stream(dev()) for _ in range(3)]
+    outs = [[(torch.empty((256, 256), device=dev()), torch.empty((256, 256), device=dev()))
+             for _ in range(6)] for _ in range(2)]
+    bouts = [batch.outputs() for _ in range(6)]
+    for rep in range(6):
+        for k in range(2):
+            plans[k].compute(d[k][0], d[k][1], outs[k][rep][0], outs[k][rep][1], stream=streams[k])
+        batch.compute([d[2][0], d[0][0]], [d[2][1], d[0][1]], bouts[rep][0], bouts[rep][1],
+                      stream=streams[2])
+    torch.cuda.synchronize()
+    for rep in range(6):
+        for k in range(2):
+            u, v = outs[k][rep]
+            assert np.array_equal(u.cpu().numpy(), ref[k][0]) and np.array_equal(v.cpu().numpy(), ref[k][1]), (rep, k)
+        for i in range(2):
+            assert np.array_equal(bouts[rep][0][i].cpu().numpy(), bref[i][0]), (rep, i)
+            assert np.array_equal(bouts[rep][1][i].cpu().numpy(), bref[i][1]), (rep, i)
+    # the batch's second pair is pair 0, so it also equals plan 0's bits
+    assert np.array_equal(bref[1][0], ref[0][0]) and np.array_equal(bref[1][1], ref[0][1])
+    for p in plans:
+        p.close()
+    batch.close()
