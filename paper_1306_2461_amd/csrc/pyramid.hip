@@ -179,7 +179,7 @@ __device__ __forceinline__ float stored<__half>(float x) { return __half2float(_
 
 // Level d of the chain from level d-1's footprint `src` (row pass into `fr`, column pass into
 // `dst`); Hd x Wd is level d's size, (tyD, txD) the tile's origin at the deepest level.
-template <typename Tout, int D, int T, int d>
+template <typename Tout, int D, int T, int d, int NTH>
 __device__ __forceinline__ void chain_level(const float* src, float* dst, float* fr, int Hd, int Wd,
                                             Tout* out, int tyD, int txD) {
   constexpr int Sp = chain_span(D, T, d - 1), Sd = chain_span(D, T, d);
@@ -187,7 +187,7 @@ __device__ __forceinline__ void chain_level(const float* src, float* dst, float*
   // footprint origin at level d: o_d = 2^(D-d) o_D - 2^(D-d+1) + 2
   const int oyd = (tyD << k) - (2 << k) + 2, oxd = (txD << k) - (2 << k) + 2;
   // Row pass: every footprint row of level d-1 at the columns of level d's footprint.
-  for (int e = threadIdx.x; e < Sp * Sd; e += 256) {
+  for (int e = threadIdx.x; e < Sp * Sd; e += NTH) {
     const int r = e / Sd, q = e - r * Sd;
     const int cx = min(max(oxd + q, 0), Wd - 1) - oxd;
     const float* w = src + r * Sp + 2 * cx;
@@ -201,7 +201,7 @@ __device__ __forceinline__ void chain_level(const float* src, float* dst, float*
   __syncthreads();
   // Column pass at the rows of level d's footprint; the tile's own part goes out.
   constexpr int own0 = (2 << k) - 2, own = T << k;
-  for (int e = threadIdx.x; e < Sd * Sd; e += 256) {
+  for (int e = threadIdx.x; e < Sd * Sd; e += NTH) {
     const int p = e / Sd, q = e - p * Sd;
     const int cy = min(max(oyd + p, 0), Hd - 1) - oyd;
     const float* h = fr + 2 * cy * Sd + q;
@@ -218,8 +218,10 @@ __device__ __forceinline__ void chain_level(const float* src, float* dst, float*
   __syncthreads();
 }
 
-template <typename Tin, typename Tout, int D, int T>
-__global__ __launch_bounds__(256) void reduce_chain_kernel(ReduceChain a, int tiles_x) {
+// NTH threads per workgroup: the chain is latency bound, so more threads per tile shorten
+// every phase (fewer footprint entries per thread).
+template <typename Tin, typename Tout, int D, int T, int NTH>
+__global__ __launch_bounds__(NTH) void reduce_chain_kernel(ReduceChain a, int tiles_x) {
   constexpr int S0 = chain_span(D, T, 0), S1 = chain_span(D, T, 1);
   __shared__ float fa[S0 * S0];   // footprints of levels 0, 2
   __shared__ float fr[S0 * S1];   // row-pass results
@@ -233,41 +235,44 @@ __global__ __launch_bounds__(256) void reduce_chain_kernel(ReduceChain a, int ti
     const int oy0 = (tyD << D) - (2 << D) + 2, ox0 = (txD << D) - (2 << D) + 2;
     // All loads in flight together: items past the end repeat the last entry (same value to
     // the same slot), so neither loads nor stores need a guard.
-    constexpr int NL = (S0 * S0 + 255) / 256;
+    constexpr int NL = (S0 * S0 + NTH - 1) / NTH;
     float v[NL];
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
-      const int e = min((int)threadIdx.x + 256 * k, S0 * S0 - 1);
+      const int e = min((int)threadIdx.x + NTH * k, S0 * S0 - 1);
       const int ry = e / S0, rx = e - ry * S0;
       const int y = min(max(oy0 + ry, 0), H - 1), x = min(max(ox0 + rx, 0), W - 1);
       v[k] = ld(in, (unsigned)y * (unsigned)W + (unsigned)x);
     }
 #pragma unroll
-    for (int k = 0; k < NL; ++k) fa[min((int)threadIdx.x + 256 * k, S0 * S0 - 1)] = v[k];
+    for (int k = 0; k < NL; ++k) fa[min((int)threadIdx.x + NTH * k, S0 * S0 - 1)] = v[k];
   }
   __syncthreads();
-  chain_level<Tout, D, T, 1>(fa, fb, fr, a.H[1], a.W[1], (Tout*)(f2 ? a.out[1][0] : a.out[0][0]),
+  chain_level<Tout, D, T, 1, NTH>(fa, fb, fr, a.H[1], a.W[1], (Tout*)(f2 ? a.out[1][0] : a.out[0][0]),
                              tyD, txD);
-  chain_level<Tout, D, T, 2>(fb, fa, fr, a.H[2], a.W[2], (Tout*)(f2 ? a.out[1][1] : a.out[0][1]),
+  chain_level<Tout, D, T, 2, NTH>(fb, fa, fr, a.H[2], a.W[2], (Tout*)(f2 ? a.out[1][1] : a.out[0][1]),
                              tyD, txD);
   if constexpr (D == 3)
-    chain_level<Tout, D, T, 3>(fa, fb, fr, a.H[3], a.W[3], (Tout*)(f2 ? a.out[1][2] : a.out[0][2]),
+    chain_level<Tout, D, T, 3, NTH>(fa, fb, fr, a.H[3], a.W[3], (Tout*)(f2 ? a.out[1][2] : a.out[0][2]),
                                tyD, txD);
 }
+
+constexpr int kChainThreads = 1024;
 
 template <typename Tin, typename Tout>
 hipError_t go_chain(const ReduceChain& c, hipStream_t s) {
   const int nf = c.in[1] ? 2 : 1;
+  constexpr int NTH = kChainThreads;
   if (c.D == 2) {
     constexpr int T = 16;
     const int tx = (c.W[2] + T - 1) / T, ty = (c.H[2] + T - 1) / T;
-    hipLaunchKernelGGL((reduce_chain_kernel<Tin, Tout, 2, T>), dim3(tx * ty, 1, nf), dim3(256), 0,
-                       s, c, tx);
+    hipLaunchKernelGGL((reduce_chain_kernel<Tin, Tout, 2, T, NTH>), dim3(tx * ty, 1, nf),
+                       dim3(NTH), 0, s, c, tx);
   } else if (c.D == 3) {
     constexpr int T = 8;
     const int tx = (c.W[3] + T - 1) / T, ty = (c.H[3] + T - 1) / T;
-    hipLaunchKernelGGL((reduce_chain_kernel<Tin, Tout, 3, T>), dim3(tx * ty, 1, nf), dim3(256), 0,
-                       s, c, tx);
+    hipLaunchKernelGGL((reduce_chain_kernel<Tin, Tout, 3, T, NTH>), dim3(tx * ty, 1, nf),
+                       dim3(NTH), 0, s, c, tx);
   } else {
     return hipErrorInvalidValue;
   }
