@@ -44,9 +44,10 @@ __device__ __forceinline__ void add_count(unsigned long long* dst, unsigned c) {
 // Threads per workgroup.  Narrow variants: 5 per output column.  Wide variants: at least 10
 // per column, and enough that the warped-frame positions of a steady pass (every pass but a
 // tile's first, which also samples the two rows above) take the fewest rounds of items per
-// thread that a workgroup of at most 1024 allows, spread evenly: e.g. r = 8 on 64-column
-// strips samples 17 x 82 positions per band, 3 rounds at 640 threads (73 % of the lanes busy)
-// and 2 rounds at 704 (99 %); on 32-column strips 17 x 50 positions, one round at 896.
+// thread that a workgroup of at most 1024 allows, rounded up to whole groups of four waves (one
+// per SIMD of the CU): e.g. r = 8 on 64-column strips samples 17 x 82 positions per band, 3
+// rounds at 640 threads (73 % of the lanes busy) and 2 at 768; on 32-column strips 17 x 50
+// positions, one round at 1024.
 template <int R, int TW, bool WIDE, int BB>
 constexpr int group_threads() {
   if (!WIDE) return 5 * TW * BB;
@@ -54,7 +55,7 @@ constexpr int group_threads() {
   const int items = (BB == 1 ? N : BB * N + 2) * WC;
   const int base = 10 * TW * BB;
   const int k = (items + 1023) / 1024;
-  int nt = ((items + k - 1) / k + 63) / 64 * 64;
+  int nt = ((items + k - 1) / k + 255) / 256 * 256;
   if (nt < base) nt = base;
   if (nt > 1024) nt = base;
   return nt;
