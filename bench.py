@@ -615,6 +615,8 @@ def main():
     ap.add_argument("--serve-frames", type=int, default=200)
     ap.add_argument("--c4-only", action="store_true",
                     help="only the 64-pair mixed batch (for profilers): autotune, 3 timed replays, no JSON line")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the 8-stream serving run (for profilers): no CPU baseline, no JSON line")
     ap.add_argument("--probe", action="store_true",
                     help="short fixed run for profilers (5 plain pairs, one batch), no timing, no JSON line")
     args = ap.parse_args()
@@ -644,6 +646,15 @@ def main():
         dev = torch.device("cuda", 0)
         torch.cuda.set_device(dev)
         bench_c4(torch, ofmi, dev, pool, workers, 3, with_cpu=False)
+        pool.shutdown()
+        return
+    if args.serve_only:
+        import torch
+        import paper_1306_2461_amd as ofmi
+        ofmi.load()
+        dev = torch.device("cuda", 0)
+        torch.cuda.set_device(dev)
+        bench_serving(torch, ofmi, dev, pool, workers, args.serve_frames, with_cpu=False)
         pool.shutdown()
         return
 
