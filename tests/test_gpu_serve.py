@@ -5,7 +5,7 @@ import pytest
 import floor_util
 import oracle
 import synth
-from gpu_util import announce, dev, flow_error
+from gpu_util import announce, dev, flow_error, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -207,3 +207,42 @@ def test_executor_keeps_only_selected_flows(gpu_lib):
     torch.cuda.synchronize()
     assert np.array_equal(reqs[1][3].u, pu.cpu().numpy()) and np.array_equal(reqs[1][3].v, pv.cpu().numpy())
     plan.close()
+
+
+def test_session_odd_sizes_and_unaligned_frames(gpu_lib):
+    """Frames whose byte count is not a multiple of 16 and frame pointers at odd addresses (the
+    push copies them with a kernel: 16-byte words where both ends are aligned, bytes
+    otherwise): the flows equal the plain path's bits."""
+    import ctypes
+
+    import torch
+    ofmi = gpu_lib
+    from paper_1306_2461_amd import _binding as B
+    lib = B.load()
+    H, W, Ls, Rs, Ks = 37, 53, 2, 2, 2
+    I = [synth.make_pair("c1", 40 + t)[0][:H, :W].copy() for t in range(3)]
+    announce("session with odd-size frames at odd addresses")
+    ws = torch.empty(lib.of_session_bytes(H, W, Ls, Rs, Ks, 0), dtype=torch.uint8, device=dev())
+    s = lib.of_session_create(H, W, Ls, Rs, Ks, 0, ws.data_ptr(), ws.numel())
+    assert s, B.last_error()
+    # each frame stored one byte into a larger buffer, so its pointer is odd
+    bufs = [torch.zeros(H * W + 64, dtype=torch.uint8, device=dev()) for _ in range(3)]
+    for b, f in zip(bufs, I):
+        b[1:1 + H * W] = torch.from_numpy(f.reshape(-1)).to(dev())
+    outs = [(torch.empty((H, W), device=dev()), torch.empty((H, W), device=dev())) for _ in range(3)]
+    has = ctypes.c_int()
+    st = torch.cuda.current_stream().cuda_stream
+    torch.cuda.synchronize()
+    for t in range(3):
+        assert lib.of_session_push(ctypes.c_void_p(s), bufs[t].data_ptr() + 1, outs[t][0].data_ptr(),
+                                   outs[t][1].data_ptr(), st, ctypes.byref(has)) == 0, B.last_error()
+        assert has.value == (0 if t == 0 else 1)
+    torch.cuda.synchronize()
+    lib.of_session_destroy(ctypes.c_void_p(s))
+    for t in (1, 2):
+        plan = ofmi.Plan(H, W, Ls, Rs, Ks, device=dev())
+        pu, pv = plan.compute(to_dev(I[t - 1]), to_dev(I[t]))
+        torch.cuda.synchronize()
+        assert np.array_equal(outs[t][0].cpu().numpy(), pu.cpu().numpy()), t
+        assert np.array_equal(outs[t][1].cpu().numpy(), pv.cpu().numpy()), t
+        plan.close()
