@@ -50,6 +50,8 @@ struct of_batch {
   size_t off_args = 0;                   // eager argument block
   size_t arg_bytes = 0;
   std::vector<int> ntiles, nitems;
+  std::vector<int> nactive;         // per level: tiles with an unmasked pixel, first in the list
+  std::vector<char> partial;        // per level: a listed tile holds masked pixels
   std::vector<size_t> items_at;
   LevelCfg cfg[OF_MAX_LEVELS];
   // Argument slots (arg_bytes each, device slots in the workspace from off_args, pinned host
@@ -61,14 +63,18 @@ struct of_batch {
   bool slot_used[kArgSlots] = {};
   int eager_next = 0;
   std::vector<std::pair<std::vector<uintptr_t>, int>> graph_slot;   // pointer set -> slot
-  // Masks (of_batch_set_masks): per pair, its mask pyramid in `maskbuf` (offsets per level,
-  // SIZE_MAX = unmasked pair), a host copy for the tile flags, and the flags of the current
-  // tile heights in `flagbuf`.
+  // Masks (of_batch_set_masks): per masked pair, its mask pyramid in `maskbuf` (offsets per
+  // level), a host copy for the tile flags, and the flags of the current tile heights in
+  // `flagbuf`.  A masked pair also gets four flow planes of its own per level >= 1 in
+  // `maskbuf` (plane_off), so that no level writes over another's zero regions: the zero
+  // regions of every intermediate plane are cleared once per tile configuration and only
+  // the final phase visits the tiles without an unmasked pixel.
   uint8_t* maskbuf = nullptr;
   uint8_t* flagbuf = nullptr;
   size_t flag_cap = 0;
   std::vector<std::vector<size_t>> mask_off;      // [pair][level]
   std::vector<std::vector<size_t>> flag_off;      // [pair][level]
+  std::vector<std::vector<size_t>> plane_off;     // [pair][level >= 1] u0, u1, v0, v1 planes
   std::vector<std::vector<std::vector<uint8_t>>> hmask;   // [pair][level] host copies
   KernelTimer timer;
   GraphCache graphs;
@@ -122,50 +128,62 @@ int default_batch_bands(const of_batch* b, int l) {
   return 1;
 }
 
-// Tile work list of level l for the current configuration (host side).
-std::vector<int4> tile_list(const of_batch* b, int l) {
-  const int TW = strip_width_for(b->R);
-  const int TH = (2 * b->R + 1) * b->cfg[l].nb;
-  std::vector<int4> t;
-  for (int p = 0; p < b->n; ++p) {
-    const int tx = (b->g[p].W[l] + TW - 1) / TW, ty = (b->g[p].H[l] + TH - 1) / TH;
-    for (int y = 0; y < ty; ++y)
-      for (int x = 0; x < tx; ++x) t.push_back(make_int4(p, x, y, TH));
-  }
-  return t;
+// Tile flags of masked pair p at level l for the current tile height (0: no unmasked pixel,
+// 1: some, 2: all); empty for an unmasked pair.
+std::vector<uint8_t> pair_flags(const of_batch* b, int p, int l) {
+  if (!b->maskbuf || b->mask_off[p].empty()) return {};
+  const Geometry& g = b->g[p];
+  return tile_flags(b->hmask[p][l].data(), g.H[l], g.W[l], strip_width_for(b->R),
+                    (2 * b->R + 1) * b->cfg[l].nb);
 }
 
-// Tile flags of every masked pair at the current tile heights (set-up calls only).
-hipError_t upload_flags(of_batch* b) {
-  if (!b->flagbuf) return hipSuccess;
-  const int TW = strip_width_for(b->R);
-  std::vector<uint8_t> all(b->flag_cap, 0);
-  for (int p = 0; p < b->n; ++p) {
-    if (b->mask_off[p].empty()) continue;
-    size_t off = 0;
-    for (int l = 0; l < b->L; ++l) {
-      const Geometry& g = b->g[p];
-      const std::vector<uint8_t> f =
-          tile_flags(b->hmask[p][l].data(), g.H[l], g.W[l], TW, (2 * b->R + 1) * b->cfg[l].nb);
-      const size_t o = b->flag_off[p][l];
-      memcpy(all.data() + o, f.data(), f.size());
-      off = o + f.size();
-    }
-    (void)off;
-  }
-  return hipMemcpy(b->flagbuf, all.data(), all.size(), hipMemcpyHostToDevice);
-}
-
+// Tile work lists of all levels for the current configuration, with the tiles that hold an
+// unmasked pixel first (nactive of them) and the all-masked tiles after them; the tile flags
+// of the masked pairs; and, for masked pairs, every intermediate flow plane cleared (the
+// phases before the final one write only the listed active tiles, so the rest stays zero).
+// Set-up calls only: no run may be in flight.
 hipError_t upload_tiles(of_batch* b) {
+  const int TW = strip_width_for(b->R);
+  std::vector<uint8_t> flags(b->flag_cap, 0);
   for (int l = 0; l < b->L; ++l) {
-    std::vector<int4> t = tile_list(b, l);
-    if (t.size() > b->cap_tiles) return hipErrorInvalidValue;
-    b->ntiles[l] = (int)t.size();
-    hipError_t e = hipMemcpy(b->ws + b->off_tiles + l * b->cap_tiles * sizeof(int4), t.data(),
-                             t.size() * sizeof(int4), hipMemcpyHostToDevice);
+    const int TH = (2 * b->R + 1) * b->cfg[l].nb;
+    std::vector<int4> act, off;
+    for (int p = 0; p < b->n; ++p) {
+      const std::vector<uint8_t> f = pair_flags(b, p, l);
+      if (!f.empty()) memcpy(flags.data() + b->flag_off[p][l], f.data(), f.size());
+      const int tx = (b->g[p].W[l] + TW - 1) / TW, ty = (b->g[p].H[l] + TH - 1) / TH;
+      for (int y = 0; y < ty; ++y)
+        for (int x = 0; x < tx; ++x)
+          (f.empty() || f[(size_t)y * tx + x] ? act : off).push_back(make_int4(p, x, y, TH));
+    }
+    b->nactive[l] = (int)act.size();
+    b->partial[l] = 0;
+    for (int p = 0; p < b->n; ++p)
+      if (b->maskbuf && !b->mask_off[p].empty()) {
+        const size_t o = b->flag_off[p][l];
+        const int tx = (b->g[p].W[l] + TW - 1) / TW, ty = (b->g[p].H[l] + TH - 1) / TH;
+        for (size_t i = 0; i < (size_t)tx * ty; ++i) b->partial[l] |= flags[o + i] == 1;
+      }
+    act.insert(act.end(), off.begin(), off.end());
+    if (act.size() > b->cap_tiles) return hipErrorInvalidValue;
+    b->ntiles[l] = (int)act.size();
+    hipError_t e = hipMemcpy(b->ws + b->off_tiles + l * b->cap_tiles * sizeof(int4), act.data(),
+                             act.size() * sizeof(int4), hipMemcpyHostToDevice);
     if (e != hipSuccess) return e;
   }
-  return upload_flags(b);
+  if (!b->flagbuf) return hipSuccess;
+  hipError_t e = hipMemcpy(b->flagbuf, flags.data(), flags.size(), hipMemcpyHostToDevice);
+  for (int p = 0; p < b->n && e == hipSuccess; ++p) {
+    if (b->mask_off[p].empty()) continue;
+    const Geometry& g = b->g[p];
+    const size_t n0 = (size_t)g.H[0] * g.W[0] * sizeof(float);
+    for (int i = 0; i < 4 && e == hipSuccess; ++i)
+      e = hipMemset(b->ws + b->pair_off[p] + g.off_flow[i], 0, n0);
+    for (int l = 1; l < b->L && e == hipSuccess; ++l)
+      e = hipMemset(b->maskbuf + b->plane_off[p][l], 0,
+                    4 * (size_t)g.H[l] * g.W[l] * sizeof(float));
+  }
+  return e;
 }
 
 // Fill the argument block for the given caller buffers.
@@ -189,12 +207,21 @@ void fill_args(const of_batch* b, char* blk, const void* const* I1, const void* 
       j[0] = {P1[l - 1], (void*)P1[l], g.H[l - 1], g.W[l - 1], g.H[l], g.W[l]};
       j[1] = {P2[l - 1], (void*)P2[l], g.H[l - 1], g.W[l - 1], g.H[l], g.W[l]};
     }
-    float* fu[2] = {(float*)(ws + g.off_flow[0]), (float*)(ws + g.off_flow[1])};
-    float* fv[2] = {(float*)(ws + g.off_flow[2]), (float*)(ws + g.off_flow[3])};
+    const bool masked = b->maskbuf && !b->mask_off[p].empty();
     const float* cu = nullptr;
     const float* cv = nullptr;
     int cH = 0, cW = 0, buf = 0, phase = 0;
     for (int l = L - 1; l >= 0; --l) {
+      float* fu[2] = {(float*)(ws + g.off_flow[0]), (float*)(ws + g.off_flow[1])};
+      float* fv[2] = {(float*)(ws + g.off_flow[2]), (float*)(ws + g.off_flow[3])};
+      if (masked && l > 0) {
+        float* pl = (float*)(b->maskbuf + b->plane_off[p][l]);
+        const size_t nl = (size_t)g.H[l] * g.W[l];
+        fu[0] = pl;
+        fu[1] = pl + nl;
+        fv[0] = pl + 2 * nl;
+        fv[1] = pl + 3 * nl;
+      }
       for (int k = 0; k < K; ++k, ++phase) {
         IterArgs& a = args[(size_t)phase * n + p];
         a = IterArgs{};
@@ -211,7 +238,7 @@ void fill_args(const of_batch* b, char* blk, const void* const* I1, const void* 
         a.uout = last ? u[p] : fu[buf];
         a.vout = last ? v[p] : fv[buf];
         if (b->flags & OF_FLAG_GAUSSIAN_WINDOW) gaussian_taps(a.taps, b->R);
-        if (b->maskbuf && !b->mask_off[p].empty()) {
+        if (masked) {
           a.mask = b->maskbuf + b->mask_off[p][l];
           a.tiles = b->flagbuf + b->flag_off[p][l];
         }
@@ -284,16 +311,25 @@ hipError_t enqueue_batch(of_batch* b, char* blk, float* const* u, float* const* 
       BatchLaunch bl;
       bl.args = args + (size_t)phase * n;
       bl.tiles = (const int4*)(b->ws + b->off_tiles + l * b->cap_tiles * sizeof(int4));
-      bl.ntiles = b->ntiles[l];
+      // Every phase computes the tiles with an unmasked pixel only.  The all-masked tiles
+      // after them in the list hold zeros in the intermediate planes from set-up; the final
+      // phase zero-fills them in the caller's planes with a launch of their own (inside the
+      // iteration launch, the contiguous per-XCD ranges of the list would leave some XCDs
+      // only zero tiles).
+      bl.ntiles = b->nactive[l];
+      const int nzero = (l == 0 && k == K - 1) ? b->ntiles[l] - b->nactive[l] : 0;
       bl.grid = b->cfg[l].grid > 0 ? std::min(b->cfg[l].grid, bl.ntiles) : bl.ntiles;
       bl.grid = (bl.grid + 7) / 8 * 8;
-      bl.variant = b->cfg[l].variant >= 0 ? b->cfg[l].variant : default_tile_variant(bl.ntiles);
+      bl.variant = b->cfg[l].variant >= 0 ? b->cfg[l].variant : default_tile_variant(b->ntiles[l]);
       if (b->flags & OF_FLAG_GAUSSIAN_WINDOW) bl.variant |= kTileGauss;
-      bl.masked = b->maskbuf != nullptr;
+      // Only tiles that hold masked and unmasked pixels need the masked kernel.
+      bl.masked = b->maskbuf != nullptr && b->partial[l];
       const int mode = k > 0 ? kFlowSame : (l == L - 1 ? kFlowZero : kFlowCoarse);
       hipEvent_t ev = nullptr;
       hipError_t e = t && t->per_launch() ? t->begin(s, &ev) : hipSuccess;
-      if (e == hipSuccess) e = launch_iter_batch(g0.elem(l), bl, b->R, mode, s);
+      if (e == hipSuccess && bl.ntiles > 0) e = launch_iter_batch(g0.elem(l), bl, b->R, mode, s);
+      if (e == hipSuccess && nzero > 0)
+        e = launch_zero_tiles(bl.args, bl.tiles + bl.ntiles, nzero, strip_width_for(b->R), s);
       if (e == hipSuccess && t && t->per_launch())
         e = t->end(s, ev, OF_KERNEL_ITERATE, px, px * (2.0 * elem_bytes(g0.elem(l)) + 16.0));
       if (e != hipSuccess) return e;
@@ -411,6 +447,8 @@ of_batch* of_batch_create(int n, const int* H, const int* W, int levels, int rad
   off += b->cap_tiles * sizeof(int4) * levels;
   b->off_items = off;
   b->ntiles.assign(levels, 0);
+  b->nactive.assign(levels, 0);
+  b->partial.assign(levels, 0);
   b->nitems.assign(levels, 0);
   b->items_at.assign(levels, 0);
   std::vector<std::vector<int2>> items(levels);
@@ -558,22 +596,32 @@ of_status of_batch_set_masks(of_batch* b, const uint8_t* const* masks, void* str
   b->maskbuf = b->flagbuf = nullptr;
   b->mask_off.assign(b->n, {});
   b->flag_off.assign(b->n, {});
+  b->plane_off.assign(b->n, {});
   b->hmask.assign(b->n, {});
   b->flag_cap = 0;
   bool any = false;
   for (int p = 0; masks && p < b->n; ++p) any |= masks[p] != nullptr;
-  if (!any) return OF_OK;
-  // layout: mask pyramids of the masked pairs; flag capacity at one-band tiles (the most tiles)
+  if (!any) {   // every tile active again
+    e = upload_tiles(b);
+    return e == hipSuccess ? OF_OK : hip_fail("set_masks", e);
+  }
+  // layout: mask pyramids and flow planes of levels >= 1 of the masked pairs; flag capacity
+  // at one-band tiles (the most tiles)
   const int TW = strip_width_for(b->R), N = 2 * b->R + 1;
   size_t mtotal = 0;
   for (int p = 0; p < b->n; ++p) {
     if (!masks[p]) continue;
+    const Geometry& g = b->g[p];
     for (int l = 0; l < b->L; ++l) {
-      const Geometry& g = b->g[p];
       b->mask_off[p].push_back(mtotal);
       mtotal += align256((size_t)g.H[l] * g.W[l]);
       b->flag_off[p].push_back(b->flag_cap);
       b->flag_cap += (size_t)((g.W[l] + TW - 1) / TW) * ((g.H[l] + N - 1) / N);
+    }
+    b->plane_off[p].assign(b->L, 0);
+    for (int l = 1; l < b->L; ++l) {
+      b->plane_off[p][l] = mtotal;
+      mtotal += align256(4 * (size_t)g.H[l] * g.W[l] * sizeof(float));
     }
   }
   e = hipMalloc((void**)&b->maskbuf, mtotal);
@@ -597,12 +645,14 @@ of_status of_batch_set_masks(of_batch* b, const uint8_t* const* masks, void* str
                     hipMemcpyDeviceToHost);
     }
   }
-  if (e == hipSuccess) e = upload_flags(b);
+  if (e == hipSuccess) e = upload_tiles(b);
   if (e != hipSuccess) {
     if (b->maskbuf) hipFree(b->maskbuf);
     if (b->flagbuf) hipFree(b->flagbuf);
     b->maskbuf = b->flagbuf = nullptr;
     b->mask_off.assign(b->n, {});
+    b->plane_off.assign(b->n, {});
+    upload_tiles(b);
     return hip_fail("set_masks", e);
   }
   return OF_OK;

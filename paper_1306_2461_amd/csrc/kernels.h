@@ -118,6 +118,10 @@ hipError_t launch_normalize(Elem t, const void* in, float* out, int H, int W, in
 
 // u = v = 0 over n elements (a fill kernel, safe under stream capture).
 hipError_t launch_zero(float* u, float* v, size_t n, hipStream_t s);
+// Zero flow over a work list of tiles (pair, tile x, tile y, tile height; tw columns wide) into
+// the output planes of args[pair] (tw divides 256).
+hipError_t launch_zero_tiles(const IterArgs* args, const int4* tiles, int ntiles, int tw,
+                             hipStream_t s);
 // Copy of `bytes` bytes by a kernel on stream s (device memory, or pinned host memory through
 // its device mapping).
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);

@@ -30,6 +30,28 @@ __global__ void zero_kernel(float* u, float* v, size_t n) {
   }
 }
 
+// Zero flow over listed tiles of many pairs (pair, tile x, tile y, tile height; tiles TW columns
+// wide), written into each pair's output planes of its arguments.  One workgroup per tile at a
+// time, TW-column rows (TW divides the workgroup size).
+__global__ __launch_bounds__(256) void zero_tiles_kernel(const IterArgs* __restrict__ args,
+                                                         const int4* __restrict__ tiles,
+                                                         int ntiles, int tw) {
+  const int c = (int)threadIdx.x % tw, rstep = (int)blockDim.x / tw;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int4 w = tiles[t];
+    float* __restrict__ u = args[w.x].uout;
+    float* __restrict__ v = args[w.x].vout;
+    const int W = args[w.x].W, H = args[w.x].H;
+    const int x = w.y * tw + c, y0 = w.z * w.w, y1 = min(H, y0 + w.w);
+    if (x >= W) continue;
+    for (int y = y0 + (int)threadIdx.x / tw; y < y1; y += rstep) {
+      const size_t o = (size_t)y * W + x;
+      u[o] = 0.f;
+      v[o] = 0.f;
+    }
+  }
+}
+
 // dst[0..bytes) = src[0..bytes): 16-byte words when both are 16-byte aligned, then the tail.
 __global__ void copy_kernel(char* __restrict__ dst, const char* __restrict__ src, size_t bytes) {
   const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -45,6 +67,15 @@ __global__ void copy_kernel(char* __restrict__ dst, const char* __restrict__ src
 }
 
 }  // namespace
+
+hipError_t launch_zero_tiles(const IterArgs* args, const int4* tiles, int ntiles, int tw,
+                             hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (tw < 1 || tw > 256 || 256 % tw != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(zero_tiles_kernel, dim3(std::min(ntiles, 4096)), dim3(256), 0, s, args, tiles,
+                     ntiles, tw);
+  return hipGetLastError();
+}
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
   if (bytes == 0) return hipSuccess;

@@ -29,10 +29,10 @@ def _mask(H, W, k):
     return M
 
 
-def _plain(ofmi, I1, I2, mask=None, gaussian=False):
+def _plain(ofmi, I1, I2, mask=None, gaussian=False, iters=K):
     import torch
     H, W = I1.shape
-    plan = ofmi.Plan(H, W, L, R, K, gaussian_window=gaussian, device=dev())
+    plan = ofmi.Plan(H, W, L, R, iters, gaussian_window=gaussian, device=dev())
     if mask is not None:
         plan.set_mask(to_dev(mask))
     u, v = plan.compute(to_dev(I1), to_dev(I2))
@@ -76,6 +76,48 @@ def test_batch_masks_and_window_equal_plain_path(gpu_lib, gaussian):
     torch.cuda.synchronize()
     pu, pv = _plain(ofmi, pairs[2][0], pairs[2][1], None, gaussian)
     assert np.array_equal(us[2].cpu().numpy(), pu) and np.array_equal(vs[2].cpu().numpy(), pv)
+    b.close()
+
+
+@pytest.mark.parametrize("iters,aligned", [(1, False), (K, False), (1, True), (K, True)])
+def test_batch_fully_masked_pairs(gpu_lib, iters, aligned):
+    """A pair whose mask excludes every pixel has no tile to compute at any level: its flow is
+    zero and the other pairs keep the plain path's bits.  With every pair fully masked, no
+    iteration launch runs before the final phase, which writes the zeros."""
+    import torch
+    ofmi = gpu_lib
+    pairs = _pairs()
+    d1 = [to_dev(p[0]) for p in pairs]
+    d2 = [to_dev(p[1]) for p in pairs]
+    announce(f"batch with fully masked pairs, iters={iters}, aligned={aligned}")
+    b = ofmi.Batch(SIZES, L, R, iters, device=dev())
+    # aligned: pair 0 has its first 64-column strip masked out, so at full resolution every
+    # tile is all masked or all unmasked (no tile needs the per-pixel mask), at coarser levels not
+    m0 = _mask(*SIZES[0], 1)
+    if aligned:
+        m0 = np.ones(SIZES[0], np.uint8)
+        m0[:, :64] = 0
+    masks = [m0, np.zeros(SIZES[1], np.uint8), None]
+    b.set_masks([None if m is None else to_dev(m) for m in masks])
+    for cfg in (None, {"bands": [1, 2, 1], "grid": [8, 0, 16], "variant": [1, 0, 2]}):
+        if cfg is not None:
+            b.set_config(cfg)
+        us, vs = b.outputs()
+        for t in us + vs:
+            t.fill_(7.0)
+        b.compute(d1, d2, us, vs)
+        torch.cuda.synchronize()
+        for i, (p, m) in enumerate(zip(pairs, masks)):
+            pu, pv = _plain(ofmi, p[0], p[1], m, iters=iters)
+            assert np.array_equal(us[i].cpu().numpy(), pu) and np.array_equal(vs[i].cpu().numpy(), pv), (i, cfg)
+        assert not us[1].any() and not vs[1].any()
+    b.set_masks([to_dev(np.zeros(s, np.uint8)) for s in SIZES])
+    us, vs = b.outputs()
+    for t in us + vs:
+        t.fill_(7.0)
+    b.compute(d1, d2, us, vs)
+    torch.cuda.synchronize()
+    assert all(not t.any() for t in us + vs)
     b.close()
 
 
