@@ -30,9 +30,11 @@ METRIC = "frame pairs/s at 1024² (FP32 vs FP16-stored, % HBM peak); p50/p99 lat
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "c2"
 
-# Launch configuration the plan autotuner settles on for this workload: used by the --probe
-# run, which profilers wrap, so that it needs no autotuning launches.
-PROBE_CONFIG = {"bands": [4, 1, 1, 1], "variant": [1, 1, 6, 6]}
+# Launch configurations the plan autotuner settles on for this workload (level 0: wide strips of
+# 4 bands, 64 or 32 columns): used by the --probe run, which profilers wrap, so that it needs
+# no autotuning launches.
+PROBE_CONFIGS = [{"bands": [4, 1, 1, 1], "variant": [1, 1, 6, 6]},
+                 {"bands": [4, 1, 1, 1], "variant": [3, 1, 6, 6]}]
 # One of the configurations the batch autotuner picks for 16 pairs of this workload.
 PROBE_BATCH_CONFIG = {"bands": [16, 8, 2, 1], "grid": [2048, 512, 1024, 512], "variant": [2, 2, 2, 1]}
 # Sources of the fused iteration kernel: the HBM traffic recorded in the counter summary is
@@ -63,17 +65,18 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per level-0 iteration launch from the committed counter summary (rocprofv3
-    FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None when the kernel sources changed
-    since the counters were taken."""
+def measured_traffic(variant):
+    """HBM bytes per level-0 iteration launch of tile variant `variant` from the committed
+    counter summary (rocprofv3 FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None when
+    the kernel sources changed since the counters were taken or that variant was not
+    profiled."""
     import re
     try:
         text = open(os.path.join(ROOT, COUNTER_SUMMARY)).read()
     except OSError:
         return None
     m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
-    m_val = re.search(r"level0_traffic_bytes_per_launch:\s*([0-9.]+)", text)
+    m_val = re.search(rf"level0_traffic_bytes_per_launch\[variant {variant}\]:\s*([0-9.]+)", text)
     if not m_hash or not m_val or m_hash.group(1) != kernel_source_hash():
         return None
     return float(m_val.group(1))
@@ -591,7 +594,7 @@ def bench_table1(torch, dev, pool):
 def probe(args):
     """Fixed short run for counter collection: a 256 MiB device copy (calibration of the
     FETCH_SIZE / WRITE_SIZE counters), then 5 plain FP32 pairs (eager launches, so every launch
-    is a kernel dispatch of its own) at PROBE_CONFIG, then one 16-pair batch at
+    is a kernel dispatch of its own) at each of PROBE_CONFIGS, then one 16-pair batch at
     PROBE_BATCH_CONFIG; no timing, no JSON line."""
     import synth
     import torch
@@ -607,11 +610,12 @@ def probe(args):
     d2 = [torch.from_numpy(p[1]).to(dev) for p in pairs]
     wl = synth.workload(WORKLOAD)
     plan = ofmi.Plan(wl.H, wl.W, wl.levels, wl.radius, wl.iters, device=dev, graph=False)
-    plan.set_config(PROBE_CONFIG)
-    u, v = plan.compute(d1[0], d2[0])
-    for i in range(4):
-        plan.compute(d1[i], d2[i], u, v)
-    torch.cuda.synchronize()
+    for cfg in PROBE_CONFIGS:
+        plan.set_config(cfg)
+        u, v = plan.compute(d1[0], d2[0])
+        for i in range(4):
+            plan.compute(d1[i], d2[i], u, v)
+        torch.cuda.synchronize()
     log(f"probe: plain path done, kernel sources {kernel_source_hash()}")
     plan.close()
     b = ofmi.Batch([(wl.H, wl.W)] * 16, wl.levels, wl.radius, wl.iters, device=dev, graph=False)
@@ -762,7 +766,7 @@ def main():
 
     r32, r16 = results["fp32"], results["fp16"]
     dom = r32["dominant"]
-    traffic = measured_traffic() if dom["level"] == 0 else None
+    traffic = measured_traffic(r32["cfg"]["variant"][0]) if dom["level"] == 0 else None
     line = {
         "metric": METRIC,
         "value": round(args.steps / r32["el"], 3),
