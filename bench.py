@@ -35,6 +35,8 @@ WORKLOAD = "c2"
 # no autotuning launches.
 PROBE_CONFIGS = [{"bands": [4, 1, 1, 1], "variant": [1, 1, 6, 6]},
                  {"bands": [4, 1, 1, 1], "variant": [3, 1, 6, 6]}]
+# The configuration the batch autotuner picked for 16 masked pairs of this workload (masked probe).
+MASK_PROBE_CONFIG = {"bands": [8, 4, 2, 1], "grid": [0, 2048, 2048, 2048], "variant": [2, 2, 2, 1]}
 # One of the configurations the batch autotuner picks for 16 pairs of this workload.
 PROBE_BATCH_CONFIG = {"bands": [16, 8, 2, 1], "grid": [2048, 512, 1024, 512], "variant": [2, 2, 2, 1]}
 # Sources of the fused iteration kernel: the HBM traffic recorded in the counter summary is
@@ -441,16 +443,23 @@ def bench_c4(torch, ofmi, dev, pool, workers, reps, with_cpu=True):
     return out
 
 
+def step_mask(H, W):
+    """Region-of-interest mask of the masked runs: a step-like obstacle over the lower-left
+    quarter and 64-row side walls top and bottom excluded (uint8, 1 = computed)."""
+    import numpy as np
+    M = np.ones((H, W), dtype=np.uint8)
+    M[H // 2:, :W // 2] = 0
+    M[:64, :] = 0
+    M[-64:, :] = 0
+    return M
+
+
 def bench_masked(torch, ofmi, dev, d1, d2, us, vs, wl, steps, warmup, unmasked_value,
                  unmasked_batch_value=None):
     """Plain FP32 path with a region-of-interest mask: a step-like obstacle over the lower-left
     quarter and 64-row side walls top and bottom (the masking lever of Sec. 3.3); then the same
     mask on every pair of the 16-pair batch, where skipped tiles free the device for the rest."""
-    import numpy as np
-    M = np.ones((wl.H, wl.W), dtype=np.uint8)
-    M[wl.H // 2:, :wl.W // 2] = 0
-    M[:64, :] = 0
-    M[-64:, :] = 0
+    M = step_mask(wl.H, wl.W)
     plan = ofmi.Plan(wl.H, wl.W, wl.levels, wl.radius, wl.iters, device=dev)
     plan.set_mask(torch.from_numpy(M).to(dev))
     tuned = plan.autotune(d1[0], d2[0], us[0], vs[0], reps=3)
@@ -627,6 +636,38 @@ def probe(args):
     b.close()
 
 
+def masked_probe(args):
+    """Fixed run for a kernel trace of masked batches: the 16-pair 1024x1024 batch at
+    MASK_PROBE_CONFIG without masks, then with step_mask on every pair; 3 warm-up and 10
+    timed graph replays each; no JSON line."""
+    import synth
+    import torch
+    import paper_1306_2461_amd as ofmi
+    dev = torch.device("cuda", 0)
+    wl = synth.workload(WORKLOAD)
+    pairs = [synth.make_pair(WORKLOAD, i)[:2] for i in range(16)]
+    d1 = [torch.from_numpy(p[0]).to(dev) for p in pairs]
+    d2 = [torch.from_numpy(p[1]).to(dev) for p in pairs]
+    dm = torch.from_numpy(step_mask(wl.H, wl.W)).to(dev)
+    for masked in (False, True):
+        b = ofmi.Batch([(wl.H, wl.W)] * 16, wl.levels, wl.radius, wl.iters, device=dev)
+        if masked:
+            b.set_masks([dm] * 16)
+        b.set_config(MASK_PROBE_CONFIG)
+        us, vs = b.outputs()
+        arrs = b.pointer_arrays(d1, d2, us, vs)
+        st = torch.cuda.current_stream().cuda_stream
+        for _ in range(3):
+            b.compute_raw(arrs, st)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(10):
+            b.compute_raw(arrs, st)
+        torch.cuda.synchronize()
+        log(f"masked probe: masks={masked}: {160 / (time.perf_counter() - t):.1f} pairs/s")
+        b.close()
+
+
 # --------------------------------------------------------------------------- main
 
 def main():
@@ -646,6 +687,8 @@ def main():
                     help="only the 64-pair mixed batch (for profilers): autotune, 3 timed replays, no JSON line")
     ap.add_argument("--serve-only", action="store_true",
                     help="only the 8-stream serving run (for profilers): no CPU baseline, no JSON line")
+    ap.add_argument("--masked-probe", action="store_true",
+                    help="fixed run for profilers: the 16-pair batch without and with masks, no JSON line")
     ap.add_argument("--probe", action="store_true",
                     help="short fixed run for profilers (5 plain pairs, one batch), no timing, no JSON line")
     args = ap.parse_args()
@@ -655,6 +698,9 @@ def main():
         sys.exit(2)
     if args.probe:
         probe(args)
+        return
+    if args.masked_probe:
+        masked_probe(args)
         return
     if args.main_only:
         args.no_extra = True
