@@ -122,6 +122,8 @@ hipError_t launch_zero(float* u, float* v, size_t n, hipStream_t s);
 // the output planes of args[pair] (tw divides 256).
 hipError_t launch_zero_tiles(const IterArgs* args, const int4* tiles, int ntiles, int tw,
                              hipStream_t s);
+// Loads the zero-tiles kernel's code on the current device (no launch).
+hipError_t prime_zero_tiles();
 // Copy of `bytes` bytes by a kernel on stream s (device memory, or pinned host memory through
 // its device mapping).
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);

@@ -77,6 +77,11 @@ hipError_t launch_zero_tiles(const IterArgs* args, const int4* tiles, int ntiles
   return hipGetLastError();
 }
 
+hipError_t prime_zero_tiles() {
+  hipFuncAttributes attr;
+  return hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&zero_tiles_kernel));
+}
+
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
   if (bytes == 0) return hipSuccess;
   const size_t words = (bytes + 15) / 16;

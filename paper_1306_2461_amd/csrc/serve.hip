@@ -65,10 +65,16 @@ struct of_session {
   int cur = 0;                    // slot that receives the next frame
   bool has_prev = false;
   // mask (of_session_set_mask): mask pyramid and the tile flags of every push tile height
+  // (device, and a host copy that orders the push tile lists), and four FP32 flow planes per
+  // level >= 1 in the same allocation, so that no level writes over another's zero regions:
+  // every intermediate plane holds zero at the masked pixels from set-up on (the launches
+  // write zero there too), so the all-masked tiles are left out of all but the final phase.
   uint8_t* maskbuf = nullptr;
   uint8_t* flagbuf = nullptr;
   size_t mask_off[OF_MAX_LEVELS] = {};
   size_t flag_off[3][OF_MAX_LEVELS] = {};
+  size_t plane_off[OF_MAX_LEVELS] = {};
+  std::vector<uint8_t> hflags;
 };
 
 struct of_server {
@@ -109,7 +115,7 @@ hipError_t prime_push_kernels(const of_server* s, bool masked) {
         const hipError_t e = launch_iter_batch(g.elem(l), bl, s->R, mode, nullptr);
         if (e != hipSuccess) return e;
       }
-  return hipSuccess;
+  return masked ? prime_zero_tiles() : hipSuccess;
 }
 
 size_t session_bytes(int H, int W, int L, int R, int K, unsigned flags, Geometry* gout,
@@ -133,6 +139,8 @@ struct Push {
   std::vector<std::vector<int2>> items;
   std::vector<std::vector<IterArgs>> args;    // per phase, one per flowing session
   std::vector<std::vector<int4>> tiles;       // per level, over flowing sessions
+  std::vector<int> nactive;                   // per level: tiles with an unmasked pixel, first
+  std::vector<char> partial;                  // per level: a listed tile holds masked pixels
   size_t bytes = 0;
   std::vector<size_t> off_jobs, off_items, off_args, off_tiles;
 };
@@ -403,30 +411,49 @@ of_status of_server_push(of_server* s, of_session* const* ss, int n, const void*
   const int TW = strip_width_for(R), N = 2 * R + 1;
   p.args.resize((size_t)L * (K > 0 ? K : 0));
   p.tiles.resize(L);
+  p.nactive.assign(L, 0);
+  p.partial.assign(L, 0);
   int level_bands[OF_MAX_LEVELS];
   for (int l = L - 1; l >= 0; --l) {
     long long px = 0;
     for (int i : flowing) px += (long long)ss[i]->g.H[l] * ss[i]->g.W[l];
     level_bands[l] = push_bands(px);
     const int TH = N * level_bands[l];
+    std::vector<int4> off;   // all-masked tiles, after the active ones
     for (int q = 0; q < (int)flowing.size(); ++q) {
       const of_session* x = ss[flowing[q]];
+      const uint8_t* f =
+          x->maskbuf ? x->hflags.data() + x->flag_off[band_slot(level_bands[l])][l] : nullptr;
       const int tx = (x->g.W[l] + TW - 1) / TW, ty = (x->g.H[l] + TH - 1) / TH;
       for (int yy = 0; yy < ty; ++yy)
-        for (int xx = 0; xx < tx; ++xx) p.tiles[l].push_back(make_int4(q, xx, yy, TH));
+        for (int xx = 0; xx < tx; ++xx) {
+          const int fl = f ? f[(size_t)yy * tx + xx] : 2;
+          p.partial[l] |= fl == 1;
+          (fl ? p.tiles[l] : off).push_back(make_int4(q, xx, yy, TH));
+        }
     }
+    p.nactive[l] = (int)p.tiles[l].size();
+    p.tiles[l].insert(p.tiles[l].end(), off.begin(), off.end());
   }
   for (int q = 0; q < (int)flowing.size(); ++q) {
     const int i = flowing[q];
     of_session* x = ss[i];
     const int prev = x->cur ^ 1;
     const size_t fb = align256((size_t)x->H * x->W * 4);
-    float* fu[2] = {(float*)(x->flow), (float*)(x->flow + fb)};
-    float* fv[2] = {(float*)(x->flow + 2 * fb), (float*)(x->flow + 3 * fb)};
     const float* cu = nullptr;
     const float* cv = nullptr;
     int cH = 0, cW = 0, buf = 0, phase = 0;
-    for (int l = L - 1; l >= 0; --l)
+    for (int l = L - 1; l >= 0; --l) {
+      float* fu[2] = {(float*)(x->flow), (float*)(x->flow + fb)};
+      float* fv[2] = {(float*)(x->flow + 2 * fb), (float*)(x->flow + 3 * fb)};
+      if (x->maskbuf && l > 0) {
+        float* pl = (float*)(x->maskbuf + x->plane_off[l]);
+        const size_t nl = (size_t)x->g.H[l] * x->g.W[l];
+        fu[0] = pl;
+        fu[1] = pl + nl;
+        fv[0] = pl + 2 * nl;
+        fv[1] = pl + 3 * nl;
+      }
       for (int k = 0; k < K; ++k, ++phase) {
         IterArgs a{};
         a.I1 = x->mem + x->slot_off[prev][l];
@@ -453,6 +480,7 @@ of_status of_server_push(of_server* s, of_session* const* ss, int n, const void*
         cW = a.W;
         buf ^= 1;
       }
+    }
   }
   layout(p);
   if (p.bytes > s->slot_bytes)   // cannot happen for sessions opened on this server
@@ -485,14 +513,18 @@ of_status of_server_push(of_server* s, of_session* const* ss, int n, const void*
       BatchLaunch bl;
       bl.args = (const IterArgs*)(dblk + p.off_args[phase]);
       bl.tiles = (const int4*)(dblk + p.off_tiles[l]);
-      bl.ntiles = (int)p.tiles[l].size();
+      // Every phase computes the tiles with an unmasked pixel only; the final phase zero-fills
+      // the all-masked tiles of the caller's planes with a launch of its own.
+      bl.ntiles = p.nactive[l];
+      const int nzero = (l == 0 && k == K - 1) ? (int)p.tiles[l].size() - p.nactive[l] : 0;
       bl.grid = (bl.ntiles + 7) / 8 * 8;
-      bl.variant = default_tile_variant(bl.ntiles);
+      bl.variant = default_tile_variant((int)p.tiles[l].size());
       if (s->flags & OF_FLAG_GAUSSIAN_WINDOW) bl.variant |= kTileGauss;
-      bl.masked = false;
-      for (int i : flowing) bl.masked |= ss[i]->maskbuf != nullptr;
+      bl.masked = p.partial[l];   // only tiles with masked and unmasked pixels need the mask
       const int mode = k > 0 ? kFlowSame : (l == L - 1 ? kFlowZero : kFlowCoarse);
-      e = launch_iter_batch(gg.elem(l), bl, R, mode, st);
+      if (bl.ntiles > 0) e = launch_iter_batch(gg.elem(l), bl, R, mode, st);
+      if (e == hipSuccess && nzero > 0)
+        e = launch_zero_tiles(bl.args, bl.tiles + bl.ntiles, nzero, TW, st);
     }
   for (int i = 0; i < n && e == hipSuccess; ++i) {
     of_session* x = ss[i];
@@ -529,6 +561,7 @@ of_status of_session_set_mask(of_session* ss, const uint8_t* mask, void* stream)
   if (ss->maskbuf) hipFree(ss->maskbuf);
   if (ss->flagbuf) hipFree(ss->flagbuf);
   ss->maskbuf = ss->flagbuf = nullptr;
+  ss->hflags.clear();
   if (!mask) return OF_OK;
   e = prime_push_kernels(s, true);
   if (e != hipSuccess) return hip_fail("set_mask", e);
@@ -544,6 +577,11 @@ of_status of_session_set_mask(of_session* ss, const uint8_t* mask, void* stream)
       ft += (size_t)((g.W[l] + TW - 1) / TW) * ((g.H[l] + TH - 1) / TH);
     }
   }
+  const size_t planes_at = mt;
+  for (int l = 1; l < L; ++l) {
+    ss->plane_off[l] = mt;
+    mt += align256(4 * (size_t)g.H[l] * g.W[l] * sizeof(float));
+  }
   uint8_t* mb = nullptr;
   uint8_t* fb = nullptr;
   e = hipMalloc((void**)&mb, mt);
@@ -552,6 +590,11 @@ of_status of_session_set_mask(of_session* ss, const uint8_t* mask, void* stream)
   for (int l = 1; l < L && e == hipSuccess; ++l)
     e = launch_mask_reduce(mb + ss->mask_off[l - 1], g.H[l - 1], g.W[l - 1], mb + ss->mask_off[l],
                            g.H[l], g.W[l], st);
+  // zero flow in every intermediate plane: the level-0 planes (written by earlier pushes) and
+  // the planes of levels >= 1
+  if (e == hipSuccess && mt > planes_at) e = hipMemsetAsync(mb + planes_at, 0, mt - planes_at, st);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(ss->flow, 0, 4 * align256((size_t)ss->H * ss->W * sizeof(float)), st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   std::vector<uint8_t> flags(ft);
   for (int l = 0; l < L && e == hipSuccess; ++l) {
@@ -570,6 +613,7 @@ of_status of_session_set_mask(of_session* ss, const uint8_t* mask, void* stream)
   }
   ss->maskbuf = mb;
   ss->flagbuf = fb;
+  ss->hflags = std::move(flags);
   return OF_OK;
 }
 

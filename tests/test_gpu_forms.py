@@ -145,3 +145,44 @@ def test_served_streams_with_mask_and_window(gpu_lib):
             pu, pv = _plain(ofmi, streams[s][t - 1], streams[s][t], M if s == 0 else None, True)
             r = reqs[s][t]
             assert r.has_flow and np.array_equal(r.u, pu) and np.array_equal(r.v, pv), (s, t)
+
+
+def test_served_masks_set_late_full_and_aligned(gpu_lib):
+    """Served masks set after unmasked flows (the session's planes held nonzero flow), a fully
+    masked stream, a tile-aligned mask (no tile needs the per-pixel mask at full resolution),
+    a push of only those two, and a mask removed again: every flow equals the plain path's
+    with the same mask, bitwise."""
+    ofmi = gpu_lib
+    from paper_1306_2461_amd.serve import GpuExecutor, Server
+    sizes = [(96, 128), (160, 120), (128, 192)]
+    streams = [[f for f, _, _ in synth.stream_frames(s, 5, size=sizes[s])] for s in range(3)]
+    aligned = np.ones(sizes[2], np.uint8)
+    aligned[:, :64] = 0
+    masks = [_mask(*sizes[0], 2), np.zeros(sizes[1], np.uint8), aligned]
+    ex = GpuExecutor(L, R, K, device=dev(), keep_on_device=False)
+    srv = Server(ex)
+    announce("served masks set late, fully masked, tile-aligned, removed")
+    # which mask each stream has when frame t is pushed (None = unmasked)
+    plan = {1: [None, None, None], 2: masks, 3: [None] + masks[1:], 4: [None] + masks[1:]}
+    reqs = {s: [srv.submit(s, streams[s][0])] for s in range(3)}
+    srv.drain()
+    for t in (1, 2, 3, 4):
+        if t == 2:
+            for s in range(3):
+                ex.set_mask(srv.sessions[s], to_dev(masks[s]))
+        if t == 4:
+            ex.set_mask(srv.sessions[0], None)
+        for s in range(3):
+            if t == 3 and s == 0:
+                continue
+            reqs[s].append((t, srv.submit(s, streams[s][t])))
+        srv.drain()
+    ex.close_all()
+    for s in range(3):
+        for t, r in reqs[s][1:]:
+            m = plan[t][s]
+            prev = t - 1 if not (s == 0 and t == 4) else 2
+            pu, pv = _plain(ofmi, streams[s][prev], streams[s][t], m)
+            assert r.has_flow and np.array_equal(r.u, pu) and np.array_equal(r.v, pv), (s, t)
+            if m is not None:
+                assert np.all(r.u[m == 0] == 0) and np.all(r.v[m == 0] == 0)
