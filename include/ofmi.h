@@ -301,9 +301,11 @@ OF_API of_status of_batch_autotune(of_batch* b, const void* const* I1, const voi
  * masks is a HOST array of n DEVICE pointers, masks[i] an H[i] x W[i] uint8 plane (nonzero =
  * compute) or NULL for an unmasked pair; masks == NULL removes every mask.  The batch builds
  * each masked pair's mask pyramid and its tile flags (refreshed when the tile heights change):
- * tiles without an unmasked pixel are skipped (zero flow written), masked pixels get zero flow,
- * results equal of_compute of a plan with the same mask, bitwise.  Set-up call: waits for the
- * device, drops the captured graphs, allocates the mask memory (freed by of_batch_destroy).
+ * tiles without an unmasked pixel are left out of every iteration launch (the last iteration
+ * writes their zero flow), masked pixels get zero flow, results equal of_compute of a plan
+ * with the same mask, bitwise.  Set-up call: waits for the device, drops the captured graphs,
+ * allocates the mask memory (mask pyramid, tile flags, and four FP32 flow planes per level
+ * >= 1 of each masked pair; freed by of_batch_destroy).
  * Errors: OF_EINVAL (NULL batch), OF_EHIP. */
 OF_API of_status of_batch_set_masks(of_batch* b, const uint8_t* const* masks, void* stream);
 
@@ -381,8 +383,10 @@ OF_API of_session* of_session_create(int H, int W, int levels, int radius, int i
 /* Region-of-interest mask of one stream (as of_plan_set_mask; Sec. 3.3): `mask` is a DEVICE
  * H x W uint8 plane of the session's size (nonzero = compute), NULL removes it.  Every later
  * push computes that session's flow with the mask: masked pixels get zero flow, tiles without
- * an unmasked pixel are skipped; equal to a plan with the same mask, bitwise.  Set-up call:
- * waits for the device, allocates the mask pyramid and tile flags (freed with the session).
+ * an unmasked pixel are left out of every iteration launch (the last iteration writes their
+ * zero flow); equal to a plan with the same mask, bitwise.  Set-up call: waits for the device,
+ * allocates the mask pyramid, tile flags and four FP32 flow planes per level >= 1 (freed with
+ * the session) and clears the session's flow planes.
  * Errors: OF_EINVAL (NULL session), OF_EHIP. */
 OF_API of_status of_session_set_mask(of_session* session, const uint8_t* mask, void* stream);
 
