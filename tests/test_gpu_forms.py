@@ -29,10 +29,10 @@ def _mask(H, W, k):
     return M
 
 
-def _plain(ofmi, I1, I2, mask=None, gaussian=False, iters=K):
+def _plain(ofmi, I1, I2, mask=None, gaussian=False, iters=K, fp16=False):
     import torch
     H, W = I1.shape
-    plan = ofmi.Plan(H, W, L, R, iters, gaussian_window=gaussian, device=dev())
+    plan = ofmi.Plan(H, W, L, R, iters, gaussian_window=gaussian, fp16=fp16, device=dev())
     if mask is not None:
         plan.set_mask(to_dev(mask))
     u, v = plan.compute(to_dev(I1), to_dev(I2))
@@ -42,14 +42,14 @@ def _plain(ofmi, I1, I2, mask=None, gaussian=False, iters=K):
     return out
 
 
-@pytest.mark.parametrize("gaussian", [False, True])
-def test_batch_masks_and_window_equal_plain_path(gpu_lib, gaussian):
+@pytest.mark.parametrize("gaussian,fp16", [(False, False), (True, False), (False, True)])
+def test_batch_masks_and_window_equal_plain_path(gpu_lib, gaussian, fp16):
     import torch
     ofmi = gpu_lib
     pairs = _pairs()
     masks = [_mask(*SIZES[0], 0), None, _mask(*SIZES[2], 3)]
-    announce(f"batch with masks, gaussian={gaussian}")
-    b = ofmi.Batch(SIZES, L, R, K, gaussian_window=gaussian, device=dev())
+    announce(f"batch with masks, gaussian={gaussian}, fp16={fp16}")
+    b = ofmi.Batch(SIZES, L, R, K, gaussian_window=gaussian, fp16=fp16, device=dev())
     d1 = [to_dev(p[0]) for p in pairs]
     d2 = [to_dev(p[1]) for p in pairs]
     b.set_masks([None if m is None else to_dev(m) for m in masks])
@@ -61,22 +61,49 @@ def test_batch_masks_and_window_equal_plain_path(gpu_lib, gaussian):
         b.compute(d1, d2, us, vs)
         torch.cuda.synchronize()
         for i, (p, m) in enumerate(zip(pairs, masks)):
-            pu, pv = _plain(ofmi, p[0], p[1], m, gaussian)
+            pu, pv = _plain(ofmi, p[0], p[1], m, gaussian, fp16=fp16)
             assert np.array_equal(us[i].cpu().numpy(), pu) and np.array_equal(vs[i].cpu().numpy(), pv), (i, cfg)
             if m is not None:
                 assert np.all(pu[m == 0] == 0) and np.all(pv[m == 0] == 0)
     ou, ov = oracle.flow(pairs[0][0], pairs[0][1], L, R, K, mask=masks[0].astype(bool),
                          window="gauss" if gaussian else "box")
     d = flow_error(us[0].cpu().numpy(), vs[0].cpu().numpy(), ou, ov)
-    assert d.max() <= 1e-3, report(d, 1e-3)
+    tol = 2e-2 if fp16 else 1e-3
+    assert d.max() <= tol, report(d, tol)
     # removing the masks gives the unmasked bits again
     b.set_masks(None)
     us, vs = b.outputs()
     b.compute(d1, d2, us, vs)
     torch.cuda.synchronize()
-    pu, pv = _plain(ofmi, pairs[2][0], pairs[2][1], None, gaussian)
+    pu, pv = _plain(ofmi, pairs[2][0], pairs[2][1], None, gaussian, fp16=fp16)
     assert np.array_equal(us[2].cpu().numpy(), pu) and np.array_equal(vs[2].cpu().numpy(), pv)
     b.close()
+
+
+def test_masked_batch_autotune_keeps_bits(gpu_lib):
+    """The autotuner on a masked batch (every candidate rebuilds the active-first tile lists and
+    clears the intermediate planes) leaves a configuration whose results equal the plain path's
+    with the same masks, bitwise, on the graph path and the eager path alike."""
+    import torch
+    ofmi = gpu_lib
+    pairs = _pairs()
+    masks = [_mask(*SIZES[0], 2), _mask(*SIZES[1], 0), None]
+    announce("masked batch autotune")
+    d1 = [to_dev(p[0]) for p in pairs]
+    d2 = [to_dev(p[1]) for p in pairs]
+    for graph in (True, False):
+        b = ofmi.Batch(SIZES, L, R, K, graph=graph, device=dev())
+        b.set_masks([None if m is None else to_dev(m) for m in masks])
+        us, vs = b.outputs()
+        b.autotune(d1, d2, us, vs, reps=1)
+        us, vs = b.outputs()
+        for _ in range(2):
+            b.compute(d1, d2, us, vs)
+        torch.cuda.synchronize()
+        for i, (p, m) in enumerate(zip(pairs, masks)):
+            pu, pv = _plain(ofmi, p[0], p[1], m)
+            assert np.array_equal(us[i].cpu().numpy(), pu) and np.array_equal(vs[i].cpu().numpy(), pv), (graph, i)
+        b.close()
 
 
 @pytest.mark.parametrize("iters,aligned", [(1, False), (K, False), (1, True), (K, True)])
