@@ -64,16 +64,13 @@ struct of_batch {
   int eager_next = 0;
   std::vector<std::pair<std::vector<uintptr_t>, int>> graph_slot;   // pointer set -> slot
   // Masks (of_batch_set_masks): per masked pair, its mask pyramid in `maskbuf` (offsets per
-  // level), a host copy for the tile flags, and the flags of the current tile heights in
-  // `flagbuf`.  A masked pair also gets four flow planes of its own per level >= 1 in
-  // `maskbuf` (plane_off), so that no level writes over another's zero regions: the zero
-  // regions of every intermediate plane are cleared once per tile configuration and only
-  // the final phase visits the tiles without an unmasked pixel.
+  // level) and a host copy from which the work lists take their tile flags and row cuts.  A
+  // masked pair also gets four flow planes of its own per level >= 1 in `maskbuf`
+  // (plane_off), so that no level writes over another's zero regions: the zero regions of
+  // every intermediate plane are cleared once per tile configuration and only the final
+  // phase visits the tiles without an unmasked pixel.
   uint8_t* maskbuf = nullptr;
-  uint8_t* flagbuf = nullptr;
-  size_t flag_cap = 0;
   std::vector<std::vector<size_t>> mask_off;      // [pair][level]
-  std::vector<std::vector<size_t>> flag_off;      // [pair][level]
   std::vector<std::vector<size_t>> plane_off;     // [pair][level >= 1] u0, u1, v0, v1 planes
   std::vector<std::vector<std::vector<uint8_t>>> hmask;   // [pair][level] host copies
   KernelTimer timer;
@@ -128,6 +125,14 @@ int default_batch_bands(const of_batch* b, int l) {
   return 1;
 }
 
+// Work items one pair's level can need at any tile height: the one-band tiles, or at taller
+// tiles every tile plus up to two zero items per tile cut to its unmasked bands (a two-band
+// tile loses at most one end, a taller one both: at most two more items per tile column than
+// the one-band tiles).
+size_t list_capacity(int H, int W, int N, int TW) {
+  return (size_t)((W + TW - 1) / TW) * ((H + N - 1) / N + 2);
+}
+
 // Tile flags of masked pair p at level l for the current tile height (0: no unmasked pixel,
 // 1: some, 2: all); empty for an unmasked pair.
 std::vector<uint8_t> pair_flags(const of_batch* b, int p, int l) {
@@ -137,33 +142,64 @@ std::vector<uint8_t> pair_flags(const of_batch* b, int p, int l) {
                     (2 * b->R + 1) * b->cfg[l].nb);
 }
 
-// Tile work lists of all levels for the current configuration, with the tiles that hold an
-// unmasked pixel first (nactive of them) and the all-masked tiles after them; the tile flags
-// of the masked pairs; and, for masked pairs, every intermediate flow plane cleared (the
-// phases before the final one write only the listed active tiles, so the rest stays zero).
-// Set-up calls only: no run may be in flight.
+// Rows [r0, r1) of rows [y0, y1) that hold an unmasked pixel in columns [c0, c1) of mask m.
+void unmasked_rows(const uint8_t* m, int W, int c0, int c1, int y0, int y1, int& r0, int& r1) {
+  r0 = y1;
+  r1 = y0;
+  for (int y = y0; y < y1; ++y) {
+    const uint8_t* row = m + (size_t)y * W;
+    bool any = false;
+    for (int c = c0; c < c1 && !any; ++c) any = row[c] != 0;
+    if (any) {
+      if (r0 == y1) r0 = y;
+      r1 = y + 1;
+    }
+  }
+}
+
+// Tile work lists of all levels for the current configuration (work items: pair | tile flag
+// << 16, tile x, first row, rows).  Each tile's height is cut to the bands the frame holds
+// (a tile at the bottom edge would otherwise run all its configured bands), and a tile with
+// masked pixels to its bands that hold unmasked rows (the masked rows cut off go to the zero
+// list).  The tiles with an unmasked pixel come first
+// (nactive of them), the all-masked ones after them.  For masked pairs every intermediate
+// flow plane is cleared: the phases before the final one write only the listed active tiles,
+// so the rest stays zero.  Set-up calls only: no run may be in flight.
 hipError_t upload_tiles(of_batch* b) {
-  const int TW = strip_width_for(b->R);
-  std::vector<uint8_t> flags(b->flag_cap, 0);
+  const int TW = strip_width_for(b->R), N = 2 * b->R + 1;
   for (int l = 0; l < b->L; ++l) {
-    const int TH = (2 * b->R + 1) * b->cfg[l].nb;
+    const int TH = N * b->cfg[l].nb;
     std::vector<int4> act, off;
+    b->partial[l] = 0;
     for (int p = 0; p < b->n; ++p) {
+      const int H = b->g[p].H[l], W = b->g[p].W[l];
       const std::vector<uint8_t> f = pair_flags(b, p, l);
-      if (!f.empty()) memcpy(flags.data() + b->flag_off[p][l], f.data(), f.size());
-      const int tx = (b->g[p].W[l] + TW - 1) / TW, ty = (b->g[p].H[l] + TH - 1) / TH;
+      const int tx = (W + TW - 1) / TW, ty = (H + TH - 1) / TH;
       for (int y = 0; y < ty; ++y)
-        for (int x = 0; x < tx; ++x)
-          (f.empty() || f[(size_t)y * tx + x] ? act : off).push_back(make_int4(p, x, y, TH));
+        for (int x = 0; x < tx; ++x) {
+          const int fl = f.empty() ? 2 : f[(size_t)y * tx + x];
+          const int y0 = y * TH, e = std::min(H, y0 + TH);
+          if (fl == 0) {
+            off.push_back(make_int4(p, x, y0, e - y0));
+            continue;
+          }
+          int ty0 = y0, th = std::min(TH, (e - y0 + N - 1) / N * N);
+          if (fl == 1) {
+            // from the first to the last band with an unmasked row; bands stay where the
+            // tile's bands are (multiples of 2r+1 from row 0), since the window sums combine
+            // per-band partial sums and so round by where the band boundaries fall
+            b->partial[l] = 1;
+            int r0, r1;
+            unmasked_rows(b->hmask[p][l].data(), W, x * TW, std::min(W, x * TW + TW), y0, e, r0, r1);
+            ty0 = y0 + (r0 - y0) / N * N;
+            th = ((r1 - 1 - ty0) / N + 1) * N;
+            if (ty0 > y0) off.push_back(make_int4(p, x, y0, ty0 - y0));
+            if (ty0 + th < e) off.push_back(make_int4(p, x, ty0 + th, e - (ty0 + th)));
+          }
+          act.push_back(make_int4(p | (fl << 16), x, ty0, th));
+        }
     }
     b->nactive[l] = (int)act.size();
-    b->partial[l] = 0;
-    for (int p = 0; p < b->n; ++p)
-      if (b->maskbuf && !b->mask_off[p].empty()) {
-        const size_t o = b->flag_off[p][l];
-        const int tx = (b->g[p].W[l] + TW - 1) / TW, ty = (b->g[p].H[l] + TH - 1) / TH;
-        for (size_t i = 0; i < (size_t)tx * ty; ++i) b->partial[l] |= flags[o + i] == 1;
-      }
     act.insert(act.end(), off.begin(), off.end());
     if (act.size() > b->cap_tiles) return hipErrorInvalidValue;
     b->ntiles[l] = (int)act.size();
@@ -171,9 +207,8 @@ hipError_t upload_tiles(of_batch* b) {
                              act.size() * sizeof(int4), hipMemcpyHostToDevice);
     if (e != hipSuccess) return e;
   }
-  if (!b->flagbuf) return hipSuccess;
-  hipError_t e = hipMemcpy(b->flagbuf, flags.data(), flags.size(), hipMemcpyHostToDevice);
-  for (int p = 0; p < b->n && e == hipSuccess; ++p) {
+  hipError_t e = hipSuccess;
+  for (int p = 0; p < b->n && e == hipSuccess && b->maskbuf; ++p) {
     if (b->mask_off[p].empty()) continue;
     const Geometry& g = b->g[p];
     const size_t n0 = (size_t)g.H[0] * g.W[0] * sizeof(float);
@@ -238,10 +273,7 @@ void fill_args(const of_batch* b, char* blk, const void* const* I1, const void* 
         a.uout = last ? u[p] : fu[buf];
         a.vout = last ? v[p] : fv[buf];
         if (b->flags & OF_FLAG_GAUSSIAN_WINDOW) gaussian_taps(a.taps, b->R);
-        if (masked) {
-          a.mask = b->maskbuf + b->mask_off[p][l];
-          a.tiles = b->flagbuf + b->flag_off[p][l];
-        }
+        if (masked) a.mask = b->maskbuf + b->mask_off[p][l];
         cu = a.uout;
         cv = a.vout;
         cH = a.H;
@@ -395,7 +427,7 @@ size_t of_batch_workspace_bytes(int n, const int* H, const int* W, int levels, i
     for (int p = 0; p < n; ++p) {
       Geometry g = make_geometry(H[p], W[p], levels, radius, iters, flags);
       if (l == 0) off += align256(g.bytes);
-      tl += (size_t)((g.W[l] + TW - 1) / TW) * ((g.H[l] + N - 1) / N);
+      tl += list_capacity(g.H[l], g.W[l], N, TW);
       if (l >= 1) it += 2 * (size_t)reduce_blocks(g.H[l], g.W[l]);
     }
     tiles = std::max(tiles, tl);
@@ -438,8 +470,7 @@ of_batch* of_batch_create(int n, const int* H, const int* W, int levels, int rad
   size_t cap = 0;
   for (int l = 0; l < levels; ++l) {
     size_t tl = 0;
-    for (int p = 0; p < n; ++p)
-      tl += (size_t)((b->g[p].W[l] + TW - 1) / TW) * ((b->g[p].H[l] + N - 1) / N);
+    for (int p = 0; p < n; ++p) tl += list_capacity(b->g[p].H[l], b->g[p].W[l], N, TW);
     cap = std::max(cap, tl);
   }
   b->cap_tiles = align256(cap * sizeof(int4)) / sizeof(int4);
@@ -579,7 +610,6 @@ void of_batch_destroy(of_batch* b) {
     if (b->slot_done[i]) hipEventDestroy(b->slot_done[i]);
   if (b->pinned) hipHostFree(b->pinned);
   if (b->maskbuf) hipFree(b->maskbuf);
-  if (b->flagbuf) hipFree(b->flagbuf);
   if (b->owns_ws) hipFree(b->ws);
   delete b;
 }
@@ -592,22 +622,17 @@ of_status of_batch_set_masks(of_batch* b, const uint8_t* const* masks, void* str
   if (e != hipSuccess) return hip_fail("set_masks", e);
   drop_graphs(b);
   if (b->maskbuf) hipFree(b->maskbuf);
-  if (b->flagbuf) hipFree(b->flagbuf);
-  b->maskbuf = b->flagbuf = nullptr;
+  b->maskbuf = nullptr;
   b->mask_off.assign(b->n, {});
-  b->flag_off.assign(b->n, {});
   b->plane_off.assign(b->n, {});
   b->hmask.assign(b->n, {});
-  b->flag_cap = 0;
   bool any = false;
   for (int p = 0; masks && p < b->n; ++p) any |= masks[p] != nullptr;
   if (!any) {   // every tile active again
     e = upload_tiles(b);
     return e == hipSuccess ? OF_OK : hip_fail("set_masks", e);
   }
-  // layout: mask pyramids and flow planes of levels >= 1 of the masked pairs; flag capacity
-  // at one-band tiles (the most tiles)
-  const int TW = strip_width_for(b->R), N = 2 * b->R + 1;
+  // layout: mask pyramids and flow planes of levels >= 1 of the masked pairs
   size_t mtotal = 0;
   for (int p = 0; p < b->n; ++p) {
     if (!masks[p]) continue;
@@ -615,8 +640,6 @@ of_status of_batch_set_masks(of_batch* b, const uint8_t* const* masks, void* str
     for (int l = 0; l < b->L; ++l) {
       b->mask_off[p].push_back(mtotal);
       mtotal += align256((size_t)g.H[l] * g.W[l]);
-      b->flag_off[p].push_back(b->flag_cap);
-      b->flag_cap += (size_t)((g.W[l] + TW - 1) / TW) * ((g.H[l] + N - 1) / N);
     }
     b->plane_off[p].assign(b->L, 0);
     for (int l = 1; l < b->L; ++l) {
@@ -625,7 +648,6 @@ of_status of_batch_set_masks(of_batch* b, const uint8_t* const* masks, void* str
     }
   }
   e = hipMalloc((void**)&b->maskbuf, mtotal);
-  if (e == hipSuccess) e = hipMalloc((void**)&b->flagbuf, std::max<size_t>(b->flag_cap, 1));
   for (int p = 0; p < b->n && e == hipSuccess; ++p) {
     if (!masks[p]) continue;
     const Geometry& g = b->g[p];
@@ -648,8 +670,7 @@ of_status of_batch_set_masks(of_batch* b, const uint8_t* const* masks, void* str
   if (e == hipSuccess) e = upload_tiles(b);
   if (e != hipSuccess) {
     if (b->maskbuf) hipFree(b->maskbuf);
-    if (b->flagbuf) hipFree(b->flagbuf);
-    b->maskbuf = b->flagbuf = nullptr;
+    b->maskbuf = nullptr;
     b->mask_off.assign(b->n, {});
     b->plane_off.assign(b->n, {});
     upload_tiles(b);

@@ -26,8 +26,9 @@ struct IterArgs {
   int Hc, Wc;          // coarse level size (kFlowCoarse)
   int mode;            // FlowMode
   const uint8_t* mask; // this level's mask (nonzero = computed) or nullptr (no mask)
-  const uint8_t* tiles; // with a mask, one flag per iteration tile: 0 = no unmasked output
-                        // pixel, 1 = some masked pixels, 2 = no masked pixel
+  const uint8_t* tiles; // plain launches with a mask: one flag per iteration tile: 0 = no
+                        // unmasked output pixel, 1 = some masked pixels, 2 = no masked pixel
+                        // (batched launches carry the flag in the work item)
   float taps[kMaxTaps]; // Gaussian-weighted window: separable taps g[0..2r] (unused for the box)
   // Recirculation-bubble count (eq. 3), final iteration of a plan only: when bcount is set,
   // the launch adds to *bcount the number of written u values <= *bthr.

@@ -70,8 +70,10 @@ constexpr int kMaxPairRadius = 8;
 // Added to a plain launch's variant: Gaussian-weighted window sums (taps in IterArgs::taps).
 constexpr int kTileGauss = 16;
 
-// Batched iteration launch: `grid` workgroups stride over `ntiles` work items
-// (pair, tile x, tile y, tile height) with per-pair arguments args[pair] (device arrays).
+// Batched iteration launch: `grid` workgroups stride over `ntiles` work items (pair | tile
+// flag << 16, tile x, first output row, output rows) with per-pair arguments args[pair]
+// (device arrays); the flag (0 no unmasked pixel, 1 some masked pixels, 2 none) is read for
+// pairs with a mask.
 struct BatchLaunch {
   const IterArgs* args;
   const int4* tiles;
@@ -118,8 +120,8 @@ hipError_t launch_normalize(Elem t, const void* in, float* out, int H, int W, in
 
 // u = v = 0 over n elements (a fill kernel, safe under stream capture).
 hipError_t launch_zero(float* u, float* v, size_t n, hipStream_t s);
-// Zero flow over a work list of tiles (pair, tile x, tile y, tile height; tw columns wide) into
-// the output planes of args[pair] (tw divides 256).
+// Zero flow over a work list of tiles (batch work items: pair in the low 16 bits of x, tile x,
+// first row, rows; tw columns wide) into the output planes of args[pair] (tw divides 256).
 hipError_t launch_zero_tiles(const IterArgs* args, const int4* tiles, int ntiles, int tw,
                              hipStream_t s);
 // Loads the zero-tiles kernel's code on the current device (no launch).

@@ -30,19 +30,21 @@ __global__ void zero_kernel(float* u, float* v, size_t n) {
   }
 }
 
-// Zero flow over listed tiles of many pairs (pair, tile x, tile y, tile height; tiles TW columns
-// wide), written into each pair's output planes of its arguments.  One workgroup per tile at a
-// time, TW-column rows (TW divides the workgroup size).
+// Zero flow over listed tiles of many pairs (batch work items: pair in the low 16 bits of x,
+// tile x, first row, rows; tiles TW columns wide), written into each pair's output planes of
+// its arguments.  One workgroup per tile at a time, TW-column rows (TW divides the workgroup
+// size).
 __global__ __launch_bounds__(256) void zero_tiles_kernel(const IterArgs* __restrict__ args,
                                                          const int4* __restrict__ tiles,
                                                          int ntiles, int tw) {
   const int c = (int)threadIdx.x % tw, rstep = (int)blockDim.x / tw;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int4 w = tiles[t];
-    float* __restrict__ u = args[w.x].uout;
-    float* __restrict__ v = args[w.x].vout;
-    const int W = args[w.x].W, H = args[w.x].H;
-    const int x = w.y * tw + c, y0 = w.z * w.w, y1 = min(H, y0 + w.w);
+    const int p = w.x & 0xffff;
+    float* __restrict__ u = args[p].uout;
+    float* __restrict__ v = args[p].vout;
+    const int W = args[p].W, H = args[p].H;
+    const int x = w.y * tw + c, y0 = w.z, y1 = min(H, y0 + w.w);
     if (x >= W) continue;
     for (int y = y0 + (int)threadIdx.x / tw; y < y1; y += rstep) {
       const size_t o = (size_t)y * W + x;

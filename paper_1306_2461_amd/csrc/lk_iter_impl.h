@@ -117,7 +117,7 @@ constexpr bool field_ring() {
   return MODE != kFlowZero && WIDE && !LEAN && BB == 1;
 }
 
-// One tile: TW output columns from x0 = bx*TW and TH output rows from y0 = by*TH, walked in
+// One tile: TW output columns from x0 = bx*TW and TH output rows from row y0, walked in
 // nbands bands (TH is a multiple of N; nbands = TH/N + 1).  `sm4` is the workgroup's LDS.
 // INTERIOR: the tile's whole warped-frame region (the tile grown by r + 1 px, all bands)
 // lies inside the image, so no position needs clamping or an in-image test.
@@ -142,7 +142,7 @@ constexpr bool field_ring() {
 // reads rows tb-R .. tb+R, at most 5R+2 < FRING apart, so no slot is shared.
 template <typename T, int R, int TW, int MODE, bool WIDE, bool DEFER, bool INTERIOR, bool LEAN,
           bool GAUSS = false, int BB = 1, bool FR = false, bool BUB = false>
-__device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands, int bx, int by,
+__device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands, int bx, int y0,
                                            bool pixel_mask, float4* sm4) {
   using C = Cfg<R, TW, WIDE, BB>;
   constexpr int N = C::N, NR = C::NR, NT = C::NT, PC = C::PC, WC = C::WC, PP = C::PP, WP = C::WP;
@@ -164,7 +164,6 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
   const int tid0 = threadIdx.x;
   const int H = a.H, W = a.W;
   const int x0 = bx * TW;
-  const int y0 = by * TH;
   const T* __restrict__ I1 = (const T*)a.I1;
   const T* __restrict__ I2 = (const T*)a.I2;
 
@@ -509,10 +508,9 @@ __device__ __forceinline__ void strip_tile(const IterArgs& a, int TH, int nbands
 // True when every warped-frame position of the tile (columns x0-R-1 .. x0+TW+R, rows
 // y0-R-1 .. y0-R+N*nbands) lies inside the image.
 template <int R, int TW>
-__device__ __forceinline__ bool tile_interior(const IterArgs& a, int TH, int nbands, int bx,
-                                              int by) {
+__device__ __forceinline__ bool tile_interior(const IterArgs& a, int nbands, int bx, int y0) {
   constexpr int N = 2 * R + 1;
-  const int x0 = bx * TW, y0 = by * TH;
+  const int x0 = bx * TW;
   return x0 - R - 1 >= 0 && x0 + TW + R <= a.W - 1 && y0 - R - 1 >= 0 &&
          y0 - R + N * nbands <= a.H - 1;
 }
@@ -521,8 +519,8 @@ __device__ __forceinline__ bool tile_interior(const IterArgs& a, int TH, int nba
 // y0) is not computed; its workgroup writes zero flow over it (and counts those zeros for the
 // eq. 3 count when the threshold is not negative).
 template <int TW>
-__device__ __forceinline__ void zero_tile(const IterArgs& a, int TH, int bx, int by) {
-  const int x0 = bx * TW, y0 = by * TH;
+__device__ __forceinline__ void zero_tile(const IterArgs& a, int TH, int bx, int y0) {
+  const int x0 = bx * TW;
   const int w = min(TW, a.W - x0), h = min(TH, a.H - y0);
   for (int i = threadIdx.x; i < w * h; i += blockDim.x) {
     const int r = i / w, c = i - r * w;
@@ -549,30 +547,31 @@ __global__ __launch_bounds__((group_threads<R, TW, WIDE, BB>())) void lk_iter_st
   extern __shared__ float4 sm4[];
   const int t = xcd_order(blockIdx.x, gridDim.x);
   if (t >= ntiles) return;
-  const int bx = t % tiles_x, by = t / tiles_x;
+  const int bx = t % tiles_x, y0 = t / tiles_x * TH;
   bool pixel_mask = false;
   if (a.mask) {
     const int f = a.tiles[t];
     if (f == 0) {
-      zero_tile<TW>(a, TH, bx, by);
+      zero_tile<TW>(a, TH, bx, y0);
       return;
     }
     pixel_mask = f == 1;
   }
   constexpr bool kDefer = WIDE || R > 8;
   constexpr bool kFR = field_ring<MODE, WIDE, LEAN, BB>();
-  if (R <= 8 && tile_interior<R, TW>(a, TH, nbands, bx, by))
+  if (R <= 8 && tile_interior<R, TW>(a, nbands, bx, y0))
     strip_tile<T, R, TW, MODE, WIDE, kDefer, true, LEAN, GAUSS, BB, kFR, true>(a, TH, nbands, bx,
-                                                                               by, pixel_mask, sm4);
+                                                                               y0, pixel_mask, sm4);
   else
     strip_tile<T, R, TW, MODE, WIDE, kDefer, false, LEAN, GAUSS, BB, kFR, true>(a, TH, nbands, bx,
-                                                                                by, pixel_mask, sm4);
+                                                                                y0, pixel_mask, sm4);
 }
 
 // Batched form: workgroups stride over a work list of tiles of many pairs at the same
-// (level, iteration) phase.  Work item = (pair, tile x, tile y, tile height).  A pair with a
-// mask carries its level mask and tile flags in its arguments (flags indexed by tile row x
-// tiles per row at this tile height): tiles without an unmasked pixel are zero-filled.
+// (level, iteration) phase.  Work item = (pair | tile flag << 16, tile x, first output row,
+// output rows, a multiple of 2r+1).  For a pair with a mask (in its arguments) the flag tells
+// a tile without an unmasked pixel (0, zero-filled), one with masked pixels (1) and one
+// without (2).
 // MASK: launches of batches with masks (the mask code costs the unmasked launches about 5 %
 // more instructions and is compiled out of them).
 template <typename T, int R, int TW, int MODE, bool WIDE, bool LEAN, bool GAUSS, bool MASK>
@@ -584,12 +583,12 @@ __global__ __launch_bounds__((group_threads<R, TW, WIDE, 1>())) void lk_iter_bat
   const int stride = (int)gridDim.x;
   for (int t = xcd_order(blockIdx.x, gridDim.x); t < ntiles; t += stride) {
     const int4 w = tiles[t];
-    const IterArgs a = args[w.x];
+    const IterArgs a = args[w.x & 0xffff];
     const int nb = w.w / C::N + 1;
     bool pixel_mask = false;
     if constexpr (MASK) {
       if (a.mask) {
-        const int f = a.tiles[w.z * ((a.W + TW - 1) / TW) + w.y];
+        const int f = (int)((unsigned)w.x >> 16);
         if (f == 0) {
           zero_tile<TW>(a, w.w, w.y, w.z);
           continue;
@@ -598,7 +597,7 @@ __global__ __launch_bounds__((group_threads<R, TW, WIDE, 1>())) void lk_iter_bat
       }
     }
     constexpr bool kFR = MODE != kFlowZero;
-    if (R <= 8 && tile_interior<R, TW>(a, w.w, nb, w.y, w.z))
+    if (R <= 8 && tile_interior<R, TW>(a, nb, w.y, w.z))
       strip_tile<T, R, TW, MODE, WIDE, true, true, LEAN, GAUSS, 1, kFR>(a, w.w, nb, w.y, w.z,
                                                                         pixel_mask, sm4);
     else

@@ -64,13 +64,12 @@ struct of_session {
   char* flow = nullptr;           // four level-0 FP32 planes
   int cur = 0;                    // slot that receives the next frame
   bool has_prev = false;
-  // mask (of_session_set_mask): mask pyramid and the tile flags of every push tile height
-  // (device, and a host copy that orders the push tile lists), and four FP32 flow planes per
-  // level >= 1 in the same allocation, so that no level writes over another's zero regions:
-  // every intermediate plane holds zero at the masked pixels from set-up on (the launches
-  // write zero there too), so the all-masked tiles are left out of all but the final phase.
+  // mask (of_session_set_mask): mask pyramid and four FP32 flow planes per level >= 1 in one
+  // allocation, so that no level writes over another's zero regions: every intermediate plane
+  // holds zero at the masked pixels from set-up on (the launches write zero there too), so
+  // the all-masked tiles are left out of all but the final phase.  The tile flags of every
+  // push tile height are kept on the host, where the push work lists are built.
   uint8_t* maskbuf = nullptr;
-  uint8_t* flagbuf = nullptr;
   size_t mask_off[OF_MAX_LEVELS] = {};
   size_t flag_off[3][OF_MAX_LEVELS] = {};
   size_t plane_off[OF_MAX_LEVELS] = {};
@@ -296,7 +295,6 @@ void destroy_server(of_server* s) {
   for (of_session* ss : s->sessions) {
     if (ss->owns_mem) hipFree(ss->mem);
     if (ss->maskbuf) hipFree(ss->maskbuf);
-    if (ss->flagbuf) hipFree(ss->flagbuf);
     delete ss;
   }
   free_ring(s);
@@ -361,7 +359,6 @@ of_status of_server_close(of_server* s, of_session* ss) {
   hipDeviceSynchronize();
   if (ss->owns_mem) hipFree(ss->mem);
   if (ss->maskbuf) hipFree(ss->maskbuf);
-  if (ss->flagbuf) hipFree(ss->flagbuf);
   s->resident -= ss->bytes;
   s->sessions.erase(std::remove(s->sessions.begin(), s->sessions.end(), ss), s->sessions.end());
   delete ss;
@@ -408,6 +405,8 @@ of_status of_server_push(of_server* s, of_session* const* ss, int n, const void*
   std::vector<int> flowing;
   for (int i = 0; i < n; ++i)
     if (ss[i]->has_prev && K > 0) flowing.push_back(i);
+  if (flowing.size() > 65536)   // work items carry the session index in 16 bits
+    return set_error("more than 65536 flowing sessions in one push"), OF_EINVAL;
   const int TW = strip_width_for(R), N = 2 * R + 1;
   p.args.resize((size_t)L * (K > 0 ? K : 0));
   p.tiles.resize(L);
@@ -429,7 +428,13 @@ of_status of_server_push(of_server* s, of_session* const* ss, int n, const void*
         for (int xx = 0; xx < tx; ++xx) {
           const int fl = f ? f[(size_t)yy * tx + xx] : 2;
           p.partial[l] |= fl == 1;
-          (fl ? p.tiles[l] : off).push_back(make_int4(q, xx, yy, TH));
+          // work item (session | flag << 16, tile x, first row, rows): the height cut to the
+          // bands the frame holds
+          const int y0 = yy * TH, rows = std::min(TH, x->g.H[l] - y0);
+          if (fl == 0)
+            off.push_back(make_int4(q, xx, y0, rows));
+          else
+            p.tiles[l].push_back(make_int4(q | (fl << 16), xx, y0, (rows + N - 1) / N * N));
         }
     }
     p.nactive[l] = (int)p.tiles[l].size();
@@ -469,10 +474,7 @@ of_status of_server_push(of_server* s, of_session* const* ss, int n, const void*
         a.uout = last ? u[i] : fu[buf];
         a.vout = last ? v[i] : fv[buf];
         if (s->flags & OF_FLAG_GAUSSIAN_WINDOW) gaussian_taps(a.taps, R);
-        if (x->maskbuf) {
-          a.mask = x->maskbuf + x->mask_off[l];
-          a.tiles = x->flagbuf + x->flag_off[band_slot(level_bands[l])][l];
-        }
+        if (x->maskbuf) a.mask = x->maskbuf + x->mask_off[l];
         p.args[phase].push_back(a);
         cu = a.uout;
         cv = a.vout;
@@ -559,8 +561,7 @@ of_status of_session_set_mask(of_session* ss, const uint8_t* mask, void* stream)
   hipError_t e = hipDeviceSynchronize();   // pushes in flight read the old mask
   if (e != hipSuccess) return hip_fail("set_mask", e);
   if (ss->maskbuf) hipFree(ss->maskbuf);
-  if (ss->flagbuf) hipFree(ss->flagbuf);
-  ss->maskbuf = ss->flagbuf = nullptr;
+  ss->maskbuf = nullptr;
   ss->hflags.clear();
   if (!mask) return OF_OK;
   e = prime_push_kernels(s, true);
@@ -583,9 +584,7 @@ of_status of_session_set_mask(of_session* ss, const uint8_t* mask, void* stream)
     mt += align256(4 * (size_t)g.H[l] * g.W[l] * sizeof(float));
   }
   uint8_t* mb = nullptr;
-  uint8_t* fb = nullptr;
   e = hipMalloc((void**)&mb, mt);
-  if (e == hipSuccess) e = hipMalloc((void**)&fb, ft);
   if (e == hipSuccess) e = hipMemcpyAsync(mb, mask, (size_t)g.H[0] * g.W[0], hipMemcpyDeviceToDevice, st);
   for (int l = 1; l < L && e == hipSuccess; ++l)
     e = launch_mask_reduce(mb + ss->mask_off[l - 1], g.H[l - 1], g.W[l - 1], mb + ss->mask_off[l],
@@ -605,14 +604,11 @@ of_status of_session_set_mask(of_session* ss, const uint8_t* mask, void* stream)
       memcpy(flags.data() + ss->flag_off[b][l], f.data(), f.size());
     }
   }
-  if (e == hipSuccess) e = hipMemcpy(fb, flags.data(), ft, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     if (mb) hipFree(mb);
-    if (fb) hipFree(fb);
     return hip_fail("set_mask", e);
   }
   ss->maskbuf = mb;
-  ss->flagbuf = fb;
   ss->hflags = std::move(flags);
   return OF_OK;
 }

@@ -213,3 +213,38 @@ def test_served_masks_set_late_full_and_aligned(gpu_lib):
             assert r.has_flow and np.array_equal(r.u, pu) and np.array_equal(r.v, pv), (s, t)
             if m is not None:
                 assert np.all(r.u[m == 0] == 0) and np.all(r.v[m == 0] == 0)
+
+
+@pytest.mark.parametrize("bands,variant", [([3, 2, 2], [1, 2, 0]), ([2, 3, 1], [2, 1, 1])])
+def test_batch_masked_tiles_cut_to_unmasked_rows(gpu_lib, bands, variant):
+    """Tiles with masked pixels run only their bands that hold unmasked rows (masked rows cut
+    off at the top, at the bottom, and at the frame's bottom edge), and the rows cut off are
+    zero-filled in the final phase; tiles at the bottom edge run only the bands the frame
+    holds.  Flows equal the plain path's with the same masks, bitwise."""
+    import torch
+    ofmi = gpu_lib
+    pairs = _pairs()
+    m0 = np.ones(SIZES[0], np.uint8)      # 160 x 200
+    m0[:20] = 0                           # a wall: the first tile row loses its top bands
+    m0[40:54, :64] = 0                    # the second tile row of the first strip its bottom
+    m0[135:151] = 0                       # the last tile row (at the bottom edge) its top
+    m0[60:66, 100:] = 0                   # masked rows inside a tile: nothing cut
+    m2 = np.ones(SIZES[2], np.uint8)      # 256 x 256
+    m2[90:, :64] = 0
+    m2[:, 200:] = 0
+    masks = [m0, None, m2]
+    announce(f"batch masked tiles cut to unmasked rows, bands={bands}")
+    d1 = [to_dev(p[0]) for p in pairs]
+    d2 = [to_dev(p[1]) for p in pairs]
+    b = ofmi.Batch(SIZES, L, R, K, device=dev())
+    b.set_masks([None if m is None else to_dev(m) for m in masks])
+    b.set_config({"bands": bands, "grid": [0, 16, 0], "variant": variant})
+    us, vs = b.outputs()
+    for t in us + vs:
+        t.fill_(7.0)
+    b.compute(d1, d2, us, vs)
+    torch.cuda.synchronize()
+    for i, (p, m) in enumerate(zip(pairs, masks)):
+        pu, pv = _plain(ofmi, p[0], p[1], m)
+        assert np.array_equal(us[i].cpu().numpy(), pu) and np.array_equal(vs[i].cpu().numpy(), pv), i
+    b.close()
