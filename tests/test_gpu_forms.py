@@ -215,8 +215,11 @@ def test_served_masks_set_late_full_and_aligned(gpu_lib):
                 assert np.all(r.u[m == 0] == 0) and np.all(r.v[m == 0] == 0)
 
 
-@pytest.mark.parametrize("bands,variant", [([3, 2, 2], [1, 2, 0]), ([2, 3, 1], [2, 1, 1])])
-def test_batch_masked_tiles_cut_to_unmasked_rows(gpu_lib, bands, variant):
+@pytest.mark.parametrize("bands,variant,gaussian,fp16", [([3, 2, 2], [1, 2, 0], False, False),
+                                                         ([2, 3, 1], [2, 1, 1], False, False),
+                                                         ([3, 2, 2], [1, 2, 0], True, False),
+                                                         ([3, 3, 2], [2, 2, 1], False, True)])
+def test_batch_masked_tiles_cut_to_unmasked_rows(gpu_lib, bands, variant, gaussian, fp16):
     """Tiles with masked pixels run only their bands that hold unmasked rows (masked rows cut
     off at the top, at the bottom, and at the frame's bottom edge), and the rows cut off are
     zero-filled in the final phase; tiles at the bottom edge run only the bands the frame
@@ -233,10 +236,10 @@ def test_batch_masked_tiles_cut_to_unmasked_rows(gpu_lib, bands, variant):
     m2[90:, :64] = 0
     m2[:, 200:] = 0
     masks = [m0, None, m2]
-    announce(f"batch masked tiles cut to unmasked rows, bands={bands}")
+    announce(f"batch masked tiles cut to unmasked rows, bands={bands}, gaussian={gaussian}, fp16={fp16}")
     d1 = [to_dev(p[0]) for p in pairs]
     d2 = [to_dev(p[1]) for p in pairs]
-    b = ofmi.Batch(SIZES, L, R, K, device=dev())
+    b = ofmi.Batch(SIZES, L, R, K, gaussian_window=gaussian, fp16=fp16, device=dev())
     b.set_masks([None if m is None else to_dev(m) for m in masks])
     b.set_config({"bands": bands, "grid": [0, 16, 0], "variant": variant})
     us, vs = b.outputs()
@@ -245,6 +248,6 @@ def test_batch_masked_tiles_cut_to_unmasked_rows(gpu_lib, bands, variant):
     b.compute(d1, d2, us, vs)
     torch.cuda.synchronize()
     for i, (p, m) in enumerate(zip(pairs, masks)):
-        pu, pv = _plain(ofmi, p[0], p[1], m)
+        pu, pv = _plain(ofmi, p[0], p[1], m, gaussian, fp16=fp16)
         assert np.array_equal(us[i].cpu().numpy(), pu) and np.array_equal(vs[i].cpu().numpy(), pv), i
     b.close()
