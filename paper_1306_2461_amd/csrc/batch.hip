@@ -142,21 +142,6 @@ std::vector<uint8_t> pair_flags(const of_batch* b, int p, int l) {
                     (2 * b->R + 1) * b->cfg[l].nb);
 }
 
-// Rows [r0, r1) of rows [y0, y1) that hold an unmasked pixel in columns [c0, c1) of mask m.
-void unmasked_rows(const uint8_t* m, int W, int c0, int c1, int y0, int y1, int& r0, int& r1) {
-  r0 = y1;
-  r1 = y0;
-  for (int y = y0; y < y1; ++y) {
-    const uint8_t* row = m + (size_t)y * W;
-    bool any = false;
-    for (int c = c0; c < c1 && !any; ++c) any = row[c] != 0;
-    if (any) {
-      if (r0 == y1) r0 = y;
-      r1 = y + 1;
-    }
-  }
-}
-
 // Tile work lists of all levels for the current configuration (work items: pair | tile flag
 // << 16, tile x, first row, rows).  Each tile's height is cut to the bands the frame holds
 // (a tile at the bottom edge would otherwise run all its configured bands), and a tile with
@@ -189,10 +174,7 @@ hipError_t upload_tiles(of_batch* b) {
             // tile's bands are (multiples of 2r+1 from row 0), since the window sums combine
             // per-band partial sums and so round by where the band boundaries fall
             b->partial[l] = 1;
-            int r0, r1;
-            unmasked_rows(b->hmask[p][l].data(), W, x * TW, std::min(W, x * TW + TW), y0, e, r0, r1);
-            ty0 = y0 + (r0 - y0) / N * N;
-            th = ((r1 - 1 - ty0) / N + 1) * N;
+            band_cut(b->hmask[p][l].data(), W, x * TW, std::min(W, x * TW + TW), y0, e, N, ty0, th);
             if (ty0 > y0) off.push_back(make_int4(p, x, y0, ty0 - y0));
             if (ty0 + th < e) off.push_back(make_int4(p, x, ty0 + th, e - (ty0 + th)));
           }

@@ -136,6 +136,11 @@ void gaussian_taps(float* taps, int R);
 // Flags of the iteration tiles (TW columns x TH rows) of an H x W mask level: 0 = no unmasked
 // pixel, 1 = some masked pixels, 2 = no masked pixel; row-major over tile rows.
 std::vector<uint8_t> tile_flags(const uint8_t* mask, int H, int W, int TW, int TH);
+// Band cut of a tile with masked pixels: rows [y0, e) and columns [c0, c1) of mask m (row
+// pitch W), bands of N rows from y0.  Returns the first row and the rows (a multiple of N) from
+// the tile's first to its last band that holds an unmasked pixel; the band boundaries stay
+// where the tile's are, so the window sums round as in the uncut tile.
+void band_cut(const uint8_t* m, int W, int c0, int c1, int y0, int e, int N, int& ty0, int& th);
 int default_bands(int H, int W, int R);
 int default_tile_variant(long long ntiles);
 bool check_params(int H, int W, int levels, int radius, int iters, unsigned flags);

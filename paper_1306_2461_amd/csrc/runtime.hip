@@ -216,6 +216,26 @@ std::vector<uint8_t> tile_flags(const uint8_t* m, int H, int W, int TW, int TH) 
   return f;
 }
 
+void band_cut(const uint8_t* m, int W, int c0, int c1, int y0, int e, int N, int& ty0, int& th) {
+  int r0 = e, r1 = y0;   // rows [r0, r1) hold an unmasked pixel
+  for (int y = y0; y < e; ++y) {
+    const uint8_t* row = m + (size_t)y * W;
+    bool any = false;
+    for (int c = c0; c < c1 && !any; ++c) any = row[c] != 0;
+    if (any) {
+      if (r0 == e) r0 = y;
+      r1 = y + 1;
+    }
+  }
+  if (r0 >= r1) {   // nothing unmasked: an empty cut
+    ty0 = y0;
+    th = 0;
+    return;
+  }
+  ty0 = y0 + (r0 - y0) / N * N;
+  th = ((r1 - 1 - ty0) / N + 1) * N;
+}
+
 int window_variant(const Geometry& g, int l, IterArgs& a) {
   if (!(g.flags & OF_FLAG_GAUSSIAN_WINDOW)) return g.variant[l];
   gaussian_taps(a.taps, g.R);

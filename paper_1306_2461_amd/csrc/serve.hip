@@ -68,12 +68,14 @@ struct of_session {
   // allocation, so that no level writes over another's zero regions: every intermediate plane
   // holds zero at the masked pixels from set-up on (the launches write zero there too), so
   // the all-masked tiles are left out of all but the final phase.  The tile flags of every
-  // push tile height are kept on the host, where the push work lists are built.
+  // push tile height, and the band cuts of the tiles with masked pixels (first row, rows), are
+  // kept on the host, where the push work lists are built.
   uint8_t* maskbuf = nullptr;
   size_t mask_off[OF_MAX_LEVELS] = {};
   size_t flag_off[3][OF_MAX_LEVELS] = {};
   size_t plane_off[OF_MAX_LEVELS] = {};
   std::vector<uint8_t> hflags;
+  std::vector<int2> hcut;
 };
 
 struct of_server {
@@ -186,8 +188,10 @@ size_t push_bound(const std::vector<of_session*>& ss, int L, int R, int K) {
   b += (size_t)L * (K > 0 ? K : 0) * align256(n * sizeof(IterArgs));
   for (int l = 0; l < L; ++l) {
     size_t tiles = 0;
+    // one-band tiles, or taller tiles plus up to two zero items per tile cut to its unmasked
+    // bands: at most two more items per tile column
     for (const of_session* x : ss)
-      tiles += (size_t)((x->g.W[l] + TW - 1) / TW) * ((x->g.H[l] + N - 1) / N);
+      tiles += (size_t)((x->g.W[l] + TW - 1) / TW) * ((x->g.H[l] + N - 1) / N + 2);
     b += align256(tiles * sizeof(int4));
   }
   return b;
@@ -421,20 +425,30 @@ of_status of_server_push(of_server* s, of_session* const* ss, int n, const void*
     std::vector<int4> off;   // all-masked tiles, after the active ones
     for (int q = 0; q < (int)flowing.size(); ++q) {
       const of_session* x = ss[flowing[q]];
-      const uint8_t* f =
-          x->maskbuf ? x->hflags.data() + x->flag_off[band_slot(level_bands[l])][l] : nullptr;
+      const size_t fo = x->maskbuf ? x->flag_off[band_slot(level_bands[l])][l] : 0;
+      const uint8_t* f = x->maskbuf ? x->hflags.data() + fo : nullptr;
       const int tx = (x->g.W[l] + TW - 1) / TW, ty = (x->g.H[l] + TH - 1) / TH;
       for (int yy = 0; yy < ty; ++yy)
         for (int xx = 0; xx < tx; ++xx) {
           const int fl = f ? f[(size_t)yy * tx + xx] : 2;
           p.partial[l] |= fl == 1;
           // work item (session | flag << 16, tile x, first row, rows): the height cut to the
-          // bands the frame holds
-          const int y0 = yy * TH, rows = std::min(TH, x->g.H[l] - y0);
-          if (fl == 0)
-            off.push_back(make_int4(q, xx, y0, rows));
-          else
-            p.tiles[l].push_back(make_int4(q | (fl << 16), xx, y0, (rows + N - 1) / N * N));
+          // bands the frame holds, a tile with masked pixels to its bands with unmasked rows
+          // (the rows cut off are zero-filled in the final phase)
+          const int y0 = yy * TH, e = std::min(x->g.H[l], y0 + TH);
+          if (fl == 0) {
+            off.push_back(make_int4(q, xx, y0, e - y0));
+            continue;
+          }
+          int ty0 = y0, th = (e - y0 + N - 1) / N * N;
+          if (fl == 1) {
+            const int2 c = x->hcut[fo + (size_t)yy * tx + xx];
+            ty0 = c.x;
+            th = c.y;
+            if (ty0 > y0) off.push_back(make_int4(q, xx, y0, ty0 - y0));
+            if (ty0 + th < e) off.push_back(make_int4(q, xx, ty0 + th, e - (ty0 + th)));
+          }
+          p.tiles[l].push_back(make_int4(q | (fl << 16), xx, ty0, th));
         }
     }
     p.nactive[l] = (int)p.tiles[l].size();
@@ -563,6 +577,7 @@ of_status of_session_set_mask(of_session* ss, const uint8_t* mask, void* stream)
   if (ss->maskbuf) hipFree(ss->maskbuf);
   ss->maskbuf = nullptr;
   ss->hflags.clear();
+  ss->hcut.clear();
   if (!mask) return OF_OK;
   e = prime_push_kernels(s, true);
   if (e != hipSuccess) return hip_fail("set_mask", e);
@@ -596,12 +611,24 @@ of_status of_session_set_mask(of_session* ss, const uint8_t* mask, void* stream)
     e = hipMemsetAsync(ss->flow, 0, 4 * align256((size_t)ss->H * ss->W * sizeof(float)), st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   std::vector<uint8_t> flags(ft);
+  std::vector<int2> cuts(ft, make_int2(0, 0));
   for (int l = 0; l < L && e == hipSuccess; ++l) {
     std::vector<uint8_t> hm((size_t)g.H[l] * g.W[l]);
     e = hipMemcpy(hm.data(), mb + ss->mask_off[l], hm.size(), hipMemcpyDeviceToHost);
     for (int b = 0; b < 3 && e == hipSuccess; ++b) {
-      const std::vector<uint8_t> f = tile_flags(hm.data(), g.H[l], g.W[l], TW, N * kPushBands[b]);
-      memcpy(flags.data() + ss->flag_off[b][l], f.data(), f.size());
+      const int TH = N * kPushBands[b];
+      const std::vector<uint8_t> f = tile_flags(hm.data(), g.H[l], g.W[l], TW, TH);
+      const size_t o = ss->flag_off[b][l];
+      memcpy(flags.data() + o, f.data(), f.size());
+      const int tx = (g.W[l] + TW - 1) / TW;
+      for (size_t i = 0; i < f.size(); ++i) {
+        if (f[i] != 1) continue;
+        const int yy = (int)(i / tx), xx = (int)(i % tx), y0 = yy * TH;
+        int ty0, th;
+        band_cut(hm.data(), g.W[l], xx * TW, std::min(g.W[l], xx * TW + TW), y0,
+                 std::min(g.H[l], y0 + TH), N, ty0, th);
+        cuts[o + i] = make_int2(ty0, th);
+      }
     }
   }
   if (e != hipSuccess) {
@@ -610,6 +637,7 @@ of_status of_session_set_mask(of_session* ss, const uint8_t* mask, void* stream)
   }
   ss->maskbuf = mb;
   ss->hflags = std::move(flags);
+  ss->hcut = std::move(cuts);
   return OF_OK;
 }
 

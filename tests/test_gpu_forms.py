@@ -251,3 +251,34 @@ def test_batch_masked_tiles_cut_to_unmasked_rows(gpu_lib, bands, variant, gaussi
         pu, pv = _plain(ofmi, p[0], p[1], m, gaussian, fp16=fp16)
         assert np.array_equal(us[i].cpu().numpy(), pu) and np.array_equal(vs[i].cpu().numpy(), pv), i
     b.close()
+
+
+def test_served_masked_tiles_cut_to_unmasked_bands(gpu_lib):
+    """A push of 4 Mi full-resolution pixels takes two-band tiles: a served stream's tiles with
+    masked pixels then run only their bands with unmasked rows (cut at the top, at the bottom),
+    the rows cut off zero-filled in the final phase.  Flows equal the plain path's with the
+    same mask, bitwise."""
+    ofmi = gpu_lib
+    from paper_1306_2461_amd.serve import GpuExecutor, Server
+    size = (1024, 2048)                   # two streams: 4 Mi pixels per push
+    streams = [[f for f, _, _ in synth.stream_frames(s, 2, size=size)] for s in range(2)]
+    M = np.ones(size, np.uint8)
+    M[:12] = 0                            # the first tile row loses its top band
+    M[99:108, :64] = 0                    # the tile row from row 90 its bottom band, first strip
+    M[500:, 1500:] = 0
+    ex = GpuExecutor(L, R, K, device=dev(), keep_on_device=False)
+    srv = Server(ex)
+    announce("served masked tiles cut to unmasked bands")
+    for s in range(2):
+        srv.submit(s, streams[s][0])
+    srv.drain()
+    ex.set_mask(srv.sessions[0], to_dev(M))
+    reqs = [srv.submit(s, streams[s][1]) for s in range(2)]
+    srv.drain()
+    ex.close_all()
+    for s in range(2):
+        pu, pv = _plain(ofmi, streams[s][0], streams[s][1], M if s == 0 else None)
+        r = reqs[s]
+        assert r.has_flow and np.array_equal(r.u, pu) and np.array_equal(r.v, pv), s
+        if s == 0:
+            assert np.all(r.u[M == 0] == 0) and np.all(r.v[M == 0] == 0)
